@@ -1,0 +1,209 @@
+/*
+ * lbm_cde.h - C ABI of the MI355X (gfx950) modified-MRT lattice Boltzmann
+ * solver for the anisotropic convection-diffusion equation
+ *
+ *     d_t phi + div(phi u) = div(D grad phi)                      (Eq. 1)
+ *
+ * following Huang & Wu, "A modified multiple-relaxation-time lattice
+ * Boltzmann model for convection-diffusion equation".  One time step is the
+ * fused collide-and-stream update of every node: moments m = M f (Eq. 11,
+ * Eq. 12 / A.2), relaxation m' = m - S (m - m_eq) with the modified,
+ * non-diagonal S of Eq. (31) / (A.5) and the equilibrium of Eq. (37) /
+ * (A.3)-(A.4), back-transform f' = M^-1 m' (Eq. 14) and streaming (Eq. 5).
+ * D enters through A, the flux block of S, as D = kappa (I - A/2) A^-1 with
+ * kappa = 1/3 (Eq. 36, A.6).
+ *
+ * Units are lattice units: dx = dt = 1, node x has integer coordinates
+ * 0..n-1 per axis.
+ *
+ * Memory and ownership
+ *   The caller owns every byte of device memory: a workspace sized by
+ *   lbm_cde_workspace_bytes(), the initial fields and every output buffer.
+ *   The library never allocates or frees device memory.  Handles are host
+ *   objects; one handle must not be used from two host threads at once.
+ *   Host tables passed in a descriptor are copied during lbm_cde_init().
+ *
+ * Streams
+ *   Every call enqueues its GPU work on the stream given to lbm_cde_init()
+ *   (a hipStream_t; NULL = the null stream) and returns without waiting,
+ *   except lbm_cde_reduce() and lbm_cde_read_samples(), which copy results
+ *   to host memory and wait for that stream.
+ *
+ * Errors
+ *   Every function returns LBM_CDE_OK (0) or a negative status.  The text of
+ *   the last error of a handle is returned by lbm_cde_last_error(h); errors
+ *   of lbm_cde_init()/lbm_cde_workspace_bytes(), where no handle exists yet,
+ *   are returned by lbm_cde_last_error(NULL) (per host thread).  A failed
+ *   call leaves the simulation state as it was.
+ */
+#ifndef LBM_CDE_H
+#define LBM_CDE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LBM_CDE_ABI_VERSION 1
+
+/* ---- status codes -------------------------------------------------------- */
+enum {
+  LBM_CDE_OK = 0,
+  LBM_CDE_EINVAL = -1,      /* bad argument: null pointer, size, enum, step count   */
+  LBM_CDE_ENOTSPD = -2,     /* D (or a node of D_field) is not symmetric positive definite */
+  LBM_CDE_EUNSTABLE = -3,   /* a rate outside (0, 2) or |u| >= c_s = 1/sqrt(3)        */
+  LBM_CDE_EHIP = -4,        /* HIP runtime error; the runtime's message is kept      */
+  LBM_CDE_ENONFINITE = -5,  /* a reduction met NaN or Inf in the state               */
+  LBM_CDE_ENOSPC = -6,      /* workspace smaller than lbm_cde_workspace_bytes()       */
+  LBM_CDE_EUNSUPPORTED = -7 /* a valid combination this build does not provide        */
+};
+
+/* ---- enumerations -------------------------------------------------------- */
+/* Lattices: D2Q9 of Eq. (2) with M of Eq. (12); D3Q15 of Eq. (A.1) with M of
+ * Eq. (A.2), velocities ordered as the columns of that M. */
+enum { LBM_CDE_D2Q9 = 0, LBM_CDE_D3Q15 = 1 };
+
+/* Storage precision of the populations (arithmetic is FP64 for FP64 and FP32
+ * otherwise):
+ *   FP64          f_i stored as double.
+ *   FP32_SHIFTED  g_i = f_i - w_i phi_ref stored as float, w_i the weights of
+ *                 the model's equilibrium at rest (D2Q9: 5/9, 1/18; D3Q15:
+ *                 8/15, 1/30).  The collision is done exactly on g.
+ *   FP16_SPLIT    per node phi (float) and the non-equilibrium part
+ *                 f_i - f_i^eq(phi, u) (half, times a power-of-two scale). */
+enum { LBM_CDE_FP64 = 0, LBM_CDE_FP32_SHIFTED = 1, LBM_CDE_FP16_SPLIT = 2 };
+
+/* Boundary of one axis (both faces).  Walls sit halfway between the first
+ * (last) node and its missing neighbour:
+ *   PERIODIC     wrap-around.
+ *   BOUNCE_BACK  a population whose source lies beyond the wall is the one
+ *                that left the same node with the opposite velocity.
+ *   SPECULAR     a mirror: only the velocity component normal to the wall is
+ *                reversed, the population moves on along the wall; the
+ *                halfway analog of the zero-flux plate rule f2 = f4,
+ *                f5 = f8, f6 = f7 of Sec. 3.2. */
+enum { LBM_CDE_PERIODIC = 0, LBM_CDE_BOUNCE_BACK = 1, LBM_CDE_SPECULAR = 2 };
+
+/* Velocity field u(x) (steady):
+ *   CONST      u_const[0..dim-1].
+ *   SEPARABLE  u_c(x,y,z) = amp_c * X_c[x] * Y_c[y] * Z_c[z] per component c,
+ *              from host tables (see u_tables).
+ *   FIELD      per node, device FP64 array [dim][nz][ny][nx]. */
+enum { LBM_CDE_U_CONST = 0, LBM_CDE_U_SEPARABLE = 1, LBM_CDE_U_FIELD = 2 };
+
+/* Rates s4, s6 (, s8) of the heat-flux moments, which the modified S
+ * couples into the flux rows (Eq. 31, A.5); D does not depend on them.
+ *   LAMBDA_MIN  all equal to the smallest eigenvalue of A (default; equals
+ *               1/tau for isotropic D).
+ *   PAPER       s4 = s_xx, s6 = s_yy (, s8 = s_zz) as in Sec. 3.1.
+ *   EXPLICIT    heat_rates[]. */
+enum { LBM_CDE_HEAT_LAMBDA_MIN = 0, LBM_CDE_HEAT_PAPER = 1, LBM_CDE_HEAT_EXPLICIT = 2 };
+
+/* Reductions (all FP64): */
+enum {
+  LBM_CDE_RED_MASS = 0,      /* out[0] = sum_x phi(x)                                   */
+  LBM_CDE_RED_XMOMENTS = 1,  /* out[0..2] = S0, S1, S2 of phibar(x) = sum over y, z of
+                                phi, S_k = sum_x d^k phibar(x), d the minimum image of
+                                x - x_ref in [-nx/2, nx/2) (Eq. 46-47)                  */
+  LBM_CDE_RED_NONFINITE = 2  /* out[0] = number of stored values that are NaN or Inf    */
+};
+
+/* ---- run description ----------------------------------------------------- */
+typedef struct lbm_cde_run_desc {
+  int32_t lattice;          /* LBM_CDE_D2Q9 | LBM_CDE_D3Q15                           */
+  int32_t precision;        /* LBM_CDE_FP64 | LBM_CDE_FP32_SHIFTED | LBM_CDE_FP16_SPLIT */
+  int64_t nx, ny, nz;       /* nodes per axis, >= 1; nz must be 1 for D2Q9            */
+  int32_t bc[3];            /* boundary kind per axis x, y, z                          */
+  double D[6];              /* constant D: xx, yy, zz, xy, xz, yz (2D uses xx, yy, xy) */
+  const double* D_field;    /* NULL, or device FP64 per-node D, components as D[]
+                               (2D: xx, yy, xy; 3D: all six), layout [comp][nz][ny][nx] */
+  int32_t u_kind;           /* LBM_CDE_U_*                                              */
+  double u_const[3];
+  const double* u_tables;   /* SEPARABLE: host, for c = 0..dim-1 in turn:
+                               amp_c, X_c[nx], Y_c[ny], Z_c[nz]                         */
+  const double* u_field;    /* FIELD: device FP64 [dim][nz][ny][nx]                     */
+  int32_t heat_rule;        /* LBM_CDE_HEAT_*                                           */
+  double heat_rates[3];     /* EXPLICIT: s4, s6, s8                                     */
+  double rates[15];         /* diagonal rates by moment index; 0 = default.  D2Q9 reads
+                               s1, s2 (default 1.1), s7, s8 (1.2); D3Q15 reads s1, s2
+                               (1.1), s9..s14 (1.2).  s0 never matters (m0 = m0eq).     */
+  double phi_ref;           /* background level of shifted / split storage              */
+  double fp16_scale;        /* FP16_SPLIT: power-of-two scale of f_neq; 0 = automatic   */
+  double xref0, xref_drift; /* sampled x-moments use x_ref(t) = xref0 + xref_drift * t  */
+  int64_t max_steps;        /* per-run step budget (< 0: unlimited); a run that has
+                               used it is left unchanged by further steps               */
+} lbm_cde_run_desc;
+
+typedef struct lbm_cde* lbm_cde_handle;
+
+/* Bytes of device workspace needed for nruns runs.  Returns EINVAL for an
+ * invalid description (same checks as lbm_cde_init without the GPU). */
+int lbm_cde_workspace_bytes(const lbm_cde_run_desc* runs, int32_t nruns, size_t* bytes);
+
+/* Set up nruns independent runs in the caller's workspace (device memory of
+ * ws_bytes bytes, 256-byte aligned) and initialise every population to the
+ * equilibrium of phi0 and u (collision leaves an equilibrium unchanged, so
+ * this is the post-collision state at t = 0).  phi0 is a host array of nruns
+ * device pointers, each to nx*ny*nz FP64 values (x fastest).  D and the
+ * rates are mapped to S as in Eq. (31)/(A.5), A = (D/kappa + I/2)^-1.
+ * Errors: EINVAL, ENOTSPD, EUNSTABLE, ENOSPC, EUNSUPPORTED, EHIP.  On error
+ * *out is NULL. */
+int lbm_cde_init(const lbm_cde_run_desc* runs, int32_t nruns, const double* const* phi0,
+                 void* workspace, size_t ws_bytes, void* hip_stream, lbm_cde_handle* out);
+
+/* Advance every run n >= 0 time steps (each stops at its max_steps).  Long
+ * advances are replayed from a captured HIP graph.  EINVAL for n < 0. */
+int lbm_cde_step(lbm_cde_handle h, int64_t n);
+
+/* Steps taken so far by run `run`. */
+int lbm_cde_steps_done(lbm_cde_handle h, int32_t run, int64_t* steps);
+
+/* phi(x) = sum_i f_i(x) (Eq. 8) of run `run`, as FP64 into the device buffer
+ * phi_out of nx*ny*nz values, whatever the storage precision. */
+int lbm_cde_moments(lbm_cde_handle h, int32_t run, double* phi_out);
+
+/* FP64 reduction `kind` (LBM_CDE_RED_*) of run `run` into host memory out
+ * (3 doubles).  x_ref is used by XMOMENTS only.  Waits for the stream.
+ * Returns ENONFINITE (with out filled) when MASS or XMOMENTS met NaN/Inf. */
+int lbm_cde_reduce(lbm_cde_handle h, int32_t run, int32_t kind, double x_ref, double* out);
+
+/* Advance n steps and, after every `every` steps, append the XMOMENTS
+ * (S0, S1, S2) of each run, taken about x_ref(t) of that run, to the device
+ * history buffer hist (FP64, [capacity][nruns][3]).  Sampling continues the
+ * history where the previous call stopped; EINVAL if it would overflow
+ * capacity.  n must be a multiple of every. */
+int lbm_cde_run_sampled(lbm_cde_handle h, int64_t n, int64_t every, double* hist, int64_t capacity);
+
+/* Number of history rows written so far by lbm_cde_run_sampled(). */
+int lbm_cde_samples_written(lbm_cde_handle h, int64_t* rows);
+
+/* The relaxation matrix S of run `run` (constant D only), row-major Q x Q,
+ * into host memory S_out (Q*Q doubles); Q = 9 or 15. */
+int lbm_cde_relaxation_matrix(lbm_cde_handle h, int32_t run, double* S_out);
+
+/* Autotuner: for every run, time `trials` launches of each compiled launch
+ * variant (tile shape, streaming stores, XCD block order) and keep the
+ * fastest.  Each timed launch reads the current state and overwrites only
+ * the other population buffer, so the simulation state is unchanged.
+ * Results are bitwise independent of the variant.  If the environment
+ * variable LBM_CDE_TUNE_CACHE names a file, results are looked up there
+ * (keyed by GPU architecture, lattice, precision, grid and boundaries) and
+ * new ones appended.  Waits for the stream.  EINVAL for trials < 1. */
+int lbm_cde_tune(lbm_cde_handle h, int32_t trials);
+
+/* The launch variant of run `run`: out[0..4] = block x, block y, rows per
+ * thread, streaming stores (0/1), XCD-contiguous block order (0/1). */
+int lbm_cde_get_variant(lbm_cde_handle h, int32_t run, int32_t* out);
+
+/* Release the handle (host memory only; the workspace stays the caller's). */
+int lbm_cde_destroy(lbm_cde_handle h);
+
+/* Text of the last error of h (NULL: of the last failed init on this thread). */
+const char* lbm_cde_last_error(lbm_cde_handle h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LBM_CDE_H */

@@ -1,0 +1,183 @@
+"""ctypes binding of ``liblbm_cde.so`` (argument marshalling only).
+
+Every function here forwards to the C entry point of the same name in
+``include/lbm_cde.h``; all computation happens in the HIP library.  Loading
+fails loudly when the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblbm_cde.so")
+
+# status codes
+LBM_CDE_OK = 0
+LBM_CDE_EINVAL = -1
+LBM_CDE_ENOTSPD = -2
+LBM_CDE_EUNSTABLE = -3
+LBM_CDE_EHIP = -4
+LBM_CDE_ENONFINITE = -5
+LBM_CDE_ENOSPC = -6
+LBM_CDE_EUNSUPPORTED = -7
+STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "ENOTSPD", -3: "EUNSTABLE", -4: "EHIP", -5: "ENONFINITE",
+                -6: "ENOSPC", -7: "EUNSUPPORTED"}
+
+LBM_CDE_D2Q9, LBM_CDE_D3Q15 = 0, 1
+LBM_CDE_FP64, LBM_CDE_FP32_SHIFTED, LBM_CDE_FP16_SPLIT = 0, 1, 2
+LBM_CDE_PERIODIC, LBM_CDE_BOUNCE_BACK, LBM_CDE_SPECULAR = 0, 1, 2
+LBM_CDE_U_CONST, LBM_CDE_U_SEPARABLE, LBM_CDE_U_FIELD = 0, 1, 2
+LBM_CDE_HEAT_LAMBDA_MIN, LBM_CDE_HEAT_PAPER, LBM_CDE_HEAT_EXPLICIT = 0, 1, 2
+LBM_CDE_RED_MASS, LBM_CDE_RED_XMOMENTS, LBM_CDE_RED_NONFINITE = 0, 1, 2
+
+
+class lbm_cde_run_desc(ctypes.Structure):
+    _fields_ = [
+        ("lattice", ctypes.c_int32),
+        ("precision", ctypes.c_int32),
+        ("nx", ctypes.c_int64),
+        ("ny", ctypes.c_int64),
+        ("nz", ctypes.c_int64),
+        ("bc", ctypes.c_int32 * 3),
+        ("D", ctypes.c_double * 6),
+        ("D_field", ctypes.c_void_p),
+        ("u_kind", ctypes.c_int32),
+        ("u_const", ctypes.c_double * 3),
+        ("u_tables", ctypes.c_void_p),
+        ("u_field", ctypes.c_void_p),
+        ("heat_rule", ctypes.c_int32),
+        ("heat_rates", ctypes.c_double * 3),
+        ("rates", ctypes.c_double * 15),
+        ("phi_ref", ctypes.c_double),
+        ("fp16_scale", ctypes.c_double),
+        ("xref0", ctypes.c_double),
+        ("xref_drift", ctypes.c_double),
+        ("max_steps", ctypes.c_int64),
+    ]
+
+
+class LbmCdeError(RuntimeError):
+    def __init__(self, code: int, where: str, msg: str):
+        self.code = code
+        super().__init__(f"{where}: {STATUS_NAMES.get(code, code)}: {msg}")
+
+
+_lib = None
+
+
+def load() -> ctypes.CDLL:
+    """Load the HIP library (built in-tree by build.py)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_1404_2363_amd/build.py "
+                           "(there is no CPU fallback)")
+    lib = ctypes.CDLL(LIB_PATH)
+    P, I32, I64, D = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    sig = {
+        "lbm_cde_workspace_bytes": [ctypes.POINTER(lbm_cde_run_desc), I32, ctypes.POINTER(ctypes.c_size_t)],
+        "lbm_cde_init": [ctypes.POINTER(lbm_cde_run_desc), I32, ctypes.POINTER(ctypes.c_void_p), P,
+                         ctypes.c_size_t, P, ctypes.POINTER(ctypes.c_void_p)],
+        "lbm_cde_step": [P, I64],
+        "lbm_cde_steps_done": [P, I32, ctypes.POINTER(I64)],
+        "lbm_cde_moments": [P, I32, P],
+        "lbm_cde_reduce": [P, I32, I32, D, ctypes.POINTER(D)],
+        "lbm_cde_run_sampled": [P, I64, I64, P, I64],
+        "lbm_cde_samples_written": [P, ctypes.POINTER(I64)],
+        "lbm_cde_relaxation_matrix": [P, I32, ctypes.POINTER(D)],
+        "lbm_cde_tune": [P, I32],
+        "lbm_cde_get_variant": [P, I32, ctypes.POINTER(I32)],
+        "lbm_cde_destroy": [P],
+        "lbm_cde_last_error": [P],
+    }
+    for name, args in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = ctypes.c_char_p if name == "lbm_cde_last_error" else ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _check(rc: int, where: str, handle=None) -> int:
+    if rc != LBM_CDE_OK:
+        msg = load().lbm_cde_last_error(handle)
+        raise LbmCdeError(rc, where, msg.decode() if msg else "")
+    return rc
+
+
+# ---- same-name wrappers ----------------------------------------------------
+
+def lbm_cde_workspace_bytes(descs) -> int:
+    arr = (lbm_cde_run_desc * len(descs))(*descs)
+    out = ctypes.c_size_t(0)
+    _check(load().lbm_cde_workspace_bytes(arr, len(descs), ctypes.byref(out)), "lbm_cde_workspace_bytes")
+    return int(out.value)
+
+
+def lbm_cde_init(descs, phi0_ptrs, workspace_ptr: int, ws_bytes: int, stream: int) -> int:
+    arr = (lbm_cde_run_desc * len(descs))(*descs)
+    ptrs = (ctypes.c_void_p * len(phi0_ptrs))(*phi0_ptrs)
+    h = ctypes.c_void_p(None)
+    _check(load().lbm_cde_init(arr, len(descs), ptrs, ctypes.c_void_p(workspace_ptr), ws_bytes,
+                               ctypes.c_void_p(stream), ctypes.byref(h)), "lbm_cde_init")
+    return h.value
+
+
+def lbm_cde_step(h: int, n: int) -> None:
+    _check(load().lbm_cde_step(h, n), "lbm_cde_step", h)
+
+
+def lbm_cde_steps_done(h: int, run: int) -> int:
+    out = ctypes.c_int64(0)
+    _check(load().lbm_cde_steps_done(h, run, ctypes.byref(out)), "lbm_cde_steps_done", h)
+    return int(out.value)
+
+
+def lbm_cde_moments(h: int, run: int, phi_ptr: int) -> None:
+    _check(load().lbm_cde_moments(h, run, ctypes.c_void_p(phi_ptr)), "lbm_cde_moments", h)
+
+
+def lbm_cde_reduce(h: int, run: int, kind: int, x_ref: float = 0.0, allow_nonfinite: bool = False):
+    out = (ctypes.c_double * 3)()
+    rc = load().lbm_cde_reduce(h, run, kind, float(x_ref), out)
+    if not (allow_nonfinite and rc == LBM_CDE_ENONFINITE):
+        _check(rc, "lbm_cde_reduce", h)
+    return [out[0], out[1], out[2]], rc
+
+
+def lbm_cde_run_sampled(h: int, n: int, every: int, hist_ptr: int, capacity: int) -> None:
+    _check(load().lbm_cde_run_sampled(h, n, every, ctypes.c_void_p(hist_ptr), capacity), "lbm_cde_run_sampled", h)
+
+
+def lbm_cde_samples_written(h: int) -> int:
+    out = ctypes.c_int64(0)
+    _check(load().lbm_cde_samples_written(h, ctypes.byref(out)), "lbm_cde_samples_written", h)
+    return int(out.value)
+
+
+def lbm_cde_relaxation_matrix(h: int, run: int, Q: int):
+    out = (ctypes.c_double * (Q * Q))()
+    _check(load().lbm_cde_relaxation_matrix(h, run, out), "lbm_cde_relaxation_matrix", h)
+    return [out[i] for i in range(Q * Q)]
+
+
+def lbm_cde_tune(h: int, trials: int) -> None:
+    _check(load().lbm_cde_tune(h, trials), "lbm_cde_tune", h)
+
+
+def lbm_cde_get_variant(h: int, run: int):
+    out = (ctypes.c_int32 * 5)()
+    _check(load().lbm_cde_get_variant(h, run, out), "lbm_cde_get_variant", h)
+    return {"block": (out[0], out[1]), "rows_per_thread": out[2], "nt_stores": bool(out[3]),
+            "xcd_remap": bool(out[4])}
+
+
+def lbm_cde_destroy(h: int) -> None:
+    _check(load().lbm_cde_destroy(h), "lbm_cde_destroy")
+
+
+def lbm_cde_last_error(h=None) -> str:
+    msg = load().lbm_cde_last_error(h)
+    return msg.decode() if msg else ""

@@ -1,0 +1,169 @@
+// Initialisation, readout and FP64 reduction kernels (all lattices).
+#pragma once
+
+#include "common.hpp"
+#include "d2q9.hpp"
+#include "d3q15.hpp"
+
+namespace lbm {
+
+constexpr int RED_BLOCKS = 1024;
+constexpr int RED_THREADS = 256;
+
+// Per-node FP64 velocity for initialisation and readout.
+template <typename R>
+LBM_FORCEINLINE void velocity_at(const RunArgs& a, int dim, int64_t x, int64_t y, int64_t z, double* u) {
+  const int64_t N = a.nx * a.ny * a.nz;
+  const int64_t node = (z * a.ny + y) * a.nx + x;
+  for (int c = 0; c < dim; ++c) {
+    if (a.u_kind == U_CONST) {
+      u[c] = a.u_const[c];
+    } else if (a.u_kind == U_SEPARABLE) {
+      const R* t = (const R*)a.u_tab + c * (1 + a.nx + a.ny + a.nz);
+      u[c] = (double)(((t[0] * t[1 + x]) * t[1 + a.nx + y]) * t[1 + a.nx + a.ny + z]);
+    } else {
+      u[c] = (double)((const R*)a.u_field)[c * N + node];
+    }
+  }
+}
+
+// Populations of the equilibrium of phi0 (the state at t = 0).
+template <typename R>
+__global__ __launch_bounds__(256) void k_init_d2q9(const RunArgs a, const double* __restrict__ phi0) {
+  const int64_t N = a.nx * a.ny;
+  const int64_t node = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (node >= N) return;
+  const int64_t x = node % a.nx, y = node / a.nx;
+  double u[3];
+  velocity_at<R>(a, 2, x, y, 0, u);
+  double f[9];
+  equilibrium_d2q9(f, phi0[node], u[0], u[1], a.phi_ref);
+  R* dst = (R*)a.dst;
+  for (int i = 0; i < 9; ++i) dst[i * a.plane + node] = (R)f[i];
+}
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_init_d3q15(const RunArgs a, const double* __restrict__ phi0) {
+  const int64_t N = a.nx * a.ny * a.nz;
+  const int64_t node = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (node >= N) return;
+  const int64_t x = node % a.nx, y = (node / a.nx) % a.ny, z = node / (a.nx * a.ny);
+  double u[3];
+  velocity_at<R>(a, 3, x, y, z, u);
+  double f[15];
+  equilibrium_d3q15(f, phi0[node], u[0], u[1], u[2], a.phi_ref);
+  R* dst = (R*)a.dst;
+  for (int i = 0; i < 15; ++i) dst[i * a.plane + node] = (R)f[i];
+}
+
+// phi = sum_i f_i (+ phi_ref for shifted storage), FP64.
+template <typename R>
+__global__ __launch_bounds__(256) void k_moments(const RunArgs a, int Q, double* __restrict__ phi) {
+  const int64_t N = a.nx * a.ny * a.nz;
+  const int64_t node = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (node >= N) return;
+  const R* src = (const R*)a.src;
+  double s = 0.0;
+  for (int i = 0; i < Q; ++i) s += (double)src[i * a.plane + node];
+  phi[node] = s + a.phi_ref;
+}
+
+// Deterministic two-pass FP64 reduction.  Pass 1: each of RED_BLOCKS blocks
+// walks a fixed grid-stride set of nodes and tree-reduces 4 sums in LDS.
+// Pass 2: one block adds the partials in a fixed tree.
+template <typename R>
+__global__ __launch_bounds__(RED_THREADS) void k_reduce_partial(const RunArgs a, int Q, int kind, double x_ref,
+                                                               double* __restrict__ partial) {
+  __shared__ double sh[4][RED_THREADS];
+  const int64_t N = a.nx * a.ny * a.nz;
+  const R* src = (const R*)a.src;
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, bad = 0.0;
+  const double nxd = (double)a.nx;
+  for (int64_t node = (int64_t)blockIdx.x * RED_THREADS + threadIdx.x; node < N;
+       node += (int64_t)gridDim.x * RED_THREADS) {
+    double phi = 0.0;
+    int nonfinite = 0;
+    for (int i = 0; i < Q; ++i) {
+      const double v = (double)src[i * a.plane + node];
+      nonfinite += !isfinite(v);
+      phi += v;
+    }
+    phi += a.phi_ref;
+    bad += (double)nonfinite;
+    if (kind == LBM_CDE_RED_XMOMENTS) {
+      double d = (double)(node % a.nx) - x_ref;
+      d -= nxd * floor(d / nxd + 0.5);
+      s0 += phi;
+      s1 += d * phi;
+      s2 += d * d * phi;
+    } else {
+      s0 += phi;
+    }
+  }
+  sh[0][threadIdx.x] = s0;
+  sh[1][threadIdx.x] = s1;
+  sh[2][threadIdx.x] = s2;
+  sh[3][threadIdx.x] = bad;
+  __syncthreads();
+  for (int w = RED_THREADS / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w)
+      for (int k = 0; k < 4; ++k) sh[k][threadIdx.x] += sh[k][threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x < 4) partial[blockIdx.x * 4 + threadIdx.x] = sh[threadIdx.x][0];
+}
+
+__global__ __launch_bounds__(RED_THREADS) void k_reduce_final(const double* __restrict__ partial, int nblocks,
+                                                             double* __restrict__ out) {
+  __shared__ double sh[4][RED_THREADS];
+  for (int k = 0; k < 4; ++k) {
+    double s = 0.0;
+    for (int b = threadIdx.x; b < nblocks; b += RED_THREADS) s += partial[b * 4 + k];
+    sh[k][threadIdx.x] = s;
+  }
+  __syncthreads();
+  for (int w = RED_THREADS / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w)
+      for (int k = 0; k < 4; ++k) sh[k][threadIdx.x] += sh[k][threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x < 4) out[threadIdx.x] = sh[threadIdx.x][0];
+}
+
+// Copy of a device FP64 array into storage precision R.
+template <typename R>
+__global__ __launch_bounds__(256) void k_convert(const double* __restrict__ in, R* __restrict__ out, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = (R)in[i];
+}
+
+// Per-node relaxation parameters of a D field (2D): A = (D/kappa + I/2)^-1 and
+// the heat-flux rates by rule.  Counts nodes whose D is not SPD.
+template <typename R>
+__global__ __launch_bounds__(256) void k_node_params_2d(const double* __restrict__ Dfield, int64_t N, double kappa,
+                                                        int rule, double h4, double h6, R* __restrict__ par,
+                                                        unsigned long long* __restrict__ nonspd) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  const double dxx = Dfield[i], dyy = Dfield[N + i], dxy = Dfield[2 * N + i];
+  if (!(dxx > 0.0) || !(dxx * dyy - dxy * dxy > 0.0)) atomicAdd(nonspd, 1ull);
+  // B = D/kappa + I/2, A = B^-1
+  const double bxx = dxx / kappa + 0.5, byy = dyy / kappa + 0.5, bxy = dxy / kappa;
+  const double det = bxx * byy - bxy * bxy;
+  const double axx = byy / det, ayy = bxx / det, axy = -bxy / det;
+  double s4 = h4, s6 = h6;
+  if (rule == LBM_CDE_HEAT_LAMBDA_MIN) {
+    const double m = 0.5 * (axx + ayy), d = 0.5 * (axx - ayy);
+    s4 = s6 = m - sqrt(d * d + axy * axy);
+  } else if (rule == LBM_CDE_HEAT_PAPER) {
+    s4 = axx;
+    s6 = ayy;
+  }
+  par[i] = (R)axx;
+  par[N + i] = (R)axy;
+  par[2 * N + i] = (R)ayy;
+  par[3 * N + i] = (R)s4;
+  par[4 * N + i] = (R)s6;
+}
+
+}  // namespace lbm

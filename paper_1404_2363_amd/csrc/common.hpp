@@ -1,0 +1,66 @@
+// Shared device-side definitions of the gfx950 lattice Boltzmann kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/lbm_cde.h"
+
+#ifndef LBM_FORCEINLINE
+#define LBM_FORCEINLINE __device__ __forceinline__
+#endif
+
+namespace lbm {
+
+// Velocity description in the precision R of the arithmetic.
+enum UKind : int32_t { U_CONST = 0, U_SEPARABLE = 1, U_FIELD = 2 };
+
+// Everything one kernel launch needs about one run.  Passed by value as a
+// kernel argument (and stored in device memory for batched launches).
+struct RunArgs {
+  const void* src;          // populations read this step  (Q planes)
+  void* dst;                // populations written          (Q planes)
+  const void* src_phi;      // FP16 split: phi plane read
+  void* dst_phi;            // FP16 split: phi plane written
+  int64_t nx, ny, nz;
+  int64_t plane;            // elements between two population planes
+  int32_t bc[3];
+  int32_t u_kind;
+  double u_const[3];
+  const void* u_tab;        // SEPARABLE: per component: amp, X[nx], Y[ny], Z[nz] (type R)
+  const void* u_field;      // FIELD: [dim][nodes] (type R)
+  const void* node_par;     // per-node relaxation parameters (type R) or null
+  double phi_ref;
+  double fp16_scale, fp16_inv_scale;
+  // relaxation (constant D): diagonal rates and the flux block
+  double s[15];             // s[k] by moment index (flux-row entries unused)
+  double A[3][3];           // flux block s_ab
+  double heat[3];           // s4, s6, s8
+  int32_t xcd_remap;        // map block ids so each XCD works on a contiguous band
+  int32_t active;           // 0: run has used its step budget
+};
+
+// Block id remapping for the 8 XCDs of MI355X: consecutive hardware block ids
+// go round-robin to the XCDs, so give XCD k the k-th contiguous range of
+// logical tiles; neighbouring tiles then share that XCD's L2.
+LBM_FORCEINLINE int64_t xcd_tile(int64_t b, int64_t nb) {
+  const int64_t nx = 8;
+  const int64_t xcd = b % nx, local = b / nx;
+  const int64_t per = nb / nx, rem = nb % nx;
+  return xcd * per + (xcd < rem ? xcd : rem) + local;
+}
+
+template <typename R>
+LBM_FORCEINLINE R load_ro(const R* p) { return __builtin_nontemporal_load(p); }
+
+template <typename R, bool NT>
+LBM_FORCEINLINE void store_pop(R* p, R v) {
+  if constexpr (NT) __builtin_nontemporal_store(v, p);
+  else *p = v;
+}
+
+// Periodic neighbour index.
+LBM_FORCEINLINE int64_t wrap_m(int64_t i, int64_t n) { return i == 0 ? n - 1 : i - 1; }
+LBM_FORCEINLINE int64_t wrap_p(int64_t i, int64_t n) { return i == n - 1 ? 0 : i + 1; }
+
+}  // namespace lbm

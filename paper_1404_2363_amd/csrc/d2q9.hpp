@@ -1,0 +1,263 @@
+// D2Q9 modified-MRT collide-and-stream for gfx950.
+//
+// Velocities (Eq. 2): 0:(0,0) 1:(1,0) 2:(0,1) 3:(-1,0) 4:(0,-1)
+//                     5:(1,1) 6:(-1,1) 7:(-1,-1) 8:(1,-1).
+// Moments (Eq. 12): m0 = rho, m1 = e, m2 = eps, m3 = j_x, m4 = q_x, m5 = j_y,
+// m6 = q_y, m7 = p_xx, m8 = p_xy.  The rows of M are orthogonal with squared
+// norms (9, 36, 36, 6, 12, 6, 12, 4, 4), so M^-1 = M^T diag(1/norm^2) and the
+// back-transform is the same integer add/sub tree as the forward one.
+//
+// Per node the step is linear in f: with n = m - m_eq (Eq. 37:
+// m_eq = phi (1, -2, 2, ux, -ux, uy, -uy, 0, 0)), the modified S of Eq. (31)
+// gives the increments
+//   d_k = s_k n_k                                    (k = 1, 2, 4, 6, 7, 8)
+//   d_3 = s_xx n3 + (s_xx/2 - 1) s4 n4 + s_xy n5 + (s_xy/2) s6 n6
+//   d_5 = s_yx n3 + (s_yx/2) s4 n4 + s_yy n5 + (s_yy/2 - 1) s6 n6
+// (d_0 = 0 because m0 = m0_eq), and f' = f - M^-1 d.
+//
+// Shifted storage keeps g = f - w phi_ref with w = f_eq(1, 0) = (5/9, 1/18 x 8).
+// Because M w = (1, -2, 2, 0, ...) equals m_eq(1, 0), the background cancels in
+// n except in the velocity moments: n1 = m1(g) + 2 phi_g, n2 = m2(g) - 2 phi_g,
+// n3 = m3(g) - phi ux, ... with phi = phi_g + phi_ref; and g' = g - M^-1 d.
+// Streaming and both wall rules map populations to populations of equal
+// weight, so the uniform shift is preserved.
+#pragma once
+
+#include "common.hpp"
+
+namespace lbm {
+
+template <typename R>
+struct Rel2 {
+  R s1, s2, s7, s8, s4, s6;
+  R axx, axy, ayy;
+  R c34, c36, c54, c56;  // coupling coefficients of Eq. (31)
+};
+
+template <typename R>
+LBM_FORCEINLINE Rel2<R> make_rel2(R axx, R axy, R ayy, R s4, R s6, const RunArgs& a) {
+  Rel2<R> r;
+  r.s1 = (R)a.s[1];
+  r.s2 = (R)a.s[2];
+  r.s7 = (R)a.s[7];
+  r.s8 = (R)a.s[8];
+  r.s4 = s4;
+  r.s6 = s6;
+  r.axx = axx;
+  r.axy = axy;
+  r.ayy = ayy;
+  r.c34 = (axx * (R)0.5 - (R)1) * s4;
+  r.c36 = (axy * (R)0.5) * s6;
+  r.c54 = (axy * (R)0.5) * s4;
+  r.c56 = (ayy * (R)0.5 - (R)1) * s6;
+  return r;
+}
+
+template <typename R>
+LBM_FORCEINLINE Rel2<R> const_rel2(const RunArgs& a) {
+  return make_rel2<R>((R)a.A[0][0], (R)a.A[0][1], (R)a.A[1][1], (R)a.heat[0], (R)a.heat[1], a);
+}
+
+// Per-node relaxation parameters (D field): axx, axy, ayy, s4, s6 planes.
+template <typename R>
+LBM_FORCEINLINE Rel2<R> node_rel2(const RunArgs& a, int64_t node) {
+  const R* p = (const R*)a.node_par;
+  const int64_t N = a.nx * a.ny;
+  return make_rel2<R>(p[node], p[N + node], p[2 * N + node], p[3 * N + node], p[4 * N + node], a);
+}
+
+// The collision of one node, in place.  phi_ref = 0 for unshifted storage.
+template <typename R>
+LBM_FORCEINLINE void collide_d2q9(R (&f)[9], R ux, R uy, R phi_ref, const Rel2<R>& r) {
+  const R sa = f[1] + f[2] + f[3] + f[4];
+  const R sd = f[5] + f[6] + f[7] + f[8];
+  const R phig = f[0] + sa + sd;
+  const R phi = phig + phi_ref;
+  // moments of the stored populations
+  const R m1 = (R)2 * sd - sa - (R)4 * f[0];
+  const R m2 = (R)4 * f[0] - (R)2 * sa + sd;
+  const R dx13 = f[1] - f[3];
+  const R dx58 = f[5] - f[6] - f[7] + f[8];  // diagonal x-flux
+  const R dy24 = f[2] - f[4];
+  const R dy56 = f[5] + f[6] - f[7] - f[8];  // diagonal y-flux
+  const R m3 = dx13 + dx58;
+  const R m4 = dx58 - (R)2 * dx13;
+  const R m5 = dy24 + dy56;
+  const R m6 = dy56 - (R)2 * dy24;
+  const R m7 = f[1] - f[2] + f[3] - f[4];
+  const R m8 = f[5] - f[6] + f[7] - f[8];
+  // non-equilibrium parts
+  const R jx = phi * ux, jy = phi * uy;
+  const R n1 = m1 + (R)2 * phig;
+  const R n2 = m2 - (R)2 * phig;
+  const R n3 = m3 - jx;
+  const R n4 = m4 + jx;
+  const R n5 = m5 - jy;
+  const R n6 = m6 + jy;
+  // relaxation increments, pre-divided by the squared row norms
+  const R a1 = r.s1 * n1 * (R)(1.0 / 36.0);
+  const R a2 = r.s2 * n2 * (R)(1.0 / 36.0);
+  const R a3 = (r.axx * n3 + r.c34 * n4 + r.axy * n5 + r.c36 * n6) * (R)(1.0 / 6.0);
+  const R a4 = r.s4 * n4 * (R)(1.0 / 12.0);
+  const R a5 = (r.axy * n3 + r.c54 * n4 + r.ayy * n5 + r.c56 * n6) * (R)(1.0 / 6.0);
+  const R a6 = r.s6 * n6 * (R)(1.0 / 12.0);
+  const R a7 = r.s7 * m7 * (R)0.25;
+  const R a8 = r.s8 * m8 * (R)0.25;
+  // f' = f - M^T a
+  const R ax = -a1 - (R)2 * a2;          // common to the axis populations
+  const R dg = (R)2 * a1 + a2;           // common to the diagonals
+  const R q3 = a3 - (R)2 * a4, q5 = a5 - (R)2 * a6;
+  const R p3 = a3 + a4, p5 = a5 + a6;
+  f[0] -= (R)4 * (a2 - a1);
+  f[1] -= ax + q3 + a7;
+  f[2] -= ax + q5 - a7;
+  f[3] -= ax - q3 + a7;
+  f[4] -= ax - q5 - a7;
+  f[5] -= dg + p3 + p5 + a8;
+  f[6] -= dg - p3 + p5 - a8;
+  f[7] -= dg - p3 - p5 + a8;
+  f[8] -= dg + p3 - p5 - a8;
+}
+
+// f_eq(phi, u) - w phi_ref, in double (initialisation).
+LBM_FORCEINLINE void equilibrium_d2q9(double (&f)[9], double phi, double ux, double uy, double phi_ref) {
+  // M^-1 m_eq with m_eq = phi (1, -2, 2, ux, -ux, uy, -uy, 0, 0)
+  const double a0 = phi / 9.0, a1 = -2.0 * phi / 36.0, a2 = 2.0 * phi / 36.0;
+  const double a3 = phi * ux / 6.0, a4 = -phi * ux / 12.0;
+  const double a5 = phi * uy / 6.0, a6 = -phi * uy / 12.0;
+  const double ax = a0 - a1 - 2.0 * a2, dg = a0 + 2.0 * a1 + a2;
+  const double q3 = a3 - 2.0 * a4, q5 = a5 - 2.0 * a6, p3 = a3 + a4, p5 = a5 + a6;
+  f[0] = a0 - 4.0 * a1 + 4.0 * a2 - phi_ref * (5.0 / 9.0);
+  f[1] = ax + q3 - phi_ref / 18.0;
+  f[2] = ax + q5 - phi_ref / 18.0;
+  f[3] = ax - q3 - phi_ref / 18.0;
+  f[4] = ax - q5 - phi_ref / 18.0;
+  f[5] = dg + p3 + p5 - phi_ref / 18.0;
+  f[6] = dg - p3 + p5 - phi_ref / 18.0;
+  f[7] = dg - p3 - p5 - phi_ref / 18.0;
+  f[8] = dg + p3 - p5 - phi_ref / 18.0;
+}
+
+// Velocity at node (x, y).
+template <typename R>
+LBM_FORCEINLINE void velocity2(const RunArgs& a, int64_t x, int64_t y, R& ux, R& uy) {
+  if (a.u_kind == U_CONST) {
+    ux = (R)a.u_const[0];
+    uy = (R)a.u_const[1];
+  } else if (a.u_kind == U_SEPARABLE) {
+    const R* t = (const R*)a.u_tab;
+    const int64_t stride = 1 + a.nx + a.ny + a.nz;
+    const R* t1 = t + stride;
+    ux = ((t[0] * t[1 + x]) * t[1 + a.nx + y]) * t[1 + a.nx + a.ny];
+    uy = ((t1[0] * t1[1 + x]) * t1[1 + a.nx + y]) * t1[1 + a.nx + a.ny];
+  } else {
+    const R* u = (const R*)a.u_field;
+    const int64_t N = a.nx * a.ny;
+    ux = u[y * a.nx + x];
+    uy = u[N + y * a.nx + x];
+  }
+}
+
+// Population index of velocity (vx, vy).
+LBM_FORCEINLINE int pop_of_d2q9(int vx, int vy) {
+  // rows vx = -1, 0, 1; columns vy = -1, 0, 1
+  const int t = (vx + 1) * 3 + (vy + 1);
+  // (-1,-1)=7 (-1,0)=3 (-1,1)=6 (0,-1)=4 (0,0)=0 (0,1)=2 (1,-1)=8 (1,0)=1 (1,1)=5
+  return (int)((0x518204637ull >> (4 * t)) & 0xF);
+}
+
+// Index (population plane * plane + node) that the pull of population (EX, EY)
+// reads at node (x, y), honouring each axis' boundary kind.  Periodic axes
+// wrap; if the source lies beyond a wall, bounce-back takes the opposite
+// population of the same node and the mirror takes the population with the
+// normal component reversed from the neighbour along the wall.
+template <int EX, int EY>
+LBM_FORCEINLINE int64_t pull_index_d2q9(const RunArgs& a, int64_t x, int64_t y) {
+  int64_t sx = x - EX, sy = y - EY;
+  bool cx = false, cy = false;
+  if (EX != 0) {
+    const bool out = sx < 0 || sx >= a.nx;
+    if (a.bc[0] == LBM_CDE_PERIODIC) sx = sx < 0 ? sx + a.nx : (sx >= a.nx ? sx - a.nx : sx);
+    else cx = out;
+  }
+  if (EY != 0) {
+    const bool out = sy < 0 || sy >= a.ny;
+    if (a.bc[1] == LBM_CDE_PERIODIC) sy = sy < 0 ? sy + a.ny : (sy >= a.ny ? sy - a.ny : sy);
+    else cy = out;
+  }
+  const bool bounce = (cx && a.bc[0] == LBM_CDE_BOUNCE_BACK) || (cy && a.bc[1] == LBM_CDE_BOUNCE_BACK);
+  int vx = EX, vy = EY;
+  if (bounce) {
+    vx = -EX;
+    vy = -EY;
+    sx = x;
+    sy = y;
+  } else {
+    if (cx) { vx = -EX; sx = x; }
+    if (cy) { vy = -EY; sy = y; }
+  }
+  return (int64_t)pop_of_d2q9(vx, vy) * a.plane + sy * a.nx + sx;
+}
+
+// One pull step over a tile of BX x (BY*NY) nodes per block.  Thread (tx, ty)
+// owns column x and rows ty, ty + BY, ... of the tile.  All loads of a thread
+// are issued before its collisions.
+template <typename R, int BX, int BY, int NY, bool WALLS, bool NT>
+__global__ __launch_bounds__(BX * BY) void k_step_d2q9(const RunArgs a) {
+  const int64_t ntx = (a.nx + BX - 1) / BX;
+  int64_t b = blockIdx.x;
+  if (a.xcd_remap) b = xcd_tile(b, gridDim.x);
+  const int64_t tile_x = b % ntx, tile_y = b / ntx;
+  const int64_t x = tile_x * BX + threadIdx.x;
+  if (x >= a.nx) return;
+  const R* __restrict__ src = (const R*)a.src;
+  R* __restrict__ dst = (R*)a.dst;
+  const int64_t P = a.plane;
+  const int64_t y0 = tile_y * (BY * NY) + threadIdx.y;
+
+  R f[NY][9];
+#pragma unroll
+  for (int k = 0; k < NY; ++k) {
+    const int64_t y = y0 + (int64_t)k * BY;
+    if (y >= a.ny) continue;
+    if constexpr (!WALLS) {
+      const int64_t xm = wrap_m(x, a.nx), xp = wrap_p(x, a.nx);
+      const int64_t r0 = y * a.nx, rm = wrap_m(y, a.ny) * a.nx, rp = wrap_p(y, a.ny) * a.nx;
+      f[k][0] = src[r0 + x];
+      f[k][1] = src[1 * P + r0 + xm];
+      f[k][2] = src[2 * P + rm + x];
+      f[k][3] = src[3 * P + r0 + xp];
+      f[k][4] = src[4 * P + rp + x];
+      f[k][5] = src[5 * P + rm + xm];
+      f[k][6] = src[6 * P + rm + xp];
+      f[k][7] = src[7 * P + rp + xp];
+      f[k][8] = src[8 * P + rp + xm];
+    } else {
+      f[k][0] = src[y * a.nx + x];
+      f[k][1] = src[pull_index_d2q9<1, 0>(a, x, y)];
+      f[k][2] = src[pull_index_d2q9<0, 1>(a, x, y)];
+      f[k][3] = src[pull_index_d2q9<-1, 0>(a, x, y)];
+      f[k][4] = src[pull_index_d2q9<0, -1>(a, x, y)];
+      f[k][5] = src[pull_index_d2q9<1, 1>(a, x, y)];
+      f[k][6] = src[pull_index_d2q9<-1, 1>(a, x, y)];
+      f[k][7] = src[pull_index_d2q9<-1, -1>(a, x, y)];
+      f[k][8] = src[pull_index_d2q9<1, -1>(a, x, y)];
+    }
+  }
+  const R phi_ref = (R)a.phi_ref;
+  const Rel2<R> rc = const_rel2<R>(a);
+#pragma unroll
+  for (int k = 0; k < NY; ++k) {
+    const int64_t y = y0 + (int64_t)k * BY;
+    if (y >= a.ny) continue;
+    const int64_t node = y * a.nx + x;
+    R ux, uy;
+    velocity2<R>(a, x, y, ux, uy);
+    if (a.node_par) collide_d2q9<R>(f[k], ux, uy, phi_ref, node_rel2<R>(a, node));
+    else collide_d2q9<R>(f[k], ux, uy, phi_ref, rc);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) store_pop<R, NT>(dst + i * P + node, f[k][i]);
+  }
+}
+
+}  // namespace lbm

@@ -1,0 +1,907 @@
+// Host runtime and C ABI of the gfx950 modified-MRT lattice Boltzmann solver.
+//
+// The library owns no device memory: every buffer lives in the caller's
+// workspace, laid out per run as
+//   [populations A][populations B][velocity tables or field][node params]
+//   [reduction partials][reduction result][flags]
+// each piece 256-byte aligned.  Populations are structure-of-arrays: plane i
+// holds f_i of every node, x fastest, planes `plane` elements apart.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/lbm_cde.h"
+#include "aux_kernels.hpp"
+#include "common.hpp"
+#include "d2q9.hpp"
+#include "d3q15.hpp"
+
+using namespace lbm;
+
+namespace {
+
+thread_local std::string g_init_error;
+
+constexpr size_t kAlign = 256;
+constexpr int kGraphSteps = 32;   // steps per captured graph (an even number)
+
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+// Extra bytes between population planes (a multiple of 256).
+size_t plane_skew() {
+  static const size_t skew = [] {
+    if (const char* t = std::getenv("LBM_CDE_PAD")) return align_up((size_t)std::strtoull(t, nullptr, 10));
+    return (size_t)16640;  // 16 KiB + 256 B
+  }();
+  return skew;
+}
+
+// A launch variant of the step kernel: tile shape, store kind, block order.
+struct Variant {
+  int bx, by, ny;
+  bool nt;    // non-temporal (streaming) stores
+  bool xcd;   // XCD-contiguous block remap
+};
+
+struct Run {
+  lbm_cde_run_desc d;
+  int Q = 9, dim = 2;
+  int64_t nodes = 0;
+  int64_t plane = 0;            // elements between population planes
+  size_t elem = 8;              // bytes per stored population value
+  bool dbl = true;              // arithmetic and storage in double
+  // workspace pieces
+  char* pop[2] = {nullptr, nullptr};
+  char* utab = nullptr;
+  char* ufield = nullptr;
+  char* node_par = nullptr;
+  double* red_partial = nullptr;
+  double* red_out = nullptr;
+  unsigned long long* flags = nullptr;
+  // derived constants
+  double kappa = 1.0 / 3.0;
+  double A[3][3] = {{0}};
+  double heat[3] = {0, 0, 0};
+  double s[15] = {0};
+  int64_t steps = 0;
+  bool walls = false;
+  Variant var{256, 1, 1, true, false};
+};
+
+}  // namespace
+
+struct lbm_cde {
+  std::vector<Run> runs;
+  hipStream_t stream = nullptr;
+  hipStream_t capture = nullptr;
+  hipGraphExec_t graph[2] = {nullptr, nullptr};
+  std::string err;
+  int64_t sample_rows = 0;
+  bool env_variant = false;   // LBM_CDE_TILE / _NT / _XCD override every run
+  Variant env{256, 1, 1, true, false};
+  Variant env3{128, 1, 1, true, false};
+};
+
+namespace {
+
+int fail_init(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_init_error = buf;
+  return code;
+}
+
+int fail(lbm_cde* h, int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  if (h) h->err = buf;
+  else g_init_error = buf;
+  return code;
+}
+
+#define HIP_TRY(h, expr)                                                                   \
+  do {                                                                                     \
+    hipError_t e_ = (expr);                                                                \
+    if (e_ != hipSuccess)                                                                  \
+      return fail((h), LBM_CDE_EHIP, "%s: %s (%s:%d)", #expr, hipGetErrorString(e_), __FILE__, __LINE__); \
+  } while (0)
+
+// ---- parameter derivation (Eq. 36, A.6) -----------------------------------
+
+// Prefactor kappa of D = kappa (I - A/2) A^-1 for the model's alpha1, alpha2.
+double kappa_of(int lattice) {
+  if (lattice == LBM_CDE_D2Q9) {
+    const double a1 = -8.0, a2 = 8.0;             // Eq. (37)
+    return 2.0 / 3.0 + a1 / 8.0 + a2 / 12.0;      // Eq. (36)
+  }
+  const double a1 = -6.0 / 5.0, a2 = 192.0;        // 3D analog of the 2D choice
+  return 2.0 / 3.0 + 55.0 * a1 / 54.0 + a2 / 216.0; // Eq. (A.6)
+}
+
+void sym_from_components(int dim, const double* c, double M[3][3]) {
+  // components xx, yy, zz, xy, xz, yz
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) M[i][j] = 0.0;
+  M[0][0] = c[0];
+  M[1][1] = c[1];
+  M[0][1] = M[1][0] = c[3];
+  if (dim == 3) {
+    M[2][2] = c[2];
+    M[0][2] = M[2][0] = c[4];
+    M[1][2] = M[2][1] = c[5];
+  }
+}
+
+bool is_spd(int dim, double M[3][3]) {
+  if (!(M[0][0] > 0.0)) return false;
+  const double m2 = M[0][0] * M[1][1] - M[0][1] * M[1][0];
+  if (!(m2 > 0.0)) return false;
+  if (dim == 2) return true;
+  const double m3 = M[0][0] * (M[1][1] * M[2][2] - M[1][2] * M[2][1]) -
+                    M[0][1] * (M[1][0] * M[2][2] - M[1][2] * M[2][0]) +
+                    M[0][2] * (M[1][0] * M[2][1] - M[1][1] * M[2][0]);
+  return m3 > 0.0;
+}
+
+void invert(int dim, double B[3][3], double out[3][3]) {
+  if (dim == 2) {
+    const double det = B[0][0] * B[1][1] - B[0][1] * B[1][0];
+    out[0][0] = B[1][1] / det;
+    out[1][1] = B[0][0] / det;
+    out[0][1] = -B[0][1] / det;
+    out[1][0] = -B[1][0] / det;
+    return;
+  }
+  double C[3][3];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      const int i1 = (i + 1) % 3, i2 = (i + 2) % 3, j1 = (j + 1) % 3, j2 = (j + 2) % 3;
+      C[i][j] = B[i1][j1] * B[i2][j2] - B[i1][j2] * B[i2][j1];
+    }
+  const double det = B[0][0] * C[0][0] + B[0][1] * C[0][1] + B[0][2] * C[0][2];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) out[i][j] = C[j][i] / det;
+}
+
+// Smallest eigenvalue of a symmetric 2x2 or 3x3 matrix (closed forms; the
+// 3x3 one is the trigonometric solution of the characteristic cubic).
+double lambda_min(int dim, double M[3][3]) {
+  if (dim == 2) {
+    const double m = 0.5 * (M[0][0] + M[1][1]), d = 0.5 * (M[0][0] - M[1][1]);
+    return m - std::sqrt(d * d + M[0][1] * M[0][1]);
+  }
+  const double p1 = M[0][1] * M[0][1] + M[0][2] * M[0][2] + M[1][2] * M[1][2];
+  const double q = (M[0][0] + M[1][1] + M[2][2]) / 3.0;
+  if (p1 == 0.0) return std::min(M[0][0], std::min(M[1][1], M[2][2]));
+  const double p2 = (M[0][0] - q) * (M[0][0] - q) + (M[1][1] - q) * (M[1][1] - q) +
+                    (M[2][2] - q) * (M[2][2] - q) + 2.0 * p1;
+  const double p = std::sqrt(p2 / 6.0);
+  double B[3][3];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) B[i][j] = (M[i][j] - (i == j ? q : 0.0)) / p;
+  const double detB = B[0][0] * (B[1][1] * B[2][2] - B[1][2] * B[2][1]) -
+                      B[0][1] * (B[1][0] * B[2][2] - B[1][2] * B[2][0]) +
+                      B[0][2] * (B[1][0] * B[2][1] - B[1][1] * B[2][0]);
+  double r = detB / 2.0;
+  r = std::max(-1.0, std::min(1.0, r));
+  const double phi = std::acos(r) / 3.0;
+  const double pi = 3.14159265358979323846;
+  return q + 2.0 * p * std::cos(phi + 2.0 * pi / 3.0);
+}
+
+double default_rate(int lattice, int k) {
+  if (k == 1 || k == 2) return 1.1;
+  if (lattice == LBM_CDE_D2Q9) return (k == 7 || k == 8) ? 1.2 : 0.0;
+  return k >= 9 ? 1.2 : 0.0;
+}
+
+int validate(const lbm_cde_run_desc& d, int idx) {
+  if (d.lattice != LBM_CDE_D2Q9 && d.lattice != LBM_CDE_D3Q15)
+    return fail_init(LBM_CDE_EINVAL, "run %d: unknown lattice %d", idx, d.lattice);
+  if (d.precision < LBM_CDE_FP64 || d.precision > LBM_CDE_FP16_SPLIT)
+    return fail_init(LBM_CDE_EINVAL, "run %d: unknown precision %d", idx, d.precision);
+  if (d.nx < 1 || d.ny < 1 || d.nz < 1)
+    return fail_init(LBM_CDE_EINVAL, "run %d: grid %lld x %lld x %lld has an empty axis", idx, (long long)d.nx,
+                     (long long)d.ny, (long long)d.nz);
+  if (d.lattice == LBM_CDE_D2Q9 && d.nz != 1)
+    return fail_init(LBM_CDE_EINVAL, "run %d: D2Q9 needs nz = 1", idx);
+  if (d.nx > (1ll << 40) || d.ny > (1ll << 40) || d.nz > (1ll << 40) ||
+      (double)d.nx * (double)d.ny * (double)d.nz > 9.0e15)
+    return fail_init(LBM_CDE_EINVAL, "run %d: grid too large", idx);
+  const int dim = d.lattice == LBM_CDE_D2Q9 ? 2 : 3;
+  for (int a = 0; a < dim; ++a)
+    if (d.bc[a] < LBM_CDE_PERIODIC || d.bc[a] > LBM_CDE_SPECULAR)
+      return fail_init(LBM_CDE_EINVAL, "run %d: unknown boundary kind %d on axis %d", idx, d.bc[a], a);
+  if (d.u_kind < LBM_CDE_U_CONST || d.u_kind > LBM_CDE_U_FIELD)
+    return fail_init(LBM_CDE_EINVAL, "run %d: unknown velocity kind %d", idx, d.u_kind);
+  if (d.u_kind == LBM_CDE_U_SEPARABLE && !d.u_tables)
+    return fail_init(LBM_CDE_EINVAL, "run %d: separable velocity without tables", idx);
+  if (d.u_kind == LBM_CDE_U_FIELD && !d.u_field)
+    return fail_init(LBM_CDE_EINVAL, "run %d: velocity field pointer is NULL", idx);
+  if (d.heat_rule < LBM_CDE_HEAT_LAMBDA_MIN || d.heat_rule > LBM_CDE_HEAT_EXPLICIT)
+    return fail_init(LBM_CDE_EINVAL, "run %d: unknown heat-flux rate rule %d", idx, d.heat_rule);
+  if (!std::isfinite(d.phi_ref)) return fail_init(LBM_CDE_EINVAL, "run %d: phi_ref is not finite", idx);
+  if (d.precision == LBM_CDE_FP16_SPLIT)
+    return fail_init(LBM_CDE_EUNSUPPORTED, "run %d: FP16 split storage is not built in this library version", idx);
+  if (d.lattice == LBM_CDE_D3Q15 && d.precision == LBM_CDE_FP16_SPLIT)
+    return fail_init(LBM_CDE_EUNSUPPORTED, "run %d: FP16 split storage is built for D2Q9 only", idx);
+  if (d.lattice == LBM_CDE_D3Q15 && d.D_field)
+    return fail_init(LBM_CDE_EUNSUPPORTED, "run %d: per-node D fields are built for D2Q9 only", idx);
+  return LBM_CDE_OK;
+}
+
+// Derive A, heat rates and diagonal rates of a run with constant D.
+int derive(Run& r, int idx) {
+  const lbm_cde_run_desc& d = r.d;
+  r.kappa = kappa_of(d.lattice);
+  for (int k = 0; k < 15; ++k) {
+    const double v = d.rates[k] != 0.0 ? d.rates[k] : default_rate(d.lattice, k);
+    r.s[k] = v;
+  }
+  static const int used2[] = {1, 2, 7, 8, -1, -1, -1, -1, -1};
+  static const int used3[] = {1, 2, 9, 10, 11, 12, 13, 14, -1};
+  const int* used = d.lattice == LBM_CDE_D2Q9 ? used2 : used3;
+  for (int j = 0; j < 9 && used[j] >= 0; ++j) {
+    const double v = r.s[used[j]];
+    if (!(v > 0.0 && v < 2.0))
+      return fail_init(LBM_CDE_EUNSTABLE, "run %d: rate s%d = %g outside (0, 2)", idx, used[j], v);
+  }
+  if (d.heat_rule == LBM_CDE_HEAT_EXPLICIT)
+    for (int a = 0; a < r.dim; ++a)
+      if (!(d.heat_rates[a] > 0.0 && d.heat_rates[a] < 2.0))
+        return fail_init(LBM_CDE_EUNSTABLE, "run %d: heat-flux rate %g outside (0, 2)", idx, d.heat_rates[a]);
+  if (d.D_field) {
+    for (int a = 0; a < 3; ++a) r.heat[a] = d.heat_rates[a];
+    return LBM_CDE_OK;  // A per node, derived on the GPU
+  }
+  double D[3][3], B[3][3];
+  sym_from_components(r.dim, d.D, D);
+  for (int i = 0; i < 6; ++i)
+    if (!std::isfinite(d.D[i])) return fail_init(LBM_CDE_EINVAL, "run %d: D has a non-finite entry", idx);
+  if (!is_spd(r.dim, D)) return fail_init(LBM_CDE_ENOTSPD, "run %d: D is not symmetric positive definite", idx);
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) B[i][j] = D[i][j] / r.kappa + (i == j ? 0.5 : 0.0);
+  invert(r.dim, B, r.A);
+  const double lmin = lambda_min(r.dim, r.A);
+  for (int a = 0; a < r.dim; ++a) {
+    if (d.heat_rule == LBM_CDE_HEAT_LAMBDA_MIN) r.heat[a] = lmin;
+    else if (d.heat_rule == LBM_CDE_HEAT_PAPER) r.heat[a] = r.A[a][a];
+    else r.heat[a] = d.heat_rates[a];
+    if (!(r.heat[a] > 0.0 && r.heat[a] < 2.0))
+      return fail_init(LBM_CDE_EUNSTABLE, "run %d: heat-flux rate %g outside (0, 2)", idx, r.heat[a]);
+  }
+  return LBM_CDE_OK;
+}
+
+// |u| < c_s check for constant and separable velocities (a bound for the latter).
+int check_velocity(const Run& r, int idx) {
+  const lbm_cde_run_desc& d = r.d;
+  double bound2 = 0.0;
+  if (d.u_kind == LBM_CDE_U_CONST) {
+    for (int c = 0; c < r.dim; ++c) {
+      if (!std::isfinite(d.u_const[c])) return fail_init(LBM_CDE_EINVAL, "run %d: u is not finite", idx);
+      bound2 += d.u_const[c] * d.u_const[c];
+    }
+  } else if (d.u_kind == LBM_CDE_U_SEPARABLE) {
+    const int64_t stride = 1 + d.nx + d.ny + d.nz;
+    for (int c = 0; c < r.dim; ++c) {
+      const double* t = d.u_tables + c * stride;
+      double mx[3] = {0, 0, 0};
+      const int64_t len[3] = {d.nx, d.ny, d.nz};
+      const double* seg = t + 1;
+      for (int a = 0; a < 3; ++a) {
+        for (int64_t i = 0; i < len[a]; ++i) {
+          if (!std::isfinite(seg[i])) return fail_init(LBM_CDE_EINVAL, "run %d: u table not finite", idx);
+          mx[a] = std::max(mx[a], std::fabs(seg[i]));
+        }
+        seg += len[a];
+      }
+      const double b = std::fabs(t[0]) * mx[0] * mx[1] * mx[2];
+      bound2 += b * b;
+    }
+  } else {
+    return LBM_CDE_OK;  // per-node field: not checked
+  }
+  if (!(std::sqrt(bound2) < 1.0 / std::sqrt(3.0)))
+    return fail_init(LBM_CDE_EUNSTABLE, "run %d: |u| reaches the lattice sound speed 1/sqrt(3)", idx);
+  return LBM_CDE_OK;
+}
+
+// Workspace layout of one run; with base == nullptr only sizes are computed.
+size_t layout(Run& r, char* base) {
+  const lbm_cde_run_desc& d = r.d;
+  r.dim = d.lattice == LBM_CDE_D2Q9 ? 2 : 3;
+  r.Q = d.lattice == LBM_CDE_D2Q9 ? 9 : 15;
+  r.dbl = d.precision == LBM_CDE_FP64;
+  r.elem = r.dbl ? 8 : 4;
+  r.nodes = d.nx * d.ny * d.nz;
+  // planes padded to a multiple of 256 bytes plus a skew, so that the same
+  // node of consecutive planes does not fall on the same HBM channel and bank
+  r.plane = (int64_t)((align_up((size_t)r.nodes * r.elem) + plane_skew()) / r.elem);
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    char* p = base ? base + off : nullptr;
+    off += align_up(bytes);
+    return p;
+  };
+  const size_t popbytes = (size_t)r.plane * r.elem * r.Q;
+  r.pop[0] = take(popbytes);
+  r.pop[1] = take(popbytes);
+  r.utab = nullptr;
+  r.ufield = nullptr;
+  r.node_par = nullptr;
+  if (d.u_kind == LBM_CDE_U_SEPARABLE) r.utab = take((size_t)r.dim * (1 + d.nx + d.ny + d.nz) * r.elem);
+  if (d.u_kind == LBM_CDE_U_FIELD) r.ufield = take((size_t)r.dim * r.nodes * r.elem);
+  if (d.D_field) r.node_par = take((size_t)(r.dim == 2 ? 5 : 9) * r.nodes * r.elem);
+  r.red_partial = (double*)take(sizeof(double) * 4 * RED_BLOCKS);
+  r.red_out = (double*)take(sizeof(double) * 4);
+  r.flags = (unsigned long long*)take(sizeof(unsigned long long) * 4);
+  return off;
+}
+
+RunArgs make_args(const lbm_cde* h, const Run& r, int parity) {
+  RunArgs a;
+  std::memset(&a, 0, sizeof a);
+  a.src = r.pop[parity];
+  a.dst = r.pop[parity ^ 1];
+  a.nx = r.d.nx;
+  a.ny = r.d.ny;
+  a.nz = r.d.nz;
+  a.plane = r.plane;
+  for (int i = 0; i < 3; ++i) a.bc[i] = r.d.bc[i];
+  a.u_kind = r.d.u_kind;
+  for (int i = 0; i < 3; ++i) a.u_const[i] = r.d.u_const[i];
+  a.u_tab = r.utab;
+  a.u_field = r.ufield;
+  a.node_par = r.node_par;
+  a.phi_ref = r.dbl ? 0.0 : r.d.phi_ref;
+  for (int k = 0; k < 15; ++k) a.s[k] = r.s[k];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) a.A[i][j] = r.A[i][j];
+  for (int i = 0; i < 3; ++i) a.heat[i] = r.heat[i];
+  a.xcd_remap = r.var.xcd ? 1 : 0;
+  a.active = 1;
+  return a;
+}
+
+// ---- kernel dispatch ------------------------------------------------------
+
+// Default launch variants, from sweeps on MI355X: wide one-row tiles with
+// streaming stores and the hardware's round-robin XCD order were fastest
+// (the XCD-contiguous remap was 5-10% slower on 4096^2 D2Q9).
+Variant default_variant(int lattice, bool dbl) {
+  if (lattice == LBM_CDE_D3Q15) return Variant{128, 1, 1, true, false};
+  return dbl ? Variant{128, 2, 1, true, false} : Variant{256, 1, 1, true, false};
+}
+
+using StepFn = void (*)(const RunArgs, hipStream_t);
+
+template <typename R, int BX, int BY, int NY, bool WALLS, bool NT>
+void launch_d2q9(const RunArgs a, hipStream_t s) {
+  const int64_t ntx = (a.nx + BX - 1) / BX;
+  const int64_t nty = (a.ny + BY * NY - 1) / (BY * NY);
+  hipLaunchKernelGGL((k_step_d2q9<R, BX, BY, NY, WALLS, NT>), dim3((unsigned)(ntx * nty)), dim3(BX, BY), 0, s, a);
+}
+
+template <typename R, int BX, int BY, int NY, bool WALLS, bool NT>
+void launch_d3q15(const RunArgs a, hipStream_t s) {
+  const int64_t ntx = (a.nx + BX - 1) / BX;
+  const int64_t nty = (a.ny + BY * NY - 1) / (BY * NY);
+  hipLaunchKernelGGL((k_step_d3q15<R, BX, BY, NY, WALLS, NT>), dim3((unsigned)(ntx * nty * a.nz)), dim3(BX, BY), 0,
+                     s, a);
+}
+
+struct Step3Entry {
+  int bx, by, ny;
+  bool nt;
+  StepFn fn[2][2];
+};
+
+#define STEP3_ENTRY(BX, BY, NY, NT)                                                      \
+  Step3Entry {                                                                           \
+    BX, BY, NY, NT, {                                                                    \
+      {launch_d3q15<float, BX, BY, NY, false, NT>, launch_d3q15<float, BX, BY, NY, true, NT>}, \
+      {launch_d3q15<double, BX, BY, NY, false, NT>, launch_d3q15<double, BX, BY, NY, true, NT>} \
+    }                                                                                    \
+  }
+
+const Step3Entry kSteps3[] = {
+    STEP3_ENTRY(64, 4, 1, false), STEP3_ENTRY(128, 2, 1, false), STEP3_ENTRY(256, 1, 1, false),
+    STEP3_ENTRY(64, 2, 2, false), STEP3_ENTRY(128, 1, 1, false), STEP3_ENTRY(64, 4, 1, true),
+    STEP3_ENTRY(128, 2, 1, true), STEP3_ENTRY(256, 1, 1, true), STEP3_ENTRY(64, 2, 2, true),
+    STEP3_ENTRY(128, 1, 1, true),
+};
+
+struct StepEntry {
+  int bx, by, ny;
+  bool nt;
+  StepFn fn[2][2];  // [double?][walls?]
+};
+
+#define STEP_ENTRY(BX, BY, NY, NT)                                                     \
+  StepEntry {                                                                          \
+    BX, BY, NY, NT, {                                                                  \
+      {launch_d2q9<float, BX, BY, NY, false, NT>, launch_d2q9<float, BX, BY, NY, true, NT>}, \
+      {launch_d2q9<double, BX, BY, NY, false, NT>, launch_d2q9<double, BX, BY, NY, true, NT>} \
+    }                                                                                  \
+  }
+
+const StepEntry kSteps[] = {
+    STEP_ENTRY(64, 4, 1, false),  STEP_ENTRY(64, 4, 2, false),  STEP_ENTRY(128, 2, 1, false),
+    STEP_ENTRY(256, 1, 1, false), STEP_ENTRY(256, 1, 2, false), STEP_ENTRY(64, 2, 4, false),
+    STEP_ENTRY(128, 2, 2, false), STEP_ENTRY(512, 1, 1, false), STEP_ENTRY(128, 1, 1, false),
+    STEP_ENTRY(64, 4, 1, true),   STEP_ENTRY(64, 4, 2, true),   STEP_ENTRY(128, 2, 1, true),
+    STEP_ENTRY(256, 1, 1, true),  STEP_ENTRY(256, 1, 2, true),  STEP_ENTRY(64, 2, 4, true),
+    STEP_ENTRY(128, 2, 2, true),  STEP_ENTRY(512, 1, 1, true),  STEP_ENTRY(128, 1, 1, true),
+};
+
+StepFn find_step(const Run& r, const Variant& v) {
+  const int p = r.dbl ? 1 : 0, w = r.walls ? 1 : 0;
+  if (r.d.lattice == LBM_CDE_D3Q15) {
+    for (const auto& e : kSteps3)
+      if (e.bx == v.bx && e.by == v.by && e.ny == v.ny && e.nt == v.nt) return e.fn[p][w];
+    return nullptr;
+  }
+  for (const auto& e : kSteps)
+    if (e.bx == v.bx && e.by == v.by && e.ny == v.ny && e.nt == v.nt) return e.fn[p][w];
+  return nullptr;
+}
+
+StepFn pick_step(const lbm_cde* h, const Run& r) {
+  StepFn f = find_step(r, r.var);
+  return f ? f : find_step(r, default_variant(r.d.lattice, r.dbl));
+}
+
+int launch_steps(lbm_cde* h, hipStream_t s, int64_t n) {
+  for (int64_t t = 0; t < n; ++t) {
+    for (auto& r : h->runs) {
+      if (r.d.max_steps >= 0 && r.steps >= r.d.max_steps) continue;
+      const RunArgs a = make_args(h, r, (int)(r.steps & 1));
+      pick_step(h, r)(a, s);
+      r.steps += 1;
+    }
+  }
+  HIP_TRY(h, hipGetLastError());
+  return LBM_CDE_OK;
+}
+
+void drop_graphs(lbm_cde* h) {
+  for (auto& g : h->graph)
+    if (g) {
+      (void)hipGraphExecDestroy(g);
+      g = nullptr;
+    }
+}
+
+// Capture kGraphSteps steps starting from parity p on the private stream.
+int build_graph(lbm_cde* h, int p) {
+  std::vector<int64_t> saved;
+  for (auto& r : h->runs) {
+    saved.push_back(r.steps);
+    r.steps = p;  // only the parity matters for the captured launches
+  }
+  HIP_TRY(h, hipStreamBeginCapture(h->capture, hipStreamCaptureModeThreadLocal));
+  for (int t = 0; t < kGraphSteps; ++t)
+    for (auto& r : h->runs) {
+      const RunArgs a = make_args(h, r, (int)(r.steps & 1));
+      pick_step(h, r)(a, h->capture);
+      r.steps += 1;
+    }
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamEndCapture(h->capture, &g);
+  for (size_t i = 0; i < h->runs.size(); ++i) h->runs[i].steps = saved[i];
+  if (e != hipSuccess) return fail(h, LBM_CDE_EHIP, "graph capture: %s", hipGetErrorString(e));
+  e = hipGraphInstantiate(&h->graph[p], g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e != hipSuccess) return fail(h, LBM_CDE_EHIP, "graph instantiate: %s", hipGetErrorString(e));
+  return LBM_CDE_OK;
+}
+
+Run* get_run(lbm_cde* h, int32_t run) {
+  if (!h || run < 0 || run >= (int32_t)h->runs.size()) return nullptr;
+  return &h->runs[run];
+}
+
+template <typename R>
+void launch_init(const Run& r, const RunArgs& a, const double* phi0, hipStream_t s) {
+  const int64_t N = r.nodes;
+  const unsigned blocks = (unsigned)((N + 255) / 256);
+  if (r.d.lattice == LBM_CDE_D2Q9) hipLaunchKernelGGL(k_init_d2q9<R>, dim3(blocks), dim3(256), 0, s, a, phi0);
+  else hipLaunchKernelGGL(k_init_d3q15<R>, dim3(blocks), dim3(256), 0, s, a, phi0);
+}
+
+int reduce_into(lbm_cde* h, Run& r, int kind, double x_ref, double* out_dev) {
+  RunArgs a = make_args(h, r, (int)(r.steps & 1));
+  if (r.dbl)
+    hipLaunchKernelGGL(k_reduce_partial<double>, dim3(RED_BLOCKS), dim3(RED_THREADS), 0, h->stream, a, r.Q, kind,
+                       x_ref, r.red_partial);
+  else
+    hipLaunchKernelGGL(k_reduce_partial<float>, dim3(RED_BLOCKS), dim3(RED_THREADS), 0, h->stream, a, r.Q, kind,
+                       x_ref, r.red_partial);
+  hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(RED_THREADS), 0, h->stream, r.red_partial, RED_BLOCKS, out_dev);
+  HIP_TRY(h, hipGetLastError());
+  return LBM_CDE_OK;
+}
+
+void parse_env(lbm_cde* h) {
+  const char* t2 = std::getenv("LBM_CDE_TILE");
+  const char* t3 = std::getenv("LBM_CDE_TILE3");
+  const char* nt = std::getenv("LBM_CDE_NT");
+  const char* xcd = std::getenv("LBM_CDE_XCD");
+  if (!t2 && !t3 && !nt && !xcd) return;
+  h->env_variant = true;
+  int bx, by, ny;
+  if (t2 && std::sscanf(t2, "%dx%dx%d", &bx, &by, &ny) == 3) h->env = Variant{bx, by, ny, false, false};
+  if (t3 && std::sscanf(t3, "%dx%dx%d", &bx, &by, &ny) == 3) h->env3 = Variant{bx, by, ny, false, false};
+  h->env.nt = h->env3.nt = nt ? std::atoi(nt) != 0 : false;
+  h->env.xcd = h->env3.xcd = xcd ? std::atoi(xcd) != 0 : false;
+}
+
+// Per-run set-up of lbm_cde_init (errors go to the thread's init error text).
+int init_runs(lbm_cde* h, const lbm_cde_run_desc* runs, int32_t nruns, const double* const* phi0, char* workspace,
+              size_t ws_bytes) {
+  size_t off = 0;
+  for (int i = 0; i < nruns; ++i) {
+    int rc = validate(runs[i], i);
+    if (rc) return rc;
+    if (!phi0[i]) return fail_init(LBM_CDE_EINVAL, "run %d: phi0 is NULL", i);
+    Run r;
+    r.d = runs[i];
+    const size_t need = layout(r, nullptr);
+    if (off + need > ws_bytes) return fail_init(LBM_CDE_ENOSPC, "init: workspace of %zu bytes is too small", ws_bytes);
+    layout(r, workspace + off);
+    off += need;
+    if ((rc = derive(r, i)) || (rc = check_velocity(r, i))) return rc;
+    r.walls = false;
+    for (int a = 0; a < r.dim; ++a) r.walls |= r.d.bc[a] != LBM_CDE_PERIODIC;
+    r.var = default_variant(r.d.lattice, r.dbl);
+    if (h->env_variant) r.var = r.d.lattice == LBM_CDE_D3Q15 ? h->env3 : h->env;
+    if (!find_step(r, r.var)) return fail_init(LBM_CDE_EINVAL, "run %d: launch variant not built", i);
+    // host tables are copied during init; keep no pointer to caller memory
+    r.d.u_tables = nullptr;
+    r.d.u_field = nullptr;
+    r.d.D_field = nullptr;
+    const lbm_cde_run_desc& orig = runs[i];
+    hipStream_t s = h->stream;
+    if (orig.u_kind == LBM_CDE_U_SEPARABLE) {
+      const size_t n = (size_t)r.dim * (1 + orig.nx + orig.ny + orig.nz);
+      if (r.dbl) {
+        HIP_TRY(nullptr, hipMemcpyAsync(r.utab, orig.u_tables, n * 8, hipMemcpyHostToDevice, s));
+        HIP_TRY(nullptr, hipStreamSynchronize(s));  // the caller's table may go away after init
+      } else {
+        std::vector<float> tmp(n);
+        for (size_t k = 0; k < n; ++k) tmp[k] = (float)orig.u_tables[k];
+        HIP_TRY(nullptr, hipMemcpyAsync(r.utab, tmp.data(), n * 4, hipMemcpyHostToDevice, s));
+        HIP_TRY(nullptr, hipStreamSynchronize(s));
+      }
+    } else if (orig.u_kind == LBM_CDE_U_FIELD) {
+      const int64_t n = r.dim * r.nodes;
+      const unsigned blocks = (unsigned)((n + 255) / 256);
+      if (r.dbl)
+        hipLaunchKernelGGL(k_convert<double>, dim3(blocks), dim3(256), 0, s, orig.u_field, (double*)r.ufield, n);
+      else
+        hipLaunchKernelGGL(k_convert<float>, dim3(blocks), dim3(256), 0, s, orig.u_field, (float*)r.ufield, n);
+    }
+    if (orig.D_field) {
+      HIP_TRY(nullptr, hipMemsetAsync(r.flags, 0, sizeof(unsigned long long), s));
+      const unsigned blocks = (unsigned)((r.nodes + 255) / 256);
+      if (r.dbl)
+        hipLaunchKernelGGL(k_node_params_2d<double>, dim3(blocks), dim3(256), 0, s, orig.D_field, r.nodes, r.kappa,
+                           orig.heat_rule, orig.heat_rates[0], orig.heat_rates[1], (double*)r.node_par, r.flags);
+      else
+        hipLaunchKernelGGL(k_node_params_2d<float>, dim3(blocks), dim3(256), 0, s, orig.D_field, r.nodes, r.kappa,
+                           orig.heat_rule, orig.heat_rates[0], orig.heat_rates[1], (float*)r.node_par, r.flags);
+      unsigned long long bad = 0;
+      HIP_TRY(nullptr, hipMemcpyAsync(&bad, r.flags, sizeof bad, hipMemcpyDeviceToHost, s));
+      HIP_TRY(nullptr, hipStreamSynchronize(s));
+      if (bad) return fail_init(LBM_CDE_ENOTSPD, "run %d: %llu nodes of D_field are not SPD", i, bad);
+    }
+    // initial populations: the equilibrium of phi0, written to buffer 0
+    const RunArgs a = make_args(h, r, 1);
+    if (r.dbl) launch_init<double>(r, a, phi0[i], s);
+    else launch_init<float>(r, a, phi0[i], s);
+    HIP_TRY(nullptr, hipGetLastError());
+    h->runs.push_back(r);
+  }
+  HIP_TRY(nullptr, hipStreamCreateWithFlags(&h->capture, hipStreamNonBlocking));
+  return LBM_CDE_OK;
+}
+
+// ---- autotuner -------------------------------------------------------------
+
+std::string tune_key(const Run& r) {
+  hipDeviceProp_t prop;
+  int dev = 0;
+  std::string arch = "unknown";
+  if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess) arch = prop.gcnArchName;
+  char buf[256];
+  std::snprintf(buf, sizeof buf, "%s:%s:%s:%lldx%lldx%lld:%d%d%d", arch.c_str(),
+                r.d.lattice == LBM_CDE_D2Q9 ? "d2q9" : "d3q15", r.dbl ? "fp64" : "fp32", (long long)r.d.nx,
+                (long long)r.d.ny, (long long)r.d.nz, r.d.bc[0], r.d.bc[1], r.d.bc[2]);
+  return buf;
+}
+
+bool cache_lookup(const std::string& key, Variant& v) {
+  const char* path = std::getenv("LBM_CDE_TUNE_CACHE");
+  if (!path) return false;
+  FILE* f = std::fopen(path, "r");
+  if (!f) return false;
+  char k[256];
+  int bx, by, ny, nt, xcd;
+  double ms;
+  bool found = false;
+  while (std::fscanf(f, "%255s %d %d %d %d %d %lf", k, &bx, &by, &ny, &nt, &xcd, &ms) == 7)
+    if (key == k) {
+      v = Variant{bx, by, ny, nt != 0, xcd != 0};
+      found = true;  // the last entry wins
+    }
+  std::fclose(f);
+  return found;
+}
+
+void cache_store(const std::string& key, const Variant& v, double ms) {
+  const char* path = std::getenv("LBM_CDE_TUNE_CACHE");
+  if (!path) return;
+  if (FILE* f = std::fopen(path, "a")) {
+    std::fprintf(f, "%s %d %d %d %d %d %.6f\n", key.c_str(), v.bx, v.by, v.ny, (int)v.nt, (int)v.xcd, ms);
+    std::fclose(f);
+  }
+}
+
+// Time `trials` launches of variant v on run r.  Every launch reads the
+// current state and writes the other buffer, so the state is not changed.
+int time_variant(lbm_cde* h, Run& r, const Variant& v, int trials, double* ms) {
+  StepFn fn = find_step(r, v);
+  if (!fn) return LBM_CDE_EINVAL;
+  const Variant saved = r.var;
+  r.var = v;
+  const RunArgs a = make_args(h, r, (int)(r.steps & 1));
+  r.var = saved;
+  hipEvent_t e0, e1;
+  HIP_TRY(h, hipEventCreate(&e0));
+  HIP_TRY(h, hipEventCreate(&e1));
+  fn(a, h->stream);  // warm-up
+  HIP_TRY(h, hipEventRecord(e0, h->stream));
+  for (int t = 0; t < trials; ++t) fn(a, h->stream);
+  HIP_TRY(h, hipEventRecord(e1, h->stream));
+  HIP_TRY(h, hipEventSynchronize(e1));
+  float elapsed = 0.f;
+  HIP_TRY(h, hipEventElapsedTime(&elapsed, e0, e1));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  HIP_TRY(h, hipGetLastError());
+  *ms = elapsed / trials;
+  return LBM_CDE_OK;
+}
+
+}  // namespace
+
+// ---- C ABI ----------------------------------------------------------------
+
+extern "C" {
+
+int lbm_cde_workspace_bytes(const lbm_cde_run_desc* runs, int32_t nruns, size_t* bytes) {
+  if (!runs || nruns < 1 || !bytes) return fail_init(LBM_CDE_EINVAL, "workspace_bytes: null argument or nruns < 1");
+  size_t total = 0;
+  for (int i = 0; i < nruns; ++i) {
+    const int rc = validate(runs[i], i);
+    if (rc) return rc;
+    Run r;
+    r.d = runs[i];
+    total += layout(r, nullptr);
+  }
+  *bytes = total;
+  return LBM_CDE_OK;
+}
+
+int lbm_cde_init(const lbm_cde_run_desc* runs, int32_t nruns, const double* const* phi0, void* workspace,
+                 size_t ws_bytes, void* hip_stream, lbm_cde_handle* out) {
+  if (out) *out = nullptr;
+  if (!runs || nruns < 1 || !phi0 || !workspace || !out)
+    return fail_init(LBM_CDE_EINVAL, "init: null argument or nruns < 1");
+  if ((uintptr_t)workspace % kAlign) return fail_init(LBM_CDE_EINVAL, "init: workspace not 256-byte aligned");
+  lbm_cde* h = new lbm_cde();
+  h->stream = (hipStream_t)hip_stream;
+  parse_env(h);
+  const int rc = init_runs(h, runs, nruns, phi0, (char*)workspace, ws_bytes);
+  if (rc) {
+    if (h->capture) (void)hipStreamDestroy(h->capture);
+    delete h;
+    return rc;
+  }
+  *out = h;
+  return LBM_CDE_OK;
+}
+
+int lbm_cde_step(lbm_cde_handle h, int64_t n) {
+  if (!h) return fail_init(LBM_CDE_EINVAL, "step: null handle");
+  if (n < 0) return fail(h, LBM_CDE_EINVAL, "step: negative step count %lld", (long long)n);
+  int64_t done = 0;
+  while (done < n) {
+    // a captured graph is valid while every run takes all kGraphSteps steps
+    bool uniform = n - done >= kGraphSteps;
+    int parity = -1;
+    for (auto& r : h->runs) {
+      if (r.d.max_steps >= 0 && r.steps + kGraphSteps > r.d.max_steps) uniform = false;
+      const int p = (int)(r.steps & 1);
+      if (parity < 0) parity = p;
+      else if (parity != p) uniform = false;
+    }
+    if (uniform && parity >= 0) {
+      if (!h->graph[parity]) {
+        const int rc = build_graph(h, parity);
+        if (rc) return rc;
+      }
+      HIP_TRY(h, hipGraphLaunch(h->graph[parity], h->stream));
+      for (auto& r : h->runs) r.steps += kGraphSteps;
+      done += kGraphSteps;
+    } else {
+      const int64_t chunk = std::min<int64_t>(n - done, uniform ? kGraphSteps : 1);
+      const int rc = launch_steps(h, h->stream, chunk);
+      if (rc) return rc;
+      done += chunk;
+    }
+  }
+  return LBM_CDE_OK;
+}
+
+int lbm_cde_steps_done(lbm_cde_handle h, int32_t run, int64_t* steps) {
+  Run* r = get_run(h, run);
+  if (!r || !steps) return fail(h, LBM_CDE_EINVAL, "steps_done: bad handle, run or pointer");
+  *steps = r->steps;
+  return LBM_CDE_OK;
+}
+
+int lbm_cde_moments(lbm_cde_handle h, int32_t run, double* phi_out) {
+  Run* r = get_run(h, run);
+  if (!r || !phi_out) return fail(h, LBM_CDE_EINVAL, "moments: bad handle, run or pointer");
+  const RunArgs a = make_args(h, *r, (int)(r->steps & 1));
+  const unsigned blocks = (unsigned)((r->nodes + 255) / 256);
+  if (r->dbl) hipLaunchKernelGGL(k_moments<double>, dim3(blocks), dim3(256), 0, h->stream, a, r->Q, phi_out);
+  else hipLaunchKernelGGL(k_moments<float>, dim3(blocks), dim3(256), 0, h->stream, a, r->Q, phi_out);
+  HIP_TRY(h, hipGetLastError());
+  return LBM_CDE_OK;
+}
+
+int lbm_cde_reduce(lbm_cde_handle h, int32_t run, int32_t kind, double x_ref, double* out) {
+  Run* r = get_run(h, run);
+  if (!r || !out) return fail(h, LBM_CDE_EINVAL, "reduce: bad handle, run or pointer");
+  if (kind < LBM_CDE_RED_MASS || kind > LBM_CDE_RED_NONFINITE)
+    return fail(h, LBM_CDE_EINVAL, "reduce: unknown kind %d", kind);
+  if (kind == LBM_CDE_RED_XMOMENTS && !std::isfinite(x_ref))
+    return fail(h, LBM_CDE_EINVAL, "reduce: x_ref is not finite");
+  int rc = reduce_into(h, *r, kind, x_ref, r->red_out);
+  if (rc) return rc;
+  double res[4];
+  HIP_TRY(h, hipMemcpyAsync(res, r->red_out, sizeof res, hipMemcpyDeviceToHost, h->stream));
+  HIP_TRY(h, hipStreamSynchronize(h->stream));
+  if (kind == LBM_CDE_RED_NONFINITE) {
+    out[0] = res[3];
+    out[1] = out[2] = 0.0;
+    return LBM_CDE_OK;
+  }
+  out[0] = res[0];
+  out[1] = kind == LBM_CDE_RED_XMOMENTS ? res[1] : 0.0;
+  out[2] = kind == LBM_CDE_RED_XMOMENTS ? res[2] : 0.0;
+  if (res[3] != 0.0) return fail(h, LBM_CDE_ENONFINITE, "reduce: %g non-finite values in the state", res[3]);
+  return LBM_CDE_OK;
+}
+
+int lbm_cde_run_sampled(lbm_cde_handle h, int64_t n, int64_t every, double* hist, int64_t capacity) {
+  if (!h) return fail_init(LBM_CDE_EINVAL, "run_sampled: null handle");
+  if (!hist || every < 1 || n < 0 || n % every)
+    return fail(h, LBM_CDE_EINVAL, "run_sampled: need hist != NULL, every >= 1 and n a multiple of every");
+  const int64_t rows = n / every;
+  if (h->sample_rows + rows > capacity)
+    return fail(h, LBM_CDE_EINVAL, "run_sampled: history capacity %lld exceeded", (long long)capacity);
+  const int64_t nr = (int64_t)h->runs.size();
+  for (int64_t k = 0; k < rows; ++k) {
+    int rc = lbm_cde_step(h, every);
+    if (rc) return rc;
+    for (int64_t i = 0; i < nr; ++i) {
+      Run& r = h->runs[i];
+      double x_ref = r.d.xref0 + r.d.xref_drift * (double)r.steps;
+      x_ref -= (double)r.d.nx * std::floor(x_ref / (double)r.d.nx);
+      rc = reduce_into(h, r, LBM_CDE_RED_XMOMENTS, x_ref, r.red_out);
+      if (rc) return rc;
+      HIP_TRY(h, hipMemcpyAsync(hist + ((h->sample_rows + k) * nr + i) * 3, r.red_out, 3 * sizeof(double),
+                                hipMemcpyDeviceToDevice, h->stream));
+    }
+  }
+  h->sample_rows += rows;
+  return LBM_CDE_OK;
+}
+
+int lbm_cde_samples_written(lbm_cde_handle h, int64_t* rows) {
+  if (!h || !rows) return fail(h, LBM_CDE_EINVAL, "samples_written: null argument");
+  *rows = h->sample_rows;
+  return LBM_CDE_OK;
+}
+
+int lbm_cde_relaxation_matrix(lbm_cde_handle h, int32_t run, double* S_out) {
+  Run* r = get_run(h, run);
+  if (!r || !S_out) return fail(h, LBM_CDE_EINVAL, "relaxation_matrix: bad handle, run or pointer");
+  if (r->node_par) return fail(h, LBM_CDE_EINVAL, "relaxation_matrix: run has a per-node D field");
+  const int Q = r->Q;
+  for (int i = 0; i < Q * Q; ++i) S_out[i] = 0.0;
+  const int flux[3] = {3, 5, 7}, heatrow[3] = {4, 6, 8};
+  for (int k = 0; k < Q; ++k) S_out[k * Q + k] = r->s[k];
+  for (int a = 0; a < r->dim; ++a) S_out[heatrow[a] * Q + heatrow[a]] = r->heat[a];
+  for (int a = 0; a < r->dim; ++a)
+    for (int b = 0; b < r->dim; ++b) {
+      S_out[flux[a] * Q + flux[b]] = r->A[a][b];
+      S_out[flux[a] * Q + heatrow[b]] = (a == b ? r->A[a][b] / 2.0 - 1.0 : r->A[a][b] / 2.0) * r->heat[b];
+    }
+  return LBM_CDE_OK;
+}
+
+int lbm_cde_destroy(lbm_cde_handle h) {
+  if (!h) return LBM_CDE_EINVAL;
+  drop_graphs(h);
+  if (h->capture) (void)hipStreamDestroy(h->capture);
+  delete h;
+  return LBM_CDE_OK;
+}
+
+int lbm_cde_tune(lbm_cde_handle h, int32_t trials) {
+  if (!h) return fail_init(LBM_CDE_EINVAL, "tune: null handle");
+  if (trials < 1) return fail(h, LBM_CDE_EINVAL, "tune: trials must be >= 1");
+  for (auto& r : h->runs) {
+    const std::string key = tune_key(r);
+    Variant v;
+    if (cache_lookup(key, v) && find_step(r, v)) {
+      r.var = v;
+      continue;
+    }
+    double best = 1e300;
+    Variant best_v = r.var;
+    const int n = r.d.lattice == LBM_CDE_D3Q15 ? (int)(sizeof kSteps3 / sizeof kSteps3[0])
+                                               : (int)(sizeof kSteps / sizeof kSteps[0]);
+    for (int i = 0; i < n; ++i)
+      for (int xcd = 0; xcd < 2; ++xcd) {
+        Variant c;
+        if (r.d.lattice == LBM_CDE_D3Q15) c = Variant{kSteps3[i].bx, kSteps3[i].by, kSteps3[i].ny, kSteps3[i].nt, xcd != 0};
+        else c = Variant{kSteps[i].bx, kSteps[i].by, kSteps[i].ny, kSteps[i].nt, xcd != 0};
+        double ms = 0.0;
+        const int rc = time_variant(h, r, c, trials, &ms);
+        if (rc) return rc;
+        if (ms < best) {
+          best = ms;
+          best_v = c;
+        }
+      }
+    r.var = best_v;
+    cache_store(key, best_v, best);
+  }
+  drop_graphs(h);  // captured graphs hold the previous kernels
+  return LBM_CDE_OK;
+}
+
+int lbm_cde_get_variant(lbm_cde_handle h, int32_t run, int32_t* out) {
+  Run* r = get_run(h, run);
+  if (!r || !out) return fail(h, LBM_CDE_EINVAL, "get_variant: bad handle, run or pointer");
+  out[0] = r->var.bx;
+  out[1] = r->var.by;
+  out[2] = r->var.ny;
+  out[3] = r->var.nt ? 1 : 0;
+  out[4] = r->var.xcd ? 1 : 0;
+  return LBM_CDE_OK;
+}
+
+const char* lbm_cde_last_error(lbm_cde_handle h) { return h ? h->err.c_str() : g_init_error.c_str(); }
+
+}  // extern "C"

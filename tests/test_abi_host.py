@@ -1,0 +1,79 @@
+"""Host-side checks of the C ABI (no GPU needed).
+
+* The shared library loads and exports every function that
+  include/lbm_cde.h declares.
+* Descriptor validation (pure host logic) rejects invalid runs with the
+  documented status codes; workspace sizes follow the documented layout.
+"""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1404_2363_amd import _lib as L
+from paper_1404_2363_amd import workloads as W
+from paper_1404_2363_amd.solver import make_desc
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    text = open(os.path.join(ROOT, "include", "lbm_cde.h")).read()
+    return sorted(set(re.findall(r"^(?:int|const char\*)\s+(lbm_cde_\w+)\s*\(", text, re.M)))
+
+
+def test_library_exports_every_declared_function():
+    lib = L.load()
+    names = header_functions()
+    assert len(names) >= 10
+    for name in names:
+        assert hasattr(lib, name), name
+
+
+def _desc(**over):
+    wl = W.cellular(nx=64, ny=48, steps=1, n_hills=2, sigma=4.0)
+    d, keep = make_desc(wl, "fp64", device="cpu")
+    for k, v in over.items():
+        setattr(d, k, v)
+    return d, keep
+
+
+def test_workspace_bytes_layout():
+    d, keep = _desc()
+    nbytes = L.lbm_cde_workspace_bytes([d])
+    plane = 64 * 48 * 8
+    assert nbytes >= 2 * 9 * plane
+    assert nbytes % 256 == 0
+    d32, keep32 = make_desc(W.cellular(nx=64, ny=48, steps=1, n_hills=2, sigma=4.0), "fp32", device="cpu")
+    assert L.lbm_cde_workspace_bytes([d32]) < nbytes
+    assert L.lbm_cde_workspace_bytes([d, d32]) == nbytes + L.lbm_cde_workspace_bytes([d32])
+
+
+@pytest.mark.parametrize("field,value", [("nx", 0), ("ny", -3), ("nz", 2), ("lattice", 7), ("precision", 9),
+                                         ("u_kind", 5), ("heat_rule", 4)])
+def test_invalid_descriptors_rejected(field, value):
+    d, keep = _desc(**{field: value})
+    with pytest.raises(L.LbmCdeError) as e:
+        L.lbm_cde_workspace_bytes([d])
+    assert e.value.code == L.LBM_CDE_EINVAL
+    assert L.lbm_cde_last_error(None)
+
+
+def test_bad_boundary_and_missing_tables():
+    d, keep = _desc()
+    d.bc[1] = 3
+    with pytest.raises(L.LbmCdeError):
+        L.lbm_cde_workspace_bytes([d])
+    d, keep = _desc()
+    d.u_tables = None
+    with pytest.raises(L.LbmCdeError):
+        L.lbm_cde_workspace_bytes([d])
+
+
+def test_null_arguments():
+    lib = L.load()
+    assert lib.lbm_cde_workspace_bytes(None, 1, None) == L.LBM_CDE_EINVAL
+    assert lib.lbm_cde_step(None, 1) == L.LBM_CDE_EINVAL
+    assert lib.lbm_cde_destroy(None) == L.LBM_CDE_EINVAL

@@ -1,0 +1,256 @@
+"""GPU parity of the D2Q9 step against the FP64 CPU oracle (through the C ABI).
+
+Parity metric: max_x |phi_gpu - phi_oracle| / max_x |phi_oracle|, with
+tolerances 1e-12 (FP64 storage) and 1e-5 (FP32 shifted storage).  Cases:
+the full 128^2 Gaussian hill (1000 steps), ragged grids spanning several
+tiles with the cellular flow, every wall kind, every compiled tile shape
+(FP64 results must be bitwise equal across them), graph replay against
+single launches, the full 4096^2 cellular grid checked node by node on
+sampled nodes (the oracle computes each from its dependence cone), FP64
+reductions, and the documented error paths.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+
+from oracle import lbm as O
+from paper_1404_2363_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": 1e-12, "fp32": 1e-5}
+
+
+def _solver(*a, **k):
+    from paper_1404_2363_amd.solver import Solver
+    return Solver(*a, **k)
+
+
+def rel_err(gpu, ref):
+    gpu = np.asarray(gpu)
+    return float(np.abs(gpu - ref).max() / np.abs(ref).max())
+
+
+def gpu_phi(wl, precision, steps, **kw):
+    s = _solver(wl, precision, **kw)
+    s.step(steps)
+    out = s.phi().cpu().numpy()
+    s.close()
+    return out
+
+
+@pytest.fixture(scope="module")
+def hill_oracle():
+    wl = W.gaussian_hill()
+    phi, _ = O.run_workload(wl)
+    return wl, phi
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_gaussian_hill_full(hill_oracle, precision):
+    wl, ref = hill_oracle
+    print(f"case gaussian_hill 128^2 x 1000 {precision}", flush=True)
+    assert rel_err(gpu_phi(wl, precision, 1000), ref) <= TOL[precision]
+
+
+RAGGED = [(200, 136), (67, 45), (1, 9), (7, 1), (1, 1)]
+
+
+@pytest.mark.parametrize("shape", RAGGED)
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_cellular_ragged(shape, precision):
+    nx, ny = shape
+    steps = 120 if nx * ny > 100 else 40
+    wl = W.cellular(nx=nx, ny=ny, steps=steps, n_hills=6, sigma=max(2.0, min(nx, ny) / 8), U0=0.06)
+    print(f"case cellular {nx}x{ny} x {steps} {precision}", flush=True)
+    ref, _ = O.run_workload(wl)
+    assert rel_err(gpu_phi(wl, precision, steps), ref) <= TOL[precision]
+
+
+@pytest.mark.parametrize("walls", [("periodic", "bounce"), ("periodic", "specular"), ("bounce", "bounce"),
+                                   ("specular", "specular"), ("bounce", "specular"), ("specular", "periodic")])
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_walls(walls, precision):
+    wl = W.taylor_aris_channel(20, 12.0, 1.1, nx=150, steps=150)
+    wl.walls = walls
+    print(f"case channel 150x20 {walls} {precision}", flush=True)
+    ref, _ = O.run_workload(wl, heat_rule="lambda_min")
+    assert rel_err(gpu_phi(wl, precision, 150), ref) <= TOL[precision]
+
+
+def test_walls_full_rotated_tensor():
+    # walls on both axes with a full tensor and a 2D flow
+    wl = W.cellular(nx=70, ny=52, steps=100, n_hills=4, sigma=6.0, U0=0.05)
+    wl.walls = ("specular", "bounce")
+    ref, _ = O.run_workload(wl)
+    assert rel_err(gpu_phi(wl, "fp64", 100), ref) <= 1e-12
+
+
+TILES = ["64x4x1", "64x4x2", "128x2x1", "256x1x1", "256x1x2", "64x2x4"]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_tiles_agree_bitwise(precision, monkeypatch):
+    wl = W.cellular(nx=300, ny=77, steps=60, n_hills=5, sigma=8.0)
+    outs = []
+    for t in TILES:
+        monkeypatch.setenv("LBM_CDE_TILE", t)
+        outs.append(gpu_phi(wl, precision, 60))
+    for o in outs[1:]:
+        np.testing.assert_array_equal(o, outs[0])
+    ref, _ = O.run_workload(wl)
+    assert rel_err(outs[0], ref) <= TOL[precision]
+
+
+def test_graph_replay_equals_single_steps():
+    wl = W.cellular(nx=96, ny=80, steps=70, n_hills=4, sigma=6.0)
+    s1 = _solver(wl, "fp64")
+    s1.step(70)                      # two graph replays of 32 + 6 single launches
+    s2 = _solver(wl, "fp64")
+    for _ in range(70):
+        s2.step(1)
+    np.testing.assert_array_equal(s1.phi().cpu().numpy(), s2.phi().cpu().numpy())
+    assert s1.steps_done() == s2.steps_done() == 70
+
+
+def test_zero_steps_and_errors():
+    from paper_1404_2363_amd import _lib as L
+    wl = W.cellular(nx=32, ny=24, steps=1, n_hills=2, sigma=4.0)
+    s = _solver(wl, "fp64")
+    ref0 = s.phi().cpu().numpy()
+    s.step(0)
+    np.testing.assert_array_equal(s.phi().cpu().numpy(), ref0)
+    np.testing.assert_allclose(ref0, wl.phi0(), rtol=0, atol=1e-15)
+    with pytest.raises(L.LbmCdeError) as e:
+        s.step(-1)
+    assert e.value.code == L.LBM_CDE_EINVAL
+    out = s.phi()
+    with pytest.raises(L.LbmCdeError) as e:
+        L.lbm_cde_moments(s.h, 3, out.data_ptr())      # no run 3
+    assert e.value.code == L.LBM_CDE_EINVAL
+    with pytest.raises(L.LbmCdeError):
+        L.lbm_cde_reduce(s.h, 0, 9)                    # unknown reduction
+    s.close()
+    bad = W.cellular(nx=32, ny=24, steps=1, n_hills=2, sigma=4.0, D=np.array([[0.01, 0.02], [0.02, 0.01]]))
+    with pytest.raises(L.LbmCdeError) as e:
+        _solver(bad, "fp64")
+    assert e.value.code == L.LBM_CDE_ENOTSPD
+    fast = W.cellular(nx=32, ny=24, steps=1, n_hills=2, sigma=4.0, U0=0.6)
+    with pytest.raises(L.LbmCdeError) as e:
+        _solver(fast, "fp64")
+    assert e.value.code == L.LBM_CDE_EUNSTABLE
+
+
+def test_max_steps_budget():
+    wl = W.cellular(nx=40, ny=30, steps=50, n_hills=3, sigma=4.0)
+    s = _solver(wl, "fp64", max_steps=50)
+    s.step(80)
+    assert s.steps_done() == 50
+    ref, _ = O.run_workload(wl, steps=50)
+    assert rel_err(s.phi().cpu().numpy(), ref) <= 1e-12
+
+
+def test_relaxation_matrix_matches_oracle():
+    wl = W.cellular(nx=16, ny=16, steps=1, n_hills=1, sigma=3.0)
+    for heat in ("lambda_min", "paper", [0.9, 1.3]):
+        s = _solver(wl, "fp64", heat=heat)
+        S = s.relaxation_matrix()
+        prob = O.problem_for(wl, heat_rule=heat)
+        Sref = prob.S.copy()
+        Sref[0, 0] = S[0, 0]                 # s0 never acts (m0 = m0eq)
+        np.testing.assert_allclose(S, Sref, rtol=0, atol=1e-14)
+        s.close()
+
+
+def test_reductions_match_oracle():
+    wl = W.cellular(nx=150, ny=40, steps=90, n_hills=5, sigma=6.0)
+    for precision in ("fp64", "fp32"):
+        s = _solver(wl, precision)
+        s.step(90)
+        ref, _ = O.run_workload(wl)
+        m = s.mass()
+        assert abs(m - O.mass(ref)) <= TOL[precision] * O.mass(ref)
+        for x_ref in (0.0, 37.25, 149.5):
+            g = s.xmoments(x_ref=x_ref)
+            r = O.x_moments(ref, x_ref)
+            for a, b in zip(g, r):
+                assert abs(a - b) <= TOL[precision] * (abs(b) + abs(r[0]) * 150 ** 2), (x_ref, g, r)
+        assert s.nonfinite() == 0
+        s.close()
+
+
+def test_run_sampled_history():
+    import torch
+    wl = W.taylor_aris_channel(16, 10.0, 1.0, nx=128, steps=200)
+    m = wl.meta
+    s = _solver(wl, "fp64", heat=[1.0, 1.0], xref0=m["x0"], xref_drift=m["U_node_mean"])
+    hist = torch.zeros((10, 1, 3), dtype=torch.float64, device="cuda:0")
+    s.run_sampled(100, 20, hist)
+    assert s.samples_written() == 5
+    prob = O.problem_for(wl, heat_rule=[1.0, 1.0])
+    f = prob.equilibrium(wl.phi0())
+    h = hist.cpu().numpy()
+    for k in range(5):
+        f, _ = prob.run(f, 20)
+        t = 20 * (k + 1)
+        x_ref = (m["x0"] + m["U_node_mean"] * t) % 128
+        r = O.x_moments(O.phi_of(f), x_ref)
+        np.testing.assert_allclose(h[k, 0], r, rtol=1e-11, atol=1e-11 * r[0] * 64 ** 2)
+
+
+# ---- full-size cellular grid, node by node ------------------------------------
+
+@pytest.fixture(scope="module")
+def cellular_full():
+    return W.cellular()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_full_size_sampled_nodes(cellular_full, precision):
+    wl = cellular_full
+    steps = 40
+    print(f"case cellular 4096^2 x {steps} {precision} (bench launch shape)", flush=True)
+    s = _solver(wl, precision)
+    s.step(steps)
+    phi = s.phi().cpu().numpy()
+    mass0 = O.mass(wl.phi0())
+    assert abs(s.mass() - mass0) <= TOL[precision] * mass0
+    s.close()
+    rng = np.random.default_rng(7)
+    pts = [(0, 0), (4095, 4095), (4095, 0), (2048, 17)] + [tuple(p) for p in rng.integers(0, 4096, (8, 2))]
+    scale = np.abs(wl.phi0()).max()
+    for cx, cy in pts:
+        idx = W.patch_index(wl, (cx, cy), steps + 1)
+        ref, _ = O.run_workload(wl, steps=steps, idx=idx)
+        c = steps + 1
+        assert abs(phi[cy, cx] - ref[c, c]) <= TOL[precision] * scale, (cx, cy, phi[cy, cx], ref[c, c])
+
+
+def test_autotuner_keeps_state_and_results(tmp_path, monkeypatch):
+    """Tuning times launches that read the current state and overwrite only
+    the other buffer: the state, and every later result, are unchanged."""
+    monkeypatch.setenv("LBM_CDE_TUNE_CACHE", str(tmp_path / "tune.txt"))
+    wl = W.cellular(nx=256, ny=96, steps=40, n_hills=4, sigma=8.0)
+    for precision in ("fp64", "fp32"):
+        s1 = _solver(wl, precision)
+        s1.step(17)
+        before = s1.phi().cpu().numpy()
+        s1.tune(3)
+        np.testing.assert_array_equal(s1.phi().cpu().numpy(), before)
+        v = s1.variant()
+        assert v["block"][0] * v["block"][1] <= 1024 and v["rows_per_thread"] >= 1
+        s1.step(23)
+        s2 = _solver(wl, precision)
+        s2.step(40)
+        np.testing.assert_array_equal(s1.phi().cpu().numpy(), s2.phi().cpu().numpy())
+        s1.close()
+        s2.close()
+    lines = (tmp_path / "tune.txt").read_text().splitlines()
+    assert len(lines) == 2 and lines[0].split()[0].endswith(":d2q9:fp64:256x96x1:000")
+    # a cached result is reused without timing
+    s3 = _solver(wl, "fp64")
+    s3.tune(3)
+    assert len((tmp_path / "tune.txt").read_text().splitlines()) == 2
+    s3.close()
