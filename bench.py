@@ -1,12 +1,15 @@
 """Throughput of the fused collide-and-stream step on one MI355X.
 
-Workload (headline): D2Q9 modified MRT on the 4096^2 periodic cellular-flow
-grid (rotated anisotropic D, 64 Gaussian hills), populations in FP32
-shifted storage.  One step = one collide-and-stream pass over all nodes.
-The line also carries the plain FP64 step on the same grid, the roofline of
-the dominant kernel and the FP64 CPU oracle timed on the host.
+Headline workload: D2Q9 modified MRT on the 4096^2 periodic cellular-flow
+grid (rotated anisotropic D, 64 Gaussian hills), populations in FP32 shifted
+storage.  One step = one collide-and-stream pass over all nodes; `value` is
+million lattice updates per second with the populations resident in HBM.
+The same line carries the plain FP64 step on that grid, the D3Q15 256^3 step
+in FP64 and FP32, the roofline of the dominant kernel and the FP64 CPU
+oracle timed on the host cores.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--only d2q9_fp32]
+                       [--no-cpu] [--copy-probe]
 """
 import argparse
 import json
@@ -17,9 +20,15 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E peak
+# algorithmic bytes per lattice update: Q populations read + Q written
 BYTES_PER_LU = {("d2q9", "fp64"): 144, ("d2q9", "fp32"): 72, ("d2q9", "fp16"): 44,
                 ("d3q15", "fp64"): 240, ("d3q15", "fp32"): 120}
+COPY_PROBE_BYTES = 1 << 30     # bytes read (and written) by one calibration copy
+
+
+def log(msg):
+    print(f"bench: {msg}", file=sys.stderr, flush=True)
 
 
 def time_steps(solver, steps, warmup):
@@ -28,49 +37,62 @@ def time_steps(solver, steps, warmup):
     torch.cuda.synchronize()
     start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
-    start.record()
+    start.record()                 # the library launches on torch's current stream
     solver.step(steps)
     stop.record()
     torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    return start.elapsed_time(stop) / 1e3, wall
+    return start.elapsed_time(stop) / 1e3, time.perf_counter() - t0
 
 
-def gpu_variant(wl, precision, steps, warmup):
+def gpu_variant(wl, precision, steps, warmup, tune=True):
     from paper_1404_2363_amd.solver import Solver
     s = Solver(wl, precision)
+    if tune:
+        s.tune(10)
     ev, wall = time_steps(s, steps, warmup)
     nonfinite = s.nonfinite()
+    var = s.variant()
     s.close()
-    nodes = wl.nodes
     t_step = ev / steps
     bpl = BYTES_PER_LU[(wl.lattice, precision)]
-    return {"precision": precision, "steps": steps, "ms_per_step": t_step * 1e3,
-            "mlups": nodes / t_step / 1e6, "achieved_gbs": nodes * bpl / t_step / 1e9,
-            "bytes_per_lu": bpl, "hbm_frac": nodes * bpl / t_step / 1e9 / HBM_PEAK_GBS,
-            "wall_s": wall, "nonfinite": nonfinite}
+    gbs = wl.nodes * bpl / t_step / 1e9
+    return {"precision": precision, "nodes": wl.nodes, "steps": steps, "ms_per_step": t_step * 1e3,
+            "mlups": wl.nodes / t_step / 1e6, "achieved_gbs": gbs, "bytes_per_lu": bpl,
+            "hbm_frac": gbs / HBM_PEAK_GBS, "wall_s": wall, "nonfinite": nonfinite, "launch": var}
+
+
+def copy_probe():
+    """A plain device copy of known size, for calibrating HBM byte counters."""
+    import torch
+    n = COPY_PROBE_BYTES // 4
+    x = torch.ones(n, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    del x, y
+    torch.cuda.empty_cache()
 
 
 def cpu_baseline(wl, steps=2):
-    """The FP64 oracle as it stands, one BLAS thread, on the same grid."""
-    import numpy as np
+    """The FP64 oracle as it stands, with one BLAS thread, on the same grid."""
     from oracle import lbm as O
     try:
         from threadpoolctl import threadpool_limits
-        limiter = threadpool_limits(1)
+        ctx = threadpool_limits(1)
     except Exception:
-        limiter = None
+        ctx = None
     prob = O.problem_for(wl)
     f = prob.equilibrium(wl.phi0())
     t0 = time.perf_counter()
     for _ in range(steps):
         f = prob.step(f)
     dt = time.perf_counter() - t0
-    if limiter is not None:
-        limiter.unregister() if hasattr(limiter, "unregister") else None
+    if ctx is not None:
+        ctx.restore_original_limits()
     return {"value": wl.nodes * steps / dt / 1e6, "unit": "MLUPS", "cores": 1, "kind": "oracle",
-            "sample": f"{steps} FP64 oracle steps of the full {wl.shape[0]}x{wl.shape[1]} grid "
-                      f"({dt:.1f} s), numpy with one BLAS thread"}
+            "sample": f"{steps} FP64 oracle steps (numpy, one BLAS thread) of the full "
+                      f"{wl.shape[0]}x{wl.shape[1]} D2Q9 grid, {dt:.1f} s"}
 
 
 def main():
@@ -78,25 +100,44 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=400)
     ap.add_argument("--warmup", type=int, default=40)
+    ap.add_argument("--only", default="")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-tune", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path (use --gpus 1)", file=sys.stderr)
+        print("bench.py measures one GPU: this build has no multi-GPU path (run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
     import torch
-    from paper_1404_2363_amd import workloads as W
     from paper_1404_2363_amd import _lib
+    from paper_1404_2363_amd import workloads as W
     _lib.load()
     torch.cuda.init()
-    wl = W.cellular()
-    print(f"bench: D2Q9 cellular {wl.shape} fp32, {args.steps} steps", file=sys.stderr, flush=True)
-    main_v = gpu_variant(wl, "fp32", args.steps, args.warmup)
-    print(f"bench: fp32 {main_v['mlups']:.0f} MLUPS", file=sys.stderr, flush=True)
-    fp64_v = gpu_variant(wl, "fp64", max(args.steps // 2, 1), max(args.warmup // 2, 1))
-    print(f"bench: fp64 {fp64_v['mlups']:.0f} MLUPS", file=sys.stderr, flush=True)
-    cpu = None if args.no_cpu else cpu_baseline(wl)
+    if args.copy_probe:
+        copy_probe()
+    tune = not args.no_tune
+    wl2 = W.cellular()
+    out = {}
+    plan = [("d2q9_4096_fp32", wl2, "fp32", args.steps, args.warmup)]
+    if not args.only:
+        wl3 = W.sine3d()
+        plan += [("d2q9_4096_fp64", wl2, "fp64", max(args.steps // 2, 1), max(args.warmup // 2, 1)),
+                 ("d3q15_256_fp32", wl3, "fp32", max(args.steps // 4, 1), max(args.warmup // 4, 1)),
+                 ("d3q15_256_fp64", wl3, "fp64", max(args.steps // 8, 1), max(args.warmup // 8, 1))]
+    for name, wl, prec, k, w in plan:
+        if args.only and name != args.only:
+            continue
+        log(f"{name}: {k} steps")
+        out[name] = gpu_variant(wl, prec, k, w, tune)
+        log(f"{name}: {out[name]['mlups']:.0f} MLUPS, {out[name]['achieved_gbs']:.0f} GB/s")
+    main_v = out["d2q9_4096_fp32"]
+    if "d2q9_4096_fp64" in out:
+        out["speedup_fp32_over_fp64_d2q9"] = main_v["mlups"] / out["d2q9_4096_fp64"]["mlups"]
+    if "d3q15_256_fp64" in out:
+        out["speedup_fp32_over_fp64_d3q15"] = out["d3q15_256_fp32"]["mlups"] / out["d3q15_256_fp64"]["mlups"]
+    cpu = None if args.no_cpu else cpu_baseline(wl2)
     line = {
-        "metric": "MLUPS (D2Q9 4096^2, FP32 shifted storage)",
+        "metric": "MLUPS, D2Q9 4096^2 modified MRT step, FP32 shifted storage",
         "value": main_v["mlups"],
         "unit": "MLUPS",
         "n_gpus": 1,
@@ -109,13 +150,12 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": "D2Q9 modified MRT, 4096x4096 periodic, cellular u (U0=0.05), D eigenvalues "
-                               "0.01/0.1 rotated 30 deg, 64 Gaussian hills sigma=32",
-                   "storage": "fp32 shifted", "nodes": wl.nodes},
+                               "0.01/0.1 rotated 30 deg, 64 Gaussian hills sigma=32, FP32 shifted storage",
+                   "nodes": wl2.nodes},
         "roofline": {"bound": "hbm", "achieved": main_v["achieved_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": main_v["hbm_frac"], "traffic": None,
-                     "kernel": "k_step_d2q9<float>", "bytes_per_lu": 72},
-        "variants": {"d2q9_4096_fp64": fp64_v, "d2q9_4096_fp32": main_v,
-                     "speedup_fp32_over_fp64": main_v["mlups"] / fp64_v["mlups"]},
+                     "frac": main_v["hbm_frac"], "traffic": None, "kernel": "k_step_d2q9<float>",
+                     "bytes_per_launch": 72 * wl2.nodes},
+        "variants": out,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

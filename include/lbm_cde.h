@@ -194,7 +194,9 @@ int lbm_cde_relaxation_matrix(lbm_cde_handle h, int32_t run, double* S_out);
 int lbm_cde_tune(lbm_cde_handle h, int32_t trials);
 
 /* The launch variant of run `run`: out[0..4] = block x, block y, rows per
- * thread, streaming stores (0/1), XCD-contiguous block order (0/1). */
+ * thread, streaming stores (0/1), block order (0: hardware order, 1: each
+ * XCD takes a contiguous range of tiles, 2: tile rows interleaved over the
+ * 8 XCDs with all x-tiles of a row on one XCD). */
 int lbm_cde_get_variant(lbm_cde_handle h, int32_t run, int32_t* out);
 
 /* Release the handle (host memory only; the workspace stays the caller's). */

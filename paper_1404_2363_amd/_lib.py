@@ -171,7 +171,7 @@ def lbm_cde_get_variant(h: int, run: int):
     out = (ctypes.c_int32 * 5)()
     _check(load().lbm_cde_get_variant(h, run, out), "lbm_cde_get_variant", h)
     return {"block": (out[0], out[1]), "rows_per_thread": out[2], "nt_stores": bool(out[3]),
-            "xcd_remap": bool(out[4])}
+            "block_order": int(out[4])}
 
 
 def lbm_cde_destroy(h: int) -> None:

@@ -130,6 +130,75 @@ __global__ __launch_bounds__(RED_THREADS) void k_reduce_final(const double* __re
   if (threadIdx.x < 4) out[threadIdx.x] = sh[threadIdx.x][0];
 }
 
+// Step count of run `a` at global step t (a run stops at its budget).
+LBM_FORCEINLINE int64_t run_steps(const RunArgs& a, int64_t t) {
+  return (a.max_steps >= 0 && t > a.max_steps) ? a.max_steps : t;
+}
+
+// Batched x-moments, pass 1: block (b, r) reduces part of run r (S0, S1, S2
+// about x_ref(t_r) = xref0 + xref_drift t_r of that run) into partial[r][b].
+template <typename R>
+__global__ __launch_bounds__(RED_THREADS) void k_batch_xmom_partial(const RunArgs* __restrict__ runs, int Q,
+                                                                   const int64_t* __restrict__ clock,
+                                                                   double* __restrict__ partial) {
+  __shared__ double sh[3][RED_THREADS];
+  const RunArgs& a = runs[blockIdx.y];
+  const int64_t tr = run_steps(a, clock[0]);
+  const R* src = (const R*)((tr & 1) ? a.dst : a.src);
+  const double nxd = (double)a.nx;
+  double x_ref = a.xref0 + a.xref_drift * (double)tr;
+  x_ref -= nxd * floor(x_ref / nxd);
+  const int64_t N = a.nx * a.ny * a.nz;
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+  for (int64_t node = (int64_t)blockIdx.x * RED_THREADS + threadIdx.x; node < N;
+       node += (int64_t)gridDim.x * RED_THREADS) {
+    double phi = 0.0;
+    for (int i = 0; i < Q; ++i) phi += (double)src[i * a.plane + node];
+    phi += a.phi_ref;
+    double d = (double)(node % a.nx) - x_ref;
+    d -= nxd * floor(d / nxd + 0.5);
+    s0 += phi;
+    s1 += d * phi;
+    s2 += d * d * phi;
+  }
+  sh[0][threadIdx.x] = s0;
+  sh[1][threadIdx.x] = s1;
+  sh[2][threadIdx.x] = s2;
+  __syncthreads();
+  for (int w = RED_THREADS / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w)
+      for (int k = 0; k < 3; ++k) sh[k][threadIdx.x] += sh[k][threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x < 3) partial[((int64_t)blockIdx.y * gridDim.x + blockIdx.x) * 3 + threadIdx.x] = sh[threadIdx.x][0];
+}
+
+// Pass 2: block r adds the nb partials of run r into hist[row][r][0..2],
+// row = clock[1].
+__global__ __launch_bounds__(RED_THREADS) void k_batch_xmom_final(const double* __restrict__ partial, int nb,
+                                                                 int nruns, const int64_t* __restrict__ clock,
+                                                                 double* __restrict__ hist) {
+  __shared__ double sh[3][RED_THREADS];
+  const int r = blockIdx.x;
+  for (int k = 0; k < 3; ++k) {
+    double s = 0.0;
+    for (int b = threadIdx.x; b < nb; b += RED_THREADS) s += partial[((int64_t)r * nb + b) * 3 + k];
+    sh[k][threadIdx.x] = s;
+  }
+  __syncthreads();
+  for (int w = RED_THREADS / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w)
+      for (int k = 0; k < 3; ++k) sh[k][threadIdx.x] += sh[k][threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x < 3) hist[(clock[1] * nruns + r) * 3 + threadIdx.x] = sh[threadIdx.x][0];
+}
+
+// Advance the device step clock (clock[0]: steps, clock[1]: history rows).
+__global__ void k_tick(int64_t* __restrict__ clock, int which) {
+  if (threadIdx.x == 0) clock[which] += 1;
+}
+
 // Copy of a device FP64 array into storage precision R.
 template <typename R>
 __global__ __launch_bounds__(256) void k_convert(const double* __restrict__ in, R* __restrict__ out, int64_t n) {

@@ -36,8 +36,10 @@ struct RunArgs {
   double s[15];             // s[k] by moment index (flux-row entries unused)
   double A[3][3];           // flux block s_ab
   double heat[3];           // s4, s6, s8
-  int32_t xcd_remap;        // map block ids so each XCD works on a contiguous band
+  int32_t xcd_remap;        // block order (see tile_of_block)
   int32_t active;           // 0: run has used its step budget
+  int64_t max_steps;        // step budget (< 0: unlimited), used by batched launches
+  double xref0, xref_drift; // sampled x-moments: x_ref(t) = xref0 + xref_drift * t
 };
 
 // Block id remapping for the 8 XCDs of MI355X: consecutive hardware block ids
@@ -48,6 +50,22 @@ LBM_FORCEINLINE int64_t xcd_tile(int64_t b, int64_t nb) {
   const int64_t xcd = b % nx, local = b / nx;
   const int64_t per = nb / nx, rem = nb % nx;
   return xcd * per + (xcd < rem ? xcd : rem) + local;
+}
+
+// Row-interleaved order: tile row r goes to XCD r mod 8 with all its x-tiles,
+// so the cache lines that x-neighbouring tiles share (the x-shifted
+// populations) are fetched into one L2.  Needs a multiple of 8 tile rows.
+LBM_FORCEINLINE int64_t xcd_rows(int64_t b, int64_t ntx) {
+  const int64_t xcd = b % 8, local = b / 8;
+  const int64_t tx = local % ntx, group = local / ntx;
+  return (group * 8 + xcd) * ntx + tx;
+}
+
+// Block order: 0 = hardware order, 1 = XCD-contiguous ranges, 2 = row-interleaved.
+LBM_FORCEINLINE int64_t tile_of_block(int64_t b, int64_t nb, int64_t ntx, int mode) {
+  if (mode == 1) return xcd_tile(b, nb);
+  if (mode == 2) return xcd_rows(b, ntx);
+  return b;
 }
 
 template <typename R>

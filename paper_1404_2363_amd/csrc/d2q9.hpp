@@ -199,15 +199,11 @@ LBM_FORCEINLINE int64_t pull_index_d2q9(const RunArgs& a, int64_t x, int64_t y) 
   return (int64_t)pop_of_d2q9(vx, vy) * a.plane + sy * a.nx + sx;
 }
 
-// One pull step over a tile of BX x (BY*NY) nodes per block.  Thread (tx, ty)
-// owns column x and rows ty, ty + BY, ... of the tile.  All loads of a thread
-// are issued before its collisions.
+// One pull step over a tile of BX x (BY*NY) nodes.  Thread (tx, ty) owns
+// column x and rows ty, ty + BY, ... of the tile.  All loads of a thread are
+// issued before its collisions.
 template <typename R, int BX, int BY, int NY, bool WALLS, bool NT>
-__global__ __launch_bounds__(BX * BY) void k_step_d2q9(const RunArgs a) {
-  const int64_t ntx = (a.nx + BX - 1) / BX;
-  int64_t b = blockIdx.x;
-  if (a.xcd_remap) b = xcd_tile(b, gridDim.x);
-  const int64_t tile_x = b % ntx, tile_y = b / ntx;
+LBM_FORCEINLINE void tile_d2q9(const RunArgs& a, int64_t tile_x, int64_t tile_y) {
   const int64_t x = tile_x * BX + threadIdx.x;
   if (x >= a.nx) return;
   const R* __restrict__ src = (const R*)a.src;
@@ -257,6 +253,44 @@ __global__ __launch_bounds__(BX * BY) void k_step_d2q9(const RunArgs a) {
     else collide_d2q9<R>(f[k], ux, uy, phi_ref, rc);
 #pragma unroll
     for (int i = 0; i < 9; ++i) store_pop<R, NT>(dst + i * P + node, f[k][i]);
+  }
+}
+
+// One step of one run: one block per tile, in the chosen block order.
+template <typename R, int BX, int BY, int NY, bool WALLS, bool NT>
+__global__ __launch_bounds__(BX * BY) void k_step_d2q9(const RunArgs a) {
+  const int64_t ntx = (a.nx + BX - 1) / BX;
+  const int64_t b = tile_of_block(blockIdx.x, gridDim.x, ntx, a.xcd_remap);
+  tile_d2q9<R, BX, BY, NY, WALLS, NT>(a, b % ntx, b / ntx);
+}
+
+// One step of every active run of a batch, in one persistent launch: the
+// grid walks a flat list of BX-wide row tiles spanning all runs.  The
+// global step t is read from device memory (so a captured graph stays valid)
+// and fixes the buffer parity; a run whose budget max_steps <= t is skipped.
+template <typename R, int BX, bool NT>
+__global__ __launch_bounds__(BX) void k_batch_d2q9(const RunArgs* __restrict__ runs,
+                                                   const int64_t* __restrict__ tile_start, int nruns,
+                                                   const int64_t* __restrict__ clock) {
+  const int64_t t_global = clock[0];
+  const int64_t total = tile_start[nruns];
+  for (int64_t t = blockIdx.x; t < total; t += gridDim.x) {
+    int lo = 0, hi = nruns - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) / 2;
+      if (tile_start[mid] <= t) lo = mid;
+      else hi = mid - 1;
+    }
+    const RunArgs& ar = runs[lo];
+    if (ar.max_steps >= 0 && t_global >= ar.max_steps) continue;
+    RunArgs a = ar;
+    if (t_global & 1) {
+      a.src = ar.dst;
+      a.dst = const_cast<void*>(ar.src);
+    }
+    const int64_t local = t - tile_start[lo];
+    const int64_t ntx = (a.nx + BX - 1) / BX;
+    tile_d2q9<R, BX, 1, 1, true, NT>(a, local % ntx, local / ntx);
   }
 }
 

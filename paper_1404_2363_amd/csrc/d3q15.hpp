@@ -229,8 +229,7 @@ template <typename R, int BX, int BY, int NY, bool WALLS, bool NT>
 __global__ __launch_bounds__(BX * BY) void k_step_d3q15(const RunArgs a) {
   const int64_t ntx = (a.nx + BX - 1) / BX;
   const int64_t nty = (a.ny + BY * NY - 1) / (BY * NY);
-  int64_t b = blockIdx.x;
-  if (a.xcd_remap) b = xcd_tile(b, gridDim.x);
+  const int64_t b = tile_of_block(blockIdx.x, gridDim.x, ntx, a.xcd_remap);
   const int64_t tile_x = b % ntx;
   const int64_t rest = b / ntx;
   const int64_t tile_y = rest % nty, z = rest / nty;

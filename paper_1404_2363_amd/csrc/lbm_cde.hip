@@ -32,6 +32,8 @@ thread_local std::string g_init_error;
 
 constexpr size_t kAlign = 256;
 constexpr int kGraphSteps = 32;   // steps per captured graph (an even number)
+constexpr int kBatchTile = 256;   // row-tile width of the batched kernel
+constexpr int kBatchRedBlocks = 64;  // reduction blocks per run in batched sampling
 
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
@@ -48,7 +50,7 @@ size_t plane_skew() {
 struct Variant {
   int bx, by, ny;
   bool nt;    // non-temporal (streaming) stores
-  bool xcd;   // XCD-contiguous block remap
+  int xcd;    // block order: 0 hardware, 1 XCD-contiguous ranges, 2 rows interleaved over XCDs
 };
 
 struct Run {
@@ -85,9 +87,21 @@ struct lbm_cde {
   hipGraphExec_t graph[2] = {nullptr, nullptr};
   std::string err;
   int64_t sample_rows = 0;
+  // batched mode: one persistent launch steps every run (same lattice and precision)
+  bool batched = false;
+  RunArgs* dev_runs = nullptr;       // per-run arguments (parity 0) in the workspace
+  int64_t* dev_tiles = nullptr;      // tile_start[nruns + 1] of the flat tile list
+  int64_t* dev_clock = nullptr;      // [0] global steps, [1] history rows written
+  double* batch_partial = nullptr;   // reduction partials [nruns][kBatchRedBlocks][3]
+  int64_t global_steps = 0;
+  unsigned batch_grid = 0;
+  hipGraphExec_t batch_graph = nullptr;
+  hipGraphExec_t sample_graph = nullptr;
+  int64_t sample_every = 0;
+  double* sample_hist = nullptr;
   bool env_variant = false;   // LBM_CDE_TILE / _NT / _XCD override every run
-  Variant env{256, 1, 1, true, false};
-  Variant env3{128, 1, 1, true, false};
+  Variant env{256, 1, 1, true, 0};
+  Variant env3{128, 1, 1, true, 0};
 };
 
 namespace {
@@ -353,6 +367,11 @@ size_t layout(Run& r, char* base) {
   return off;
 }
 
+// Number of tile rows of a launch (y tiles times z planes).
+int64_t tile_rows(const Run& r, const Variant& v) {
+  return (r.d.ny + (int64_t)v.by * v.ny - 1) / ((int64_t)v.by * v.ny) * r.d.nz;
+}
+
 RunArgs make_args(const lbm_cde* h, const Run& r, int parity) {
   RunArgs a;
   std::memset(&a, 0, sizeof a);
@@ -373,9 +392,29 @@ RunArgs make_args(const lbm_cde* h, const Run& r, int parity) {
   for (int i = 0; i < 3; ++i)
     for (int j = 0; j < 3; ++j) a.A[i][j] = r.A[i][j];
   for (int i = 0; i < 3; ++i) a.heat[i] = r.heat[i];
-  a.xcd_remap = r.var.xcd ? 1 : 0;
+  a.max_steps = r.d.max_steps;
+  a.xref0 = r.d.xref0;
+  a.xref_drift = r.d.xref_drift;
+  a.xcd_remap = r.var.xcd;
+  if (a.xcd_remap == 2 && tile_rows(r, r.var) % 8 != 0) a.xcd_remap = 0;
   a.active = 1;
   return a;
+}
+
+// A batch of runs is stepped by one persistent launch when every run is D2Q9
+// in the same FP64 or FP32 precision.
+bool batch_eligible(const lbm_cde_run_desc* runs, int32_t nruns) {
+  if (nruns < 2) return false;
+  for (int i = 0; i < nruns; ++i)
+    if (runs[i].lattice != LBM_CDE_D2Q9 || runs[i].precision != runs[0].precision ||
+        runs[i].precision == LBM_CDE_FP16_SPLIT)
+      return false;
+  return true;
+}
+
+size_t batch_bytes(int32_t nruns) {
+  return align_up(sizeof(RunArgs) * nruns) + align_up(sizeof(int64_t) * (nruns + 1)) + align_up(2 * sizeof(int64_t)) +
+         align_up(sizeof(double) * 3 * kBatchRedBlocks * nruns);
 }
 
 // ---- kernel dispatch ------------------------------------------------------
@@ -384,8 +423,8 @@ RunArgs make_args(const lbm_cde* h, const Run& r, int parity) {
 // streaming stores and the hardware's round-robin XCD order were fastest
 // (the XCD-contiguous remap was 5-10% slower on 4096^2 D2Q9).
 Variant default_variant(int lattice, bool dbl) {
-  if (lattice == LBM_CDE_D3Q15) return Variant{128, 1, 1, true, false};
-  return dbl ? Variant{128, 2, 1, true, false} : Variant{256, 1, 1, true, false};
+  if (lattice == LBM_CDE_D3Q15) return Variant{128, 1, 1, true, 0};
+  return dbl ? Variant{128, 2, 1, true, 0} : Variant{256, 1, 1, true, 0};
 }
 
 using StepFn = void (*)(const RunArgs, hipStream_t);
@@ -485,6 +524,11 @@ void drop_graphs(lbm_cde* h) {
       (void)hipGraphExecDestroy(g);
       g = nullptr;
     }
+  for (hipGraphExec_t* g : {&h->batch_graph, &h->sample_graph})
+    if (*g) {
+      (void)hipGraphExecDestroy(*g);
+      *g = nullptr;
+    }
 }
 
 // Capture kGraphSteps steps starting from parity p on the private stream.
@@ -545,10 +589,10 @@ void parse_env(lbm_cde* h) {
   if (!t2 && !t3 && !nt && !xcd) return;
   h->env_variant = true;
   int bx, by, ny;
-  if (t2 && std::sscanf(t2, "%dx%dx%d", &bx, &by, &ny) == 3) h->env = Variant{bx, by, ny, false, false};
-  if (t3 && std::sscanf(t3, "%dx%dx%d", &bx, &by, &ny) == 3) h->env3 = Variant{bx, by, ny, false, false};
+  if (t2 && std::sscanf(t2, "%dx%dx%d", &bx, &by, &ny) == 3) h->env = Variant{bx, by, ny, false, 0};
+  if (t3 && std::sscanf(t3, "%dx%dx%d", &bx, &by, &ny) == 3) h->env3 = Variant{bx, by, ny, false, 0};
   h->env.nt = h->env3.nt = nt ? std::atoi(nt) != 0 : false;
-  h->env.xcd = h->env3.xcd = xcd ? std::atoi(xcd) != 0 : false;
+  h->env.xcd = h->env3.xcd = xcd ? std::atoi(xcd) : 0;
 }
 
 // Per-run set-up of lbm_cde_init (errors go to the thread's init error text).
@@ -617,7 +661,105 @@ int init_runs(lbm_cde* h, const lbm_cde_run_desc* runs, int32_t nruns, const dou
     HIP_TRY(nullptr, hipGetLastError());
     h->runs.push_back(r);
   }
+  if (batch_eligible(runs, nruns)) {
+    if (off + batch_bytes(nruns) > ws_bytes)
+      return fail_init(LBM_CDE_ENOSPC, "init: workspace of %zu bytes is too small", ws_bytes);
+    char* p = workspace + off;
+    h->dev_runs = (RunArgs*)p;
+    p += align_up(sizeof(RunArgs) * nruns);
+    h->dev_tiles = (int64_t*)p;
+    p += align_up(sizeof(int64_t) * (nruns + 1));
+    h->dev_clock = (int64_t*)p;
+    p += align_up(2 * sizeof(int64_t));
+    h->batch_partial = (double*)p;
+    std::vector<RunArgs> args;
+    std::vector<int64_t> tiles(1, 0);
+    for (auto& r : h->runs) {
+      args.push_back(make_args(h, r, 0));
+      tiles.push_back(tiles.back() + (r.d.nx + kBatchTile - 1) / kBatchTile * r.d.ny);
+    }
+    hipStream_t s = h->stream;
+    HIP_TRY(nullptr, hipMemcpyAsync(h->dev_runs, args.data(), sizeof(RunArgs) * nruns, hipMemcpyHostToDevice, s));
+    HIP_TRY(nullptr, hipMemcpyAsync(h->dev_tiles, tiles.data(), sizeof(int64_t) * (nruns + 1),
+                                    hipMemcpyHostToDevice, s));
+    HIP_TRY(nullptr, hipMemsetAsync(h->dev_clock, 0, 2 * sizeof(int64_t), s));
+    HIP_TRY(nullptr, hipStreamSynchronize(s));
+    int dev = 0, cus = 256;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+      cus = prop.multiProcessorCount;
+    h->batch_grid = (unsigned)std::min<int64_t>(tiles.back(), (int64_t)8 * cus);
+    h->batched = true;
+  }
   HIP_TRY(nullptr, hipStreamCreateWithFlags(&h->capture, hipStreamNonBlocking));
+  return LBM_CDE_OK;
+}
+
+// One batched step: the persistent kernel, then the clock tick.
+void launch_batch_step(lbm_cde* h, hipStream_t s) {
+  const int nr = (int)h->runs.size();
+  if (h->runs[0].dbl)
+    hipLaunchKernelGGL((k_batch_d2q9<double, kBatchTile, true>), dim3(h->batch_grid), dim3(kBatchTile), 0, s,
+                       h->dev_runs, h->dev_tiles, nr, h->dev_clock);
+  else
+    hipLaunchKernelGGL((k_batch_d2q9<float, kBatchTile, true>), dim3(h->batch_grid), dim3(kBatchTile), 0, s,
+                       h->dev_runs, h->dev_tiles, nr, h->dev_clock);
+  hipLaunchKernelGGL(k_tick, dim3(1), dim3(64), 0, s, h->dev_clock, 0);
+}
+
+// Sample the x-moments of every run into hist[row], then advance the row clock.
+void launch_batch_sample(lbm_cde* h, hipStream_t s, double* hist) {
+  const int nr = (int)h->runs.size();
+  const int Q = h->runs[0].Q;
+  if (h->runs[0].dbl)
+    hipLaunchKernelGGL(k_batch_xmom_partial<double>, dim3(kBatchRedBlocks, nr), dim3(RED_THREADS), 0, s,
+                       h->dev_runs, Q, h->dev_clock, h->batch_partial);
+  else
+    hipLaunchKernelGGL(k_batch_xmom_partial<float>, dim3(kBatchRedBlocks, nr), dim3(RED_THREADS), 0, s,
+                       h->dev_runs, Q, h->dev_clock, h->batch_partial);
+  hipLaunchKernelGGL(k_batch_xmom_final, dim3(nr), dim3(RED_THREADS), 0, s, h->batch_partial, kBatchRedBlocks, nr,
+                     h->dev_clock, hist);
+  hipLaunchKernelGGL(k_tick, dim3(1), dim3(64), 0, s, h->dev_clock, 1);
+}
+
+// Capture `steps` batched steps (and, with hist, one sample) as a graph.
+int capture_batch(lbm_cde* h, int64_t steps, double* hist, hipGraphExec_t* out) {
+  HIP_TRY(h, hipStreamBeginCapture(h->capture, hipStreamCaptureModeThreadLocal));
+  for (int64_t t = 0; t < steps; ++t) launch_batch_step(h, h->capture);
+  if (hist) launch_batch_sample(h, h->capture, hist);
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamEndCapture(h->capture, &g);
+  if (e != hipSuccess) return fail(h, LBM_CDE_EHIP, "graph capture: %s", hipGetErrorString(e));
+  e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e != hipSuccess) return fail(h, LBM_CDE_EHIP, "graph instantiate: %s", hipGetErrorString(e));
+  return LBM_CDE_OK;
+}
+
+void advance_host_clock(lbm_cde* h, int64_t n) {
+  h->global_steps += n;
+  for (auto& r : h->runs)
+    r.steps = (r.d.max_steps >= 0 && h->global_steps > r.d.max_steps) ? r.d.max_steps : h->global_steps;
+}
+
+int batch_step(lbm_cde* h, int64_t n) {
+  int64_t done = 0;
+  while (done < n) {
+    if (n - done >= kGraphSteps) {
+      if (!h->batch_graph) {
+        const int rc = capture_batch(h, kGraphSteps, nullptr, &h->batch_graph);
+        if (rc) return rc;
+      }
+      HIP_TRY(h, hipGraphLaunch(h->batch_graph, h->stream));
+      advance_host_clock(h, kGraphSteps);
+      done += kGraphSteps;
+    } else {
+      launch_batch_step(h, h->stream);
+      HIP_TRY(h, hipGetLastError());
+      advance_host_clock(h, 1);
+      done += 1;
+    }
+  }
   return LBM_CDE_OK;
 }
 
@@ -646,7 +788,7 @@ bool cache_lookup(const std::string& key, Variant& v) {
   bool found = false;
   while (std::fscanf(f, "%255s %d %d %d %d %d %lf", k, &bx, &by, &ny, &nt, &xcd, &ms) == 7)
     if (key == k) {
-      v = Variant{bx, by, ny, nt != 0, xcd != 0};
+      v = Variant{bx, by, ny, nt != 0, xcd};
       found = true;  // the last entry wins
     }
   std::fclose(f);
@@ -657,7 +799,7 @@ void cache_store(const std::string& key, const Variant& v, double ms) {
   const char* path = std::getenv("LBM_CDE_TUNE_CACHE");
   if (!path) return;
   if (FILE* f = std::fopen(path, "a")) {
-    std::fprintf(f, "%s %d %d %d %d %d %.6f\n", key.c_str(), v.bx, v.by, v.ny, (int)v.nt, (int)v.xcd, ms);
+    std::fprintf(f, "%s %d %d %d %d %d %.6f\n", key.c_str(), v.bx, v.by, v.ny, (int)v.nt, v.xcd, ms);
     std::fclose(f);
   }
 }
@@ -704,6 +846,7 @@ int lbm_cde_workspace_bytes(const lbm_cde_run_desc* runs, int32_t nruns, size_t*
     r.d = runs[i];
     total += layout(r, nullptr);
   }
+  if (batch_eligible(runs, nruns)) total += batch_bytes(nruns);
   *bytes = total;
   return LBM_CDE_OK;
 }
@@ -730,6 +873,7 @@ int lbm_cde_init(const lbm_cde_run_desc* runs, int32_t nruns, const double* cons
 int lbm_cde_step(lbm_cde_handle h, int64_t n) {
   if (!h) return fail_init(LBM_CDE_EINVAL, "step: null handle");
   if (n < 0) return fail(h, LBM_CDE_EINVAL, "step: negative step count %lld", (long long)n);
+  if (h->batched) return batch_step(h, n);
   int64_t done = 0;
   while (done < n) {
     // a captured graph is valid while every run takes all kGraphSteps steps
@@ -809,6 +953,22 @@ int lbm_cde_run_sampled(lbm_cde_handle h, int64_t n, int64_t every, double* hist
   if (h->sample_rows + rows > capacity)
     return fail(h, LBM_CDE_EINVAL, "run_sampled: history capacity %lld exceeded", (long long)capacity);
   const int64_t nr = (int64_t)h->runs.size();
+  if (h->batched) {
+    if (!h->sample_graph || h->sample_every != every || h->sample_hist != hist) {
+      if (h->sample_graph) (void)hipGraphExecDestroy(h->sample_graph);
+      h->sample_graph = nullptr;
+      const int rc = capture_batch(h, every, hist, &h->sample_graph);
+      if (rc) return rc;
+      h->sample_every = every;
+      h->sample_hist = hist;
+    }
+    for (int64_t k = 0; k < rows; ++k) {
+      HIP_TRY(h, hipGraphLaunch(h->sample_graph, h->stream));
+      advance_host_clock(h, every);
+    }
+    h->sample_rows += rows;
+    return LBM_CDE_OK;
+  }
   for (int64_t k = 0; k < rows; ++k) {
     int rc = lbm_cde_step(h, every);
     if (rc) return rc;
@@ -872,10 +1032,11 @@ int lbm_cde_tune(lbm_cde_handle h, int32_t trials) {
     const int n = r.d.lattice == LBM_CDE_D3Q15 ? (int)(sizeof kSteps3 / sizeof kSteps3[0])
                                                : (int)(sizeof kSteps / sizeof kSteps[0]);
     for (int i = 0; i < n; ++i)
-      for (int xcd = 0; xcd < 2; ++xcd) {
+      for (int xcd = 0; xcd < 3; ++xcd) {
         Variant c;
-        if (r.d.lattice == LBM_CDE_D3Q15) c = Variant{kSteps3[i].bx, kSteps3[i].by, kSteps3[i].ny, kSteps3[i].nt, xcd != 0};
-        else c = Variant{kSteps[i].bx, kSteps[i].by, kSteps[i].ny, kSteps[i].nt, xcd != 0};
+        if (r.d.lattice == LBM_CDE_D3Q15) c = Variant{kSteps3[i].bx, kSteps3[i].by, kSteps3[i].ny, kSteps3[i].nt, xcd};
+        else c = Variant{kSteps[i].bx, kSteps[i].by, kSteps[i].ny, kSteps[i].nt, xcd};
+        if (xcd == 2 && tile_rows(r, c) % 8 != 0) continue;
         double ms = 0.0;
         const int rc = time_variant(h, r, c, trials, &ms);
         if (rc) return rc;
@@ -898,7 +1059,7 @@ int lbm_cde_get_variant(lbm_cde_handle h, int32_t run, int32_t* out) {
   out[1] = r->var.by;
   out[2] = r->var.ny;
   out[3] = r->var.nt ? 1 : 0;
-  out[4] = r->var.xcd ? 1 : 0;
+  out[4] = r->var.xcd == 2 && tile_rows(*r, r->var) % 8 != 0 ? 0 : r->var.xcd;
   return LBM_CDE_OK;
 }
 

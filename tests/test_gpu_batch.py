@@ -1,0 +1,108 @@
+"""Batched persistent stepping of uneven runs (the Taylor-Aris ensemble form).
+
+Several channels of different length, gap, Peclet number, relaxation time
+and step budget are advanced by one persistent launch per step (replayed
+from captured graphs); each run is compared with the FP64 oracle run alone,
+at its own budget.  The in-graph x-moment history is compared with the
+oracle's moments at the sampled times.
+"""
+import numpy as np
+import pytest
+
+from oracle import lbm as O
+from paper_1404_2363_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": 1e-12, "fp32": 1e-5}
+
+CHANNELS = [  # (h, Pe, tau, nx, max_steps)
+    (12, 20.0, 0.8, 100, -1),
+    (20, 8.0, 1.4, 64, 47),
+    (7, 40.0, 0.6, 130, -1),
+    (16, 12.0, 1.1, 90, 70),
+    (9, 5.0, 1.9, 77, 33),
+]
+
+
+def channels(wall="specular"):
+    out = []
+    for h, Pe, tau, nx, budget in CHANNELS:
+        wl = W.taylor_aris_channel(h, Pe, tau, nx=nx, wall=wall, steps=100)
+        out.append((wl, budget, tau))
+    return out
+
+
+def solver_for(chs, precision):
+    from paper_1404_2363_amd.solver import Solver
+    wls = [c[0] for c in chs]
+    per_run = [{"max_steps": b, "heat": [1 / tau, 1 / tau], "xref0": wl.meta["x0"],
+                "xref_drift": wl.meta["U_node_mean"]} for wl, b, tau in chs]
+    return Solver(wls, precision, per_run=per_run)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("wall", ["specular", "bounce"])
+def test_batch_matches_oracle_per_run(precision, wall):
+    chs = channels(wall)
+    s = solver_for(chs, precision)
+    print(f"case batch of {len(chs)} channels {wall} {precision}", flush=True)
+    s.step(100)          # 3 graph replays of 32 steps + 4 single launches
+    for i, (wl, budget, tau) in enumerate(chs):
+        steps = 100 if budget < 0 else budget
+        assert s.steps_done(i) == steps
+        ref, _ = O.run_workload(wl, steps=steps, heat_rule=[1 / tau, 1 / tau])
+        err = float(np.abs(s.phi(i).cpu().numpy() - ref).max() / np.abs(ref).max())
+        assert err <= TOL[precision], (i, err)
+    s.close()
+
+
+def test_batch_graph_equals_single_steps():
+    chs = channels()
+    a = solver_for(chs, "fp64")
+    a.step(70)
+    b = solver_for(chs, "fp64")
+    for _ in range(70):
+        b.step(1)
+    for i in range(len(chs)):
+        np.testing.assert_array_equal(a.phi(i).cpu().numpy(), b.phi(i).cpu().numpy())
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_batch_sampled_history(precision):
+    import torch
+    chs = channels()
+    s = solver_for(chs, precision)
+    every, rows = 10, 6
+    hist = torch.zeros((rows + 2, len(chs), 3), dtype=torch.float64, device="cuda:0")
+    s.run_sampled(every * 3, every, hist)     # two calls continue one history
+    s.run_sampled(every * 3, every, hist)
+    assert s.samples_written() == rows
+    h = hist.cpu().numpy()
+    for i, (wl, budget, tau) in enumerate(chs):
+        m = wl.meta
+        prob = O.problem_for(wl, heat_rule=[1 / tau, 1 / tau])
+        f = prob.equilibrium(wl.phi0())
+        t = 0
+        for k in range(rows):
+            target = (k + 1) * every
+            if budget >= 0:
+                target = min(target, budget)
+            f, _ = prob.run(f, target - t)
+            t = target
+            x_ref = (m["x0"] + m["U_node_mean"] * t) % wl.shape[0]
+            ref = O.x_moments(O.phi_of(f), x_ref)
+            scale = ref[0] * wl.shape[0] ** 2
+            np.testing.assert_allclose(h[k, i], ref, rtol=0, atol=TOL[precision] * scale)
+    s.close()
+
+
+def test_mixed_precisions_fall_back_to_separate_launches():
+    from paper_1404_2363_amd.solver import Solver
+    chs = channels()[:2]
+    s = Solver([c[0] for c in chs], "fp64", per_run=[{"precision": "fp64"}, {"precision": "fp32"}])
+    s.step(40)
+    for i, (wl, _, _) in enumerate(chs):
+        ref, _ = O.run_workload(wl, steps=40)
+        err = float(np.abs(s.phi(i).cpu().numpy() - ref).max() / np.abs(ref).max())
+        assert err <= TOL["fp64" if i == 0 else "fp32"]
