@@ -199,6 +199,47 @@ int lbm_cde_tune(lbm_cde_handle h, int32_t trials);
  * 8 XCDs with all x-tiles of a row on one XCD). */
 int lbm_cde_get_variant(lbm_cde_handle h, int32_t run, int32_t* out);
 
+/* ---- state access (checkpoints) ------------------------------------------ */
+
+/* Bytes of one population state of run `run` (Q planes in storage precision,
+ * planes laid out as in the workspace). */
+int lbm_cde_state_bytes(lbm_cde_handle h, int32_t run, size_t* bytes);
+
+/* Copy the current state of run `run` to the device buffer dst
+ * (lbm_cde_state_bytes bytes).  Async on the stream. */
+int lbm_cde_get_state(lbm_cde_handle h, int32_t run, void* dst);
+
+/* Overwrite the state of run `run` with src and set its step count to
+ * `steps` (a restart from a checkpoint).  EUNSUPPORTED on batched handles
+ * (several D2Q9 runs of one precision), whose runs share one step clock. */
+int lbm_cde_set_state(lbm_cde_handle h, int32_t run, const void* src, int64_t steps);
+
+/* ---- discrete adjoint (D2Q9, FP64 or FP32 storage) ------------------------
+ * The step is linear in the populations, p_{t+1} = C(D) Pi p_t with Pi the
+ * streaming permutation (Eq. 5 with the wall rules) and C the collision of
+ * Eq. (10)-(14) with the modified S of Eq. (31).  For a loss L of the phi
+ * snapshots the adjoint recursion is lambda_t = Pi^T C^T lambda_{t+1} +
+ * dL/dp_t and dL/dD = sum_t lambda_{t+1}^T (dC/dD) Pi p_t; the library keeps
+ * mu_t = C^T lambda_{t+1} between reverse steps.  D enters S through
+ * A = (D/kappa + I/2)^-1 (Eq. 36).  The heat-flux rates must be EXPLICIT
+ * (fixed); otherwise EUNSUPPORTED.  All buffers are device memory. */
+
+/* Reverse sweep over one checkpoint segment of nsteps = K >= 1 steps,
+ * t0 .. t0+K.  ckpt: the state p_t0 (lbm_cde_get_state layout).  seg:
+ * scratch for K states.  inj: NULL, or a host array of K device pointers,
+ * inj[k] = dL/dphi at step t0+k+1 (FP64 per node, x fastest) or NULL.
+ * mu: in mu_{t0+K} (all zero for the last segment), out mu_{t0}; mu_tmp:
+ * scratch of the same size (both state-sized, storage precision).  grad:
+ * FP64 [3][ny][nx], components xx, yy, xy of dL/dD at every node (for a
+ * constant D their sum over nodes), accumulated (+=).  The run's own state
+ * is not touched. */
+int lbm_cde_adjoint_segment(lbm_cde_handle h, int32_t run, const void* ckpt, int32_t nsteps, void* seg,
+                            const double* const* inj, void* mu, void* mu_tmp, double* grad);
+
+/* dL/dphi0 (FP64 per node) from mu_0 and dL/dphi at t = 0 (inj0, may be
+ * NULL), through the equilibrium initialisation f(0) = f_eq(phi0, u). */
+int lbm_cde_adjoint_phi0(lbm_cde_handle h, int32_t run, const void* mu0, const double* inj0, double* dphi0);
+
 /* Release the handle (host memory only; the workspace stays the caller's). */
 int lbm_cde_destroy(lbm_cde_handle h);
 

@@ -505,14 +505,15 @@ def misfit(prob: Problem, phi0: np.ndarray, phi_obs: Sequence[np.ndarray], snap_
 
 
 def misfit_gradient(prob: Problem, phi0: np.ndarray, phi_obs: Sequence[np.ndarray], snap_every: int,
-                    ckpt_every: int = 0):
-    """(J, dJ/dD_field) by the discrete adjoint of the push step.
+                    ckpt_every: int = 0, return_dphi0: bool = False):
+    """(J, dJ/dD_field[, dJ/dphi0]) by the discrete adjoint of the push step.
 
     Forward: f_{t+1} = P C f_t.  Adjoint: lam_T = dJ/df_T,
     lam_t = C^T P^T lam_{t+1} + dJ/df_t, and
     dJ/dD = sum_t d<P^T lam_{t+1}, C(D) f_t>/dD.
     The forward states are stored (or recomputed from checkpoints every
-    ``ckpt_every`` steps when that is set)."""
+    ``ckpt_every`` steps when that is set).  dJ/dphi0 follows from lam_0
+    through f_0 = f_eq(phi0, u), which is linear in phi0."""
     if isinstance(prob.heat_rule, str):
         raise ValueError("the D-gradient holds for heat-flux rates that do not depend on D: "
                          "give explicit values")
@@ -543,6 +544,8 @@ def misfit_gradient(prob: Problem, phi0: np.ndarray, phi_obs: Sequence[np.ndarra
             lam_pre = prob.stream_T(lam)
             grad += prob.grad_D_step(lam_pre, states[t - 1 - seg_start])
             lam = prob.collide_T(lam_pre)
+    if return_dphi0:
+        return J, grad, (lam * prob.equilibrium(np.ones(prob.grid))).sum(axis=0)
     return J, grad
 
 

@@ -89,6 +89,11 @@ def load() -> ctypes.CDLL:
         "lbm_cde_relaxation_matrix": [P, I32, ctypes.POINTER(D)],
         "lbm_cde_tune": [P, I32],
         "lbm_cde_get_variant": [P, I32, ctypes.POINTER(I32)],
+        "lbm_cde_state_bytes": [P, I32, ctypes.POINTER(ctypes.c_size_t)],
+        "lbm_cde_get_state": [P, I32, P],
+        "lbm_cde_set_state": [P, I32, P, I64],
+        "lbm_cde_adjoint_segment": [P, I32, P, I32, P, ctypes.POINTER(ctypes.c_void_p), P, P, P],
+        "lbm_cde_adjoint_phi0": [P, I32, P, P, P],
         "lbm_cde_destroy": [P],
         "lbm_cde_last_error": [P],
     }
@@ -172,6 +177,35 @@ def lbm_cde_get_variant(h: int, run: int):
     _check(load().lbm_cde_get_variant(h, run, out), "lbm_cde_get_variant", h)
     return {"block": (out[0], out[1]), "rows_per_thread": out[2], "nt_stores": bool(out[3]),
             "block_order": int(out[4])}
+
+
+def lbm_cde_state_bytes(h: int, run: int) -> int:
+    out = ctypes.c_size_t(0)
+    _check(load().lbm_cde_state_bytes(h, run, ctypes.byref(out)), "lbm_cde_state_bytes", h)
+    return int(out.value)
+
+
+def lbm_cde_get_state(h: int, run: int, dst_ptr: int) -> None:
+    _check(load().lbm_cde_get_state(h, run, ctypes.c_void_p(dst_ptr)), "lbm_cde_get_state", h)
+
+
+def lbm_cde_set_state(h: int, run: int, src_ptr: int, steps: int) -> None:
+    _check(load().lbm_cde_set_state(h, run, ctypes.c_void_p(src_ptr), steps), "lbm_cde_set_state", h)
+
+
+def lbm_cde_adjoint_segment(h: int, run: int, ckpt_ptr: int, nsteps: int, seg_ptr: int, inj_ptrs,
+                            mu_ptr: int, mu_tmp_ptr: int, grad_ptr: int) -> None:
+    inj = None
+    if inj_ptrs is not None:
+        inj = (ctypes.c_void_p * len(inj_ptrs))(*[p if p else None for p in inj_ptrs])
+    _check(load().lbm_cde_adjoint_segment(h, run, ctypes.c_void_p(ckpt_ptr), nsteps, ctypes.c_void_p(seg_ptr), inj,
+                                          ctypes.c_void_p(mu_ptr), ctypes.c_void_p(mu_tmp_ptr),
+                                          ctypes.c_void_p(grad_ptr)), "lbm_cde_adjoint_segment", h)
+
+
+def lbm_cde_adjoint_phi0(h: int, run: int, mu0_ptr: int, inj0_ptr, dphi0_ptr: int) -> None:
+    _check(load().lbm_cde_adjoint_phi0(h, run, ctypes.c_void_p(mu0_ptr), ctypes.c_void_p(inj0_ptr),
+                                       ctypes.c_void_p(dphi0_ptr)), "lbm_cde_adjoint_phi0", h)
 
 
 def lbm_cde_destroy(h: int) -> None:

@@ -23,6 +23,7 @@
 #include "common.hpp"
 #include "d2q9.hpp"
 #include "d3q15.hpp"
+#include "adjoint_d2q9.hpp"
 
 using namespace lbm;
 
@@ -832,6 +833,32 @@ int time_variant(lbm_cde* h, Run& r, const Variant& v, int trials, double* ms) {
 
 }  // namespace
 
+namespace {
+
+int check_adjoint_run(lbm_cde* h, Run* r) {
+  if (!r) return fail(h, LBM_CDE_EINVAL, "adjoint: bad handle or run");
+  if (r->d.lattice != LBM_CDE_D2Q9 || r->d.precision == LBM_CDE_FP16_SPLIT)
+    return fail(h, LBM_CDE_EUNSUPPORTED, "adjoint: built for D2Q9 in FP64 or FP32 storage");
+  if (r->d.heat_rule != LBM_CDE_HEAT_EXPLICIT)
+    return fail(h, LBM_CDE_EUNSUPPORTED,
+                "adjoint: needs explicit heat-flux rates (the other rules make them depend on D)");
+  return LBM_CDE_OK;
+}
+
+template <typename R>
+void launch_adjoint(const Run& r, const RunArgs& a, const void* mu_in, const double* inj, void* mu_out,
+                    double* grad, double inv_kappa, hipStream_t s) {
+  const unsigned blocks = (unsigned)((r.nodes + 255) / 256);
+  if (r.walls)
+    hipLaunchKernelGGL((k_adjoint_d2q9<R, true>), dim3(blocks), dim3(256), 0, s, a, (const R*)mu_in, inj,
+                       (R*)mu_out, grad, inv_kappa);
+  else
+    hipLaunchKernelGGL((k_adjoint_d2q9<R, false>), dim3(blocks), dim3(256), 0, s, a, (const R*)mu_in, inj,
+                       (R*)mu_out, grad, inv_kappa);
+}
+
+}  // namespace
+
 // ---- C ABI ----------------------------------------------------------------
 
 extern "C" {
@@ -1060,6 +1087,93 @@ int lbm_cde_get_variant(lbm_cde_handle h, int32_t run, int32_t* out) {
   out[2] = r->var.ny;
   out[3] = r->var.nt ? 1 : 0;
   out[4] = r->var.xcd == 2 && tile_rows(*r, r->var) % 8 != 0 ? 0 : r->var.xcd;
+  return LBM_CDE_OK;
+}
+
+int lbm_cde_state_bytes(lbm_cde_handle h, int32_t run, size_t* bytes) {
+  Run* r = get_run(h, run);
+  if (!r || !bytes) return fail(h, LBM_CDE_EINVAL, "state_bytes: bad handle, run or pointer");
+  *bytes = (size_t)r->Q * (size_t)r->plane * r->elem;
+  return LBM_CDE_OK;
+}
+
+int lbm_cde_get_state(lbm_cde_handle h, int32_t run, void* dst) {
+  Run* r = get_run(h, run);
+  if (!r || !dst) return fail(h, LBM_CDE_EINVAL, "get_state: bad handle, run or pointer");
+  HIP_TRY(h, hipMemcpyAsync(dst, r->pop[r->steps & 1], (size_t)r->Q * r->plane * r->elem, hipMemcpyDeviceToDevice,
+                            h->stream));
+  return LBM_CDE_OK;
+}
+
+int lbm_cde_set_state(lbm_cde_handle h, int32_t run, const void* src, int64_t steps) {
+  Run* r = get_run(h, run);
+  if (!r || !src || steps < 0) return fail(h, LBM_CDE_EINVAL, "set_state: bad handle, run, pointer or step count");
+  if (h->batched) return fail(h, LBM_CDE_EUNSUPPORTED, "set_state: not available for batched handles");
+  if (r->d.max_steps >= 0 && steps > r->d.max_steps)
+    return fail(h, LBM_CDE_EINVAL, "set_state: step count beyond the run's budget");
+  r->steps = steps;
+  HIP_TRY(h, hipMemcpyAsync(r->pop[steps & 1], src, (size_t)r->Q * r->plane * r->elem, hipMemcpyDeviceToDevice,
+                            h->stream));
+  return LBM_CDE_OK;
+}
+
+int lbm_cde_adjoint_segment(lbm_cde_handle h, int32_t run, const void* ckpt, int32_t nsteps, void* seg,
+                            const double* const* inj, void* mu, void* mu_tmp, double* grad) {
+  Run* r = get_run(h, run);
+  int rc = check_adjoint_run(h, r);
+  if (rc) return rc;
+  if (!ckpt || nsteps < 1 || !seg || !mu || !mu_tmp || !grad)
+    return fail(h, LBM_CDE_EINVAL, "adjoint_segment: null buffer or nsteps < 1");
+  const size_t sb = (size_t)r->Q * r->plane * r->elem;
+  char* segc = (char*)seg;
+  // recompute the forward states p_t0 .. p_t0+K-1 of the segment
+  HIP_TRY(h, hipMemcpyAsync(segc, ckpt, sb, hipMemcpyDeviceToDevice, h->stream));
+  StepFn step = pick_step(h, *r);
+  for (int k = 1; k < nsteps; ++k) {
+    RunArgs a = make_args(h, *r, 0);
+    a.src = segc + (size_t)(k - 1) * sb;
+    a.dst = segc + (size_t)k * sb;
+    step(a, h->stream);
+  }
+  // reverse sweep: mu_{t+1} -> mu_t for t = t0+K-1 .. t0
+  void* cur = mu;
+  void* nxt = mu_tmp;
+  for (int k = nsteps - 1; k >= 0; --k) {
+    RunArgs a = make_args(h, *r, 0);
+    a.src = segc + (size_t)k * sb;
+    const double* injk = inj ? inj[k] : nullptr;
+    if (r->dbl) launch_adjoint<double>(*r, a, cur, injk, nxt, grad, 1.0 / r->kappa, h->stream);
+    else launch_adjoint<float>(*r, a, cur, injk, nxt, grad, 1.0 / r->kappa, h->stream);
+    std::swap(cur, nxt);
+  }
+  if (cur != mu) HIP_TRY(h, hipMemcpyAsync(mu, cur, sb, hipMemcpyDeviceToDevice, h->stream));
+  HIP_TRY(h, hipGetLastError());
+  return LBM_CDE_OK;
+}
+
+int lbm_cde_adjoint_phi0(lbm_cde_handle h, int32_t run, const void* mu0, const double* inj0, double* dphi0) {
+  Run* r = get_run(h, run);
+  int rc = check_adjoint_run(h, r);
+  if (rc) return rc;
+  if (!mu0 || !dphi0) return fail(h, LBM_CDE_EINVAL, "adjoint_phi0: null buffer");
+  const RunArgs a = make_args(h, *r, 0);
+  const unsigned blocks = (unsigned)((r->nodes + 255) / 256);
+  if (r->dbl) {
+    if (r->walls)
+      hipLaunchKernelGGL((k_adjoint_phi0_d2q9<double, true>), dim3(blocks), dim3(256), 0, h->stream, a,
+                         (const double*)mu0, inj0, dphi0);
+    else
+      hipLaunchKernelGGL((k_adjoint_phi0_d2q9<double, false>), dim3(blocks), dim3(256), 0, h->stream, a,
+                         (const double*)mu0, inj0, dphi0);
+  } else {
+    if (r->walls)
+      hipLaunchKernelGGL((k_adjoint_phi0_d2q9<float, true>), dim3(blocks), dim3(256), 0, h->stream, a,
+                         (const float*)mu0, inj0, dphi0);
+    else
+      hipLaunchKernelGGL((k_adjoint_phi0_d2q9<float, false>), dim3(blocks), dim3(256), 0, h->stream, a,
+                         (const float*)mu0, inj0, dphi0);
+  }
+  HIP_TRY(h, hipGetLastError());
   return LBM_CDE_OK;
 }
 

@@ -43,7 +43,10 @@ def make_desc(wl, precision: str = "fp64", device="cuda:0", heat="lambda_min", r
     for a, w in enumerate(wl.walls):
         d.bc[a] = WALLS[w]
     if wl.D_field is not None:
-        Df = torch.as_tensor(np.ascontiguousarray(wl.D_field), dtype=torch.float64, device=device)
+        if isinstance(wl.D_field, torch.Tensor):
+            Df = wl.D_field.detach().to(device=device, dtype=torch.float64).contiguous()
+        else:
+            Df = torch.as_tensor(np.ascontiguousarray(wl.D_field), dtype=torch.float64, device=device)
         keep.append(Df)
         d.D_field = Df.data_ptr()
     else:
@@ -81,7 +84,7 @@ class Solver:
     """
 
     def __init__(self, runs, precision: str = "fp64", device="cuda:0", per_run: Optional[Sequence[dict]] = None,
-                 **kw):
+                 phi0: Optional[Sequence[torch.Tensor]] = None, **kw):
         L.load()
         if not torch.cuda.is_available():
             raise RuntimeError("the HIP solver needs a GPU (torch.cuda.is_available() is False)")
@@ -96,7 +99,10 @@ class Solver:
             d, k = make_desc(wl, opts.pop("precision", precision), device=self.device, **opts)
             descs.append(d)
             keep += k
-            p = torch.as_tensor(np.ascontiguousarray(wl.phi0()), dtype=torch.float64, device=self.device)
+            if phi0 is not None:
+                p = phi0[i].detach().to(device=self.device, dtype=torch.float64).contiguous()
+            else:
+                p = torch.as_tensor(np.ascontiguousarray(wl.phi0()), dtype=torch.float64, device=self.device)
             phis.append(p)
         self.descs = descs
         self.ws_bytes = L.lbm_cde_workspace_bytes(descs)
@@ -140,6 +146,17 @@ class Solver:
 
     def samples_written(self) -> int:
         return L.lbm_cde_samples_written(self.h)
+
+    def state_bytes(self, run: int = 0) -> int:
+        return L.lbm_cde_state_bytes(self.h, run)
+
+    def get_state(self, run: int = 0) -> torch.Tensor:
+        out = torch.empty(self.state_bytes(run), dtype=torch.uint8, device=self.device)
+        L.lbm_cde_get_state(self.h, run, out.data_ptr())
+        return out
+
+    def set_state(self, state: torch.Tensor, steps: int, run: int = 0) -> None:
+        L.lbm_cde_set_state(self.h, run, state.data_ptr(), int(steps))
 
     def tune(self, trials: int = 20) -> None:
         L.lbm_cde_tune(self.h, int(trials))

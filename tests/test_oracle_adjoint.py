@@ -71,6 +71,18 @@ def test_gradient_matches_finite_differences(walls):
         assert abs(grad[c, y, x] - fd) <= 1e-6 * np.abs(grad).max(), (c, y, x, grad[c, y, x], fd)
 
 
+def test_phi0_gradient_matches_finite_differences():
+    make, dtrial, phi0, obs, snap_every = _misfit_setup(("periodic", "bounce"))
+    J, _, dphi0 = O.misfit_gradient(make(dtrial), phi0, obs, snap_every, return_dphi0=True)
+    eps = 1e-6
+    for (y, x) in [(3, 4), (6, 7), (0, 13), (11, 0)]:
+        pp, pm = phi0.copy(), phi0.copy()
+        pp[y, x] += eps
+        pm[y, x] -= eps
+        fd = (O.misfit(make(dtrial), pp, obs, snap_every) - O.misfit(make(dtrial), pm, obs, snap_every)) / (2 * eps)
+        assert abs(dphi0[y, x] - fd) <= 1e-6 * np.abs(dphi0).max(), (y, x, dphi0[y, x], fd)
+
+
 def test_checkpointed_gradient_equals_stored():
     make, dtrial, phi0, obs, snap_every = _misfit_setup()
     J1, g1 = O.misfit_gradient(make(dtrial), phi0, obs, snap_every)
