@@ -57,7 +57,8 @@ enum {
   LBM_CDE_EHIP = -4,        /* HIP runtime error; the runtime's message is kept      */
   LBM_CDE_ENONFINITE = -5,  /* a reduction met NaN or Inf in the state               */
   LBM_CDE_ENOSPC = -6,      /* workspace smaller than lbm_cde_workspace_bytes()       */
-  LBM_CDE_EUNSUPPORTED = -7 /* a valid combination this build does not provide        */
+  LBM_CDE_EUNSUPPORTED = -7, /* a valid combination this build does not provide       */
+  LBM_CDE_EOVERFLOW = -8     /* 16-bit storage saturated at least once (sticky)         */
 };
 
 /* ---- enumerations -------------------------------------------------------- */
@@ -72,8 +73,16 @@ enum { LBM_CDE_D2Q9 = 0, LBM_CDE_D3Q15 = 1 };
  *                 the model's equilibrium at rest (D2Q9: 5/9, 1/18; D3Q15:
  *                 8/15, 1/30).  The collision is done exactly on g.
  *   FP16_SPLIT    per node phi (float) and the non-equilibrium part
- *                 f_i - f_i^eq(phi, u) (half, times a power-of-two scale). */
-enum { LBM_CDE_FP64 = 0, LBM_CDE_FP32_SHIFTED = 1, LBM_CDE_FP16_SPLIT = 2 };
+ *                 f_i - f_i^eq(phi, u) of the populations (half, times a
+ *                 power-of-two scale).  D2Q9, constant D only.
+ *   FP16_SHIFTED  g_i = f_i - w_i phi_ref as half times a power-of-two scale
+ *                 (the literal 16-bit form; far less accurate than SPLIT).
+ * The 16-bit scale is fp16_scale, or (0) chosen at init as the power of two
+ * that puts the largest stored magnitude (the non-equilibrium part after the
+ * first step for SPLIT, the shifted equilibrium for SHIFTED) at about 1/256
+ * of the half range.  Values that would exceed the half range are
+ * saturated and make later reductions return LBM_CDE_EOVERFLOW. */
+enum { LBM_CDE_FP64 = 0, LBM_CDE_FP32_SHIFTED = 1, LBM_CDE_FP16_SPLIT = 2, LBM_CDE_FP16_SHIFTED = 3 };
 
 /* Boundary of one axis (both faces).  Walls sit halfway between the first
  * (last) node and its missing neighbour:
@@ -166,7 +175,8 @@ int lbm_cde_moments(lbm_cde_handle h, int32_t run, double* phi_out);
 
 /* FP64 reduction `kind` (LBM_CDE_RED_*) of run `run` into host memory out
  * (3 doubles).  x_ref is used by XMOMENTS only.  Waits for the stream.
- * Returns ENONFINITE (with out filled) when MASS or XMOMENTS met NaN/Inf. */
+ * Returns ENONFINITE (with out filled) when MASS or XMOMENTS met NaN/Inf, and
+ * EOVERFLOW (with out filled) when 16-bit storage of the run has saturated. */
 int lbm_cde_reduce(lbm_cde_handle h, int32_t run, int32_t kind, double x_ref, double* out);
 
 /* Advance n steps and, after every `every` steps, append the XMOMENTS

@@ -21,11 +21,12 @@ LBM_CDE_EHIP = -4
 LBM_CDE_ENONFINITE = -5
 LBM_CDE_ENOSPC = -6
 LBM_CDE_EUNSUPPORTED = -7
+LBM_CDE_EOVERFLOW = -8
 STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "ENOTSPD", -3: "EUNSTABLE", -4: "EHIP", -5: "ENONFINITE",
-                -6: "ENOSPC", -7: "EUNSUPPORTED"}
+                -6: "ENOSPC", -7: "EUNSUPPORTED", -8: "EOVERFLOW"}
 
 LBM_CDE_D2Q9, LBM_CDE_D3Q15 = 0, 1
-LBM_CDE_FP64, LBM_CDE_FP32_SHIFTED, LBM_CDE_FP16_SPLIT = 0, 1, 2
+LBM_CDE_FP64, LBM_CDE_FP32_SHIFTED, LBM_CDE_FP16_SPLIT, LBM_CDE_FP16_SHIFTED = 0, 1, 2, 3
 LBM_CDE_PERIODIC, LBM_CDE_BOUNCE_BACK, LBM_CDE_SPECULAR = 0, 1, 2
 LBM_CDE_U_CONST, LBM_CDE_U_SEPARABLE, LBM_CDE_U_FIELD = 0, 1, 2
 LBM_CDE_HEAT_LAMBDA_MIN, LBM_CDE_HEAT_PAPER, LBM_CDE_HEAT_EXPLICIT = 0, 1, 2

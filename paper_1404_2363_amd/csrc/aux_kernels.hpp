@@ -1,6 +1,8 @@
 // Initialisation, readout and FP64 reduction kernels (all lattices).
 #pragma once
 
+#include <hip/hip_fp16.h>
+
 #include "common.hpp"
 #include "d2q9.hpp"
 #include "d3q15.hpp"
@@ -56,39 +58,56 @@ __global__ __launch_bounds__(256) void k_init_d3q15(const RunArgs a, const doubl
   for (int i = 0; i < 15; ++i) dst[i * a.plane + node] = (R)f[i];
 }
 
+// A stored population value in FP64 (16-bit storage carries a scale).
+template <typename S>
+LBM_FORCEINLINE double ld_pop(const void* p, int64_t i, double inv) {
+  if constexpr (sizeof(S) == 2) return (double)__half2float(((const __half*)p)[i]) * inv;
+  else return (double)((const S*)p)[i];
+}
+
+// phi of one node and the number of non-finite stored values there.  Split
+// storage keeps phi itself; otherwise phi = sum_i f_i (+ phi_ref).
+template <typename S>
+LBM_FORCEINLINE double node_phi(const RunArgs& a, int Q, int64_t node, int& nonfinite) {
+  if (a.src_phi) {
+    const double phi = (double)((const float*)a.src_phi)[node];
+    nonfinite += !isfinite(phi);
+    for (int i = 0; i < Q; ++i) nonfinite += !isfinite(ld_pop<S>(a.src, i * a.plane + node, 1.0));
+    return phi;
+  }
+  double s = 0.0;
+  for (int i = 0; i < Q; ++i) {
+    const double v = ld_pop<S>(a.src, i * a.plane + node, a.fp16_inv_scale);
+    nonfinite += !isfinite(v);
+    s += v;
+  }
+  return s + a.phi_ref;
+}
+
 // phi = sum_i f_i (+ phi_ref for shifted storage), FP64.
-template <typename R>
+template <typename S>
 __global__ __launch_bounds__(256) void k_moments(const RunArgs a, int Q, double* __restrict__ phi) {
   const int64_t N = a.nx * a.ny * a.nz;
   const int64_t node = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (node >= N) return;
-  const R* src = (const R*)a.src;
-  double s = 0.0;
-  for (int i = 0; i < Q; ++i) s += (double)src[i * a.plane + node];
-  phi[node] = s + a.phi_ref;
+  int bad = 0;
+  phi[node] = node_phi<S>(a, Q, node, bad);
 }
 
 // Deterministic two-pass FP64 reduction.  Pass 1: each of RED_BLOCKS blocks
 // walks a fixed grid-stride set of nodes and tree-reduces 4 sums in LDS.
 // Pass 2: one block adds the partials in a fixed tree.
-template <typename R>
+template <typename S>
 __global__ __launch_bounds__(RED_THREADS) void k_reduce_partial(const RunArgs a, int Q, int kind, double x_ref,
                                                                double* __restrict__ partial) {
   __shared__ double sh[4][RED_THREADS];
   const int64_t N = a.nx * a.ny * a.nz;
-  const R* src = (const R*)a.src;
   double s0 = 0.0, s1 = 0.0, s2 = 0.0, bad = 0.0;
   const double nxd = (double)a.nx;
   for (int64_t node = (int64_t)blockIdx.x * RED_THREADS + threadIdx.x; node < N;
        node += (int64_t)gridDim.x * RED_THREADS) {
-    double phi = 0.0;
     int nonfinite = 0;
-    for (int i = 0; i < Q; ++i) {
-      const double v = (double)src[i * a.plane + node];
-      nonfinite += !isfinite(v);
-      phi += v;
-    }
-    phi += a.phi_ref;
+    const double phi = node_phi<S>(a, Q, node, nonfinite);
     bad += (double)nonfinite;
     if (kind == LBM_CDE_RED_XMOMENTS) {
       double d = (double)(node % a.nx) - x_ref;

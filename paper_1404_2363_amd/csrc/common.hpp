@@ -32,6 +32,7 @@ struct RunArgs {
   const void* node_par;     // per-node relaxation parameters (type R) or null
   double phi_ref;
   double fp16_scale, fp16_inv_scale;
+  void* fp16_flags;         // 16-bit storage: set to 1 when a value saturates
   // relaxation (constant D): diagonal rates and the flux block
   double s[15];             // s[k] by moment index (flux-row entries unused)
   double A[3][3];           // flux block s_ab

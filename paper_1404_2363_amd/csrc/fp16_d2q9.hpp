@@ -1,0 +1,294 @@
+// D2Q9 steps with 16-bit population storage (arithmetic in FP32).
+//
+// Split storage (the accurate form): per node phi (float) and the
+// non-equilibrium part of the post-collision populations,
+// h_i = half(2^k (p_i - f_eq_i(phi, u))).  The pull step rebuilds each
+// incoming population at its source node s as f_eq_j(phi(s), u(s)) + 2^-k h_j(s)
+// (j = i, or the population the wall rule takes), collides in FP32 and splits
+// the result again; 4 + 18 bytes are read and written per node.  The phi
+// plane of a tile and its one-node halo is staged through LDS, so each phi is
+// fetched from memory about (BY + 2) / BY times instead of nine.
+//
+// Literal storage: g_i = f_i - w_i phi_ref (as FP32 shifted storage) kept as
+// half(2^k g_i).
+//
+// MRT-A equilibrium in velocity space (Eq. 17 with alpha1 = -8, alpha2 = 8):
+//   f_eq_0 = 5 phi / 9, axis f_eq_i = phi (1/18 + e_i.u / 3),
+//   diagonal f_eq_i = phi (1/18 + e_i.u / 12).
+#pragma once
+
+#include <hip/hip_fp16.h>
+
+#include "common.hpp"
+#include "d2q9.hpp"
+
+namespace lbm {
+
+constexpr float kHalfMax = 65504.0f;
+
+LBM_FORCEINLINE float feq_d2q9(int i, float phi, float ux, float uy) {
+  if (i == 0) return phi * (5.0f / 9.0f);
+  const int ex = (i == 1 || i == 5 || i == 8) ? 1 : (i == 3 || i == 6 || i == 7) ? -1 : 0;
+  const int ey = (i == 2 || i == 5 || i == 6) ? 1 : (i == 4 || i == 7 || i == 8) ? -1 : 0;
+  const float eu = (float)ex * ux + (float)ey * uy;
+  return i <= 4 ? phi * (1.0f / 18.0f + eu * (1.0f / 3.0f)) : phi * (1.0f / 18.0f + eu * (1.0f / 12.0f));
+}
+
+// Scale, round and saturate to half; flags an out-of-range value.
+LBM_FORCEINLINE __half to_half(float v, float scale, bool& over) {
+  float s = v * scale;
+  if (!(fabsf(s) <= kHalfMax)) {
+    over = true;
+    s = s != s ? 0.0f : (s > 0.0f ? kHalfMax : -kHalfMax);
+  }
+  return __float2half_rn(s);
+}
+
+LBM_FORCEINLINE int64_t wrap_any(int64_t i, int64_t n) {
+  const int64_t r = i % n;
+  return r < 0 ? r + n : r;
+}
+
+// Source of population (EX, EY) at (x, y): population index, node, and the
+// offset (dx, dy) of the source node from (x, y) (for the LDS phi tile).
+template <int EX, int EY>
+LBM_FORCEINLINE void pull_source_d2q9(const RunArgs& a, int64_t x, int64_t y, int& pop, int64_t& sx, int64_t& sy,
+                                      int& dx, int& dy) {
+  sx = x - EX;
+  sy = y - EY;
+  dx = -EX;
+  dy = -EY;
+  bool cx = false, cy = false;
+  if (EX != 0) {
+    const bool out = sx < 0 || sx >= a.nx;
+    if (a.bc[0] == LBM_CDE_PERIODIC) sx = sx < 0 ? sx + a.nx : (sx >= a.nx ? sx - a.nx : sx);
+    else cx = out;
+  }
+  if (EY != 0) {
+    const bool out = sy < 0 || sy >= a.ny;
+    if (a.bc[1] == LBM_CDE_PERIODIC) sy = sy < 0 ? sy + a.ny : (sy >= a.ny ? sy - a.ny : sy);
+    else cy = out;
+  }
+  const bool bounce = (cx && a.bc[0] == LBM_CDE_BOUNCE_BACK) || (cy && a.bc[1] == LBM_CDE_BOUNCE_BACK);
+  int vx = EX, vy = EY;
+  if (bounce) {
+    vx = -EX;
+    vy = -EY;
+    sx = x;
+    sy = y;
+    dx = dy = 0;
+  } else {
+    if (cx) { vx = -EX; sx = x; dx = 0; }
+    if (cy) { vy = -EY; sy = y; dy = 0; }
+  }
+  pop = pop_of_d2q9(vx, vy);
+}
+
+template <int BX, int BY, bool WALLS>
+__global__ __launch_bounds__(BX * BY) void k_step_d2q9_split(const RunArgs a, unsigned* __restrict__ overflow) {
+  __shared__ float sphi[BY + 2][BX + 2];
+  const int64_t ntx = (a.nx + BX - 1) / BX;
+  const int64_t b = tile_of_block(blockIdx.x, gridDim.x, ntx, a.xcd_remap);
+  const int64_t tx0 = (b % ntx) * BX, ty0 = (b / ntx) * BY;
+  const float* __restrict__ phis = (const float*)a.src_phi;
+  const int tid = threadIdx.y * BX + threadIdx.x;
+  for (int k = tid; k < (BX + 2) * (BY + 2); k += BX * BY) {
+    const int lx = k % (BX + 2), ly = k / (BX + 2);
+    int64_t gx = tx0 + lx - 1, gy = ty0 + ly - 1;
+    // periodic axes wrap; elsewhere the value is never used, any in-range node will do
+    gx = a.bc[0] == LBM_CDE_PERIODIC ? wrap_any(gx, a.nx) : (gx < 0 ? 0 : (gx >= a.nx ? a.nx - 1 : gx));
+    gy = a.bc[1] == LBM_CDE_PERIODIC ? wrap_any(gy, a.ny) : (gy < 0 ? 0 : (gy >= a.ny ? a.ny - 1 : gy));
+    sphi[ly][lx] = phis[gy * a.nx + gx];
+  }
+  __syncthreads();
+  const int64_t x = tx0 + threadIdx.x, y = ty0 + threadIdx.y;
+  if (x >= a.nx || y >= a.ny) return;
+  const __half* __restrict__ src = (const __half*)a.src;
+  const float inv = (float)a.fp16_inv_scale;
+  float f[9];
+#define LBM_SPLIT_PULL(I, EX, EY)                                                        \
+  {                                                                                      \
+    int pop, dx, dy;                                                                     \
+    int64_t sx, sy;                                                                      \
+    if constexpr (WALLS) {                                                               \
+      pull_source_d2q9<EX, EY>(a, x, y, pop, sx, sy, dx, dy);                            \
+    } else {                                                                             \
+      pop = I;                                                                           \
+      dx = -(EX);                                                                        \
+      dy = -(EY);                                                                        \
+      sx = (EX) == 1 ? wrap_m(x, a.nx) : (EX) == -1 ? wrap_p(x, a.nx) : x;               \
+      sy = (EY) == 1 ? wrap_m(y, a.ny) : (EY) == -1 ? wrap_p(y, a.ny) : y;               \
+    }                                                                                    \
+    const float ph = sphi[threadIdx.y + 1 + dy][threadIdx.x + 1 + dx];                   \
+    float ux, uy;                                                                        \
+    velocity2<float>(a, sx, sy, ux, uy);                                                 \
+    f[I] = feq_d2q9(pop, ph, ux, uy) +                                                   \
+           __half2float(src[(int64_t)pop * a.plane + sy * a.nx + sx]) * inv;             \
+  }
+  LBM_SPLIT_PULL(0, 0, 0)
+  LBM_SPLIT_PULL(1, 1, 0)
+  LBM_SPLIT_PULL(2, 0, 1)
+  LBM_SPLIT_PULL(3, -1, 0)
+  LBM_SPLIT_PULL(4, 0, -1)
+  LBM_SPLIT_PULL(5, 1, 1)
+  LBM_SPLIT_PULL(6, -1, 1)
+  LBM_SPLIT_PULL(7, -1, -1)
+  LBM_SPLIT_PULL(8, 1, -1)
+#undef LBM_SPLIT_PULL
+  float ux, uy;
+  velocity2<float>(a, x, y, ux, uy);
+  const float phi = f[0] + f[1] + f[2] + f[3] + f[4] + f[5] + f[6] + f[7] + f[8];
+  collide_d2q9<float>(f, ux, uy, 0.0f, const_rel2<float>(a));
+  const int64_t node = y * a.nx + x;
+  ((float*)a.dst_phi)[node] = phi;
+  __half* __restrict__ dst = (__half*)a.dst;
+  const float scale = (float)a.fp16_scale;
+  bool over = false;
+#pragma unroll
+  for (int i = 0; i < 9; ++i) dst[i * a.plane + node] = to_half(f[i] - feq_d2q9(i, phi, ux, uy), scale, over);
+  if (over) overflow[0] = 1u;
+}
+
+// Literal half storage of the shifted populations, same step as FP32.
+template <int BX, bool WALLS>
+__global__ __launch_bounds__(BX) void k_step_d2q9_half(const RunArgs a, unsigned* __restrict__ overflow) {
+  const int64_t ntx = (a.nx + BX - 1) / BX;
+  const int64_t b = tile_of_block(blockIdx.x, gridDim.x, ntx, a.xcd_remap);
+  const int64_t x = (b % ntx) * BX + threadIdx.x, y = b / ntx;
+  if (x >= a.nx) return;
+  const __half* __restrict__ src = (const __half*)a.src;
+  const float inv = (float)a.fp16_inv_scale;
+  float f[9];
+#define LBM_HALF_PULL(I, EX, EY)                                                                       \
+  {                                                                                                    \
+    int64_t idx;                                                                                       \
+    if constexpr (WALLS) {                                                                             \
+      idx = pull_index_d2q9<EX, EY>(a, x, y);                                                          \
+    } else {                                                                                           \
+      const int64_t sx = (EX) == 1 ? wrap_m(x, a.nx) : (EX) == -1 ? wrap_p(x, a.nx) : x;              \
+      const int64_t sy = (EY) == 1 ? wrap_m(y, a.ny) : (EY) == -1 ? wrap_p(y, a.ny) : y;              \
+      idx = (int64_t)(I) * a.plane + sy * a.nx + sx;                                                   \
+    }                                                                                                  \
+    f[I] = __half2float(src[idx]) * inv;                                                               \
+  }
+  LBM_HALF_PULL(0, 0, 0)
+  LBM_HALF_PULL(1, 1, 0)
+  LBM_HALF_PULL(2, 0, 1)
+  LBM_HALF_PULL(3, -1, 0)
+  LBM_HALF_PULL(4, 0, -1)
+  LBM_HALF_PULL(5, 1, 1)
+  LBM_HALF_PULL(6, -1, 1)
+  LBM_HALF_PULL(7, -1, -1)
+  LBM_HALF_PULL(8, 1, -1)
+#undef LBM_HALF_PULL
+  float ux, uy;
+  velocity2<float>(a, x, y, ux, uy);
+  collide_d2q9<float>(f, ux, uy, (float)a.phi_ref, const_rel2<float>(a));
+  const int64_t node = y * a.nx + x;
+  __half* __restrict__ dst = (__half*)a.dst;
+  const float scale = (float)a.fp16_scale;
+  bool over = false;
+#pragma unroll
+  for (int i = 0; i < 9; ++i) dst[i * a.plane + node] = to_half(f[i], scale, over);
+  if (over) overflow[0] = 1u;
+}
+
+// Largest magnitude, per block, of what 16-bit storage will hold for this
+// run: the non-equilibrium part after the first step (split form), or the
+// shifted equilibrium populations (literal form).  Block maxima go to
+// partial[blockIdx.x]; a second pass takes the maximum of those.
+__global__ __launch_bounds__(256) void k_fp16_probe(const RunArgs a, const double* __restrict__ phi0, int split,
+                                                    float* __restrict__ partial) {
+  __shared__ float sh[256];
+  const int64_t N = a.nx * a.ny;
+  float m = 0.0f;
+  for (int64_t node = (int64_t)blockIdx.x * 256 + threadIdx.x; node < N; node += (int64_t)gridDim.x * 256) {
+    const int64_t x = node % a.nx, y = node / a.nx;
+    if (split) {
+      // first step from the equilibrium state: f_i = f_eq(phi0(s), u(s)) at the pull sources
+      float f[9];
+      const int ex[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+      const int ey[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+      for (int i = 0; i < 9; ++i) {
+        int64_t sx = x - ex[i], sy = y - ey[i];
+        int pop = i;
+        const bool ox = sx < 0 || sx >= a.nx, oy = sy < 0 || sy >= a.ny;
+        if (a.bc[0] == LBM_CDE_PERIODIC) sx = wrap_any(sx, a.nx);
+        if (a.bc[1] == LBM_CDE_PERIODIC) sy = wrap_any(sy, a.ny);
+        const bool cx = ox && a.bc[0] != LBM_CDE_PERIODIC, cy = oy && a.bc[1] != LBM_CDE_PERIODIC;
+        int vx = ex[i], vy = ey[i];
+        if ((cx && a.bc[0] == LBM_CDE_BOUNCE_BACK) || (cy && a.bc[1] == LBM_CDE_BOUNCE_BACK)) {
+          vx = -vx;
+          vy = -vy;
+          sx = x;
+          sy = y;
+        } else {
+          if (cx) { vx = -vx; sx = x; }
+          if (cy) { vy = -vy; sy = y; }
+        }
+        pop = pop_of_d2q9(vx, vy);
+        float ux, uy;
+        velocity2<float>(a, sx, sy, ux, uy);
+        f[i] = feq_d2q9(pop, (float)phi0[sy * a.nx + sx], ux, uy);
+      }
+      float ux, uy;
+      velocity2<float>(a, x, y, ux, uy);
+      const float phi = f[0] + f[1] + f[2] + f[3] + f[4] + f[5] + f[6] + f[7] + f[8];
+      collide_d2q9<float>(f, ux, uy, 0.0f, const_rel2<float>(a));
+      for (int i = 0; i < 9; ++i) m = fmaxf(m, fabsf(f[i] - feq_d2q9(i, phi, ux, uy)));
+    } else {
+      double u[3];
+      float ux, uy;
+      velocity2<float>(a, x, y, ux, uy);
+      u[0] = ux;
+      u[1] = uy;
+      double f[9];
+      equilibrium_d2q9(f, phi0[node], u[0], u[1], a.phi_ref);
+      for (int i = 0; i < 9; ++i) m = fmaxf(m, fabsf((float)f[i]));
+    }
+  }
+  sh[threadIdx.x] = m;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) sh[threadIdx.x] = fmaxf(sh[threadIdx.x], sh[threadIdx.x + w]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[blockIdx.x] = sh[0];
+}
+
+__global__ __launch_bounds__(256) void k_max_final(const float* __restrict__ partial, int n, float* __restrict__ out) {
+  __shared__ float sh[256];
+  float m = 0.0f;
+  for (int i = threadIdx.x; i < n; i += 256) m = fmaxf(m, partial[i]);
+  sh[threadIdx.x] = m;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) sh[threadIdx.x] = fmaxf(sh[threadIdx.x], sh[threadIdx.x + w]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = sh[0];
+}
+
+// Initial split or literal 16-bit state from phi0 (the equilibrium).
+__global__ __launch_bounds__(256) void k_init_d2q9_fp16(const RunArgs a, const double* __restrict__ phi0, int split,
+                                                        unsigned* __restrict__ overflow) {
+  const int64_t N = a.nx * a.ny;
+  const int64_t node = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (node >= N) return;
+  __half* dst = (__half*)a.dst;
+  bool over = false;
+  if (split) {
+    ((float*)a.dst_phi)[node] = (float)phi0[node];
+    for (int i = 0; i < 9; ++i) dst[i * a.plane + node] = __float2half_rn(0.0f);
+  } else {
+    const int64_t x = node % a.nx, y = node / a.nx;
+    float ux, uy;
+    velocity2<float>(a, x, y, ux, uy);
+    double f[9];
+    equilibrium_d2q9(f, phi0[node], (double)ux, (double)uy, a.phi_ref);
+    for (int i = 0; i < 9; ++i) dst[i * a.plane + node] = to_half((float)f[i], (float)a.fp16_scale, over);
+  }
+  if (over) overflow[0] = 1u;
+}
+
+}  // namespace lbm

@@ -24,6 +24,7 @@
 #include "d2q9.hpp"
 #include "d3q15.hpp"
 #include "adjoint_d2q9.hpp"
+#include "fp16_d2q9.hpp"
 
 using namespace lbm;
 
@@ -63,6 +64,10 @@ struct Run {
   bool dbl = true;              // arithmetic and storage in double
   // workspace pieces
   char* pop[2] = {nullptr, nullptr};
+  char* phi[2] = {nullptr, nullptr};   // split 16-bit storage: phi planes
+  bool half = false;                   // 16-bit population storage
+  bool split = false;                  // ... with phi stored apart
+  double fp16_scale = 1.0;
   char* utab = nullptr;
   char* ufield = nullptr;
   char* node_par = nullptr;
@@ -227,7 +232,7 @@ double default_rate(int lattice, int k) {
 int validate(const lbm_cde_run_desc& d, int idx) {
   if (d.lattice != LBM_CDE_D2Q9 && d.lattice != LBM_CDE_D3Q15)
     return fail_init(LBM_CDE_EINVAL, "run %d: unknown lattice %d", idx, d.lattice);
-  if (d.precision < LBM_CDE_FP64 || d.precision > LBM_CDE_FP16_SPLIT)
+  if (d.precision < LBM_CDE_FP64 || d.precision > LBM_CDE_FP16_SHIFTED)
     return fail_init(LBM_CDE_EINVAL, "run %d: unknown precision %d", idx, d.precision);
   if (d.nx < 1 || d.ny < 1 || d.nz < 1)
     return fail_init(LBM_CDE_EINVAL, "run %d: grid %lld x %lld x %lld has an empty axis", idx, (long long)d.nx,
@@ -250,10 +255,14 @@ int validate(const lbm_cde_run_desc& d, int idx) {
   if (d.heat_rule < LBM_CDE_HEAT_LAMBDA_MIN || d.heat_rule > LBM_CDE_HEAT_EXPLICIT)
     return fail_init(LBM_CDE_EINVAL, "run %d: unknown heat-flux rate rule %d", idx, d.heat_rule);
   if (!std::isfinite(d.phi_ref)) return fail_init(LBM_CDE_EINVAL, "run %d: phi_ref is not finite", idx);
-  if (d.precision == LBM_CDE_FP16_SPLIT)
-    return fail_init(LBM_CDE_EUNSUPPORTED, "run %d: FP16 split storage is not built in this library version", idx);
-  if (d.lattice == LBM_CDE_D3Q15 && d.precision == LBM_CDE_FP16_SPLIT)
-    return fail_init(LBM_CDE_EUNSUPPORTED, "run %d: FP16 split storage is built for D2Q9 only", idx);
+  const bool half = d.precision == LBM_CDE_FP16_SPLIT || d.precision == LBM_CDE_FP16_SHIFTED;
+  if (half && d.lattice == LBM_CDE_D3Q15)
+    return fail_init(LBM_CDE_EUNSUPPORTED, "run %d: 16-bit storage is built for D2Q9 only", idx);
+  if (half && (d.D_field || d.u_kind == LBM_CDE_U_FIELD))
+    return fail_init(LBM_CDE_EUNSUPPORTED, "run %d: 16-bit storage needs constant D and a constant or separable u",
+                     idx);
+  if (half && (d.fp16_scale < 0.0 || !std::isfinite(d.fp16_scale)))
+    return fail_init(LBM_CDE_EINVAL, "run %d: fp16_scale must be >= 0", idx);
   if (d.lattice == LBM_CDE_D3Q15 && d.D_field)
     return fail_init(LBM_CDE_EUNSUPPORTED, "run %d: per-node D fields are built for D2Q9 only", idx);
   return LBM_CDE_OK;
@@ -342,7 +351,9 @@ size_t layout(Run& r, char* base) {
   r.dim = d.lattice == LBM_CDE_D2Q9 ? 2 : 3;
   r.Q = d.lattice == LBM_CDE_D2Q9 ? 9 : 15;
   r.dbl = d.precision == LBM_CDE_FP64;
-  r.elem = r.dbl ? 8 : 4;
+  r.half = d.precision == LBM_CDE_FP16_SPLIT || d.precision == LBM_CDE_FP16_SHIFTED;
+  r.split = d.precision == LBM_CDE_FP16_SPLIT;
+  r.elem = r.dbl ? 8 : (r.half ? 2 : 4);
   r.nodes = d.nx * d.ny * d.nz;
   // planes padded to a multiple of 256 bytes plus a skew, so that the same
   // node of consecutive planes does not fall on the same HBM channel and bank
@@ -356,12 +367,18 @@ size_t layout(Run& r, char* base) {
   const size_t popbytes = (size_t)r.plane * r.elem * r.Q;
   r.pop[0] = take(popbytes);
   r.pop[1] = take(popbytes);
+  r.phi[0] = r.phi[1] = nullptr;
+  if (r.split) {
+    r.phi[0] = take(sizeof(float) * (size_t)r.nodes);
+    r.phi[1] = take(sizeof(float) * (size_t)r.nodes);
+  }
   r.utab = nullptr;
   r.ufield = nullptr;
   r.node_par = nullptr;
-  if (d.u_kind == LBM_CDE_U_SEPARABLE) r.utab = take((size_t)r.dim * (1 + d.nx + d.ny + d.nz) * r.elem);
-  if (d.u_kind == LBM_CDE_U_FIELD) r.ufield = take((size_t)r.dim * r.nodes * r.elem);
-  if (d.D_field) r.node_par = take((size_t)(r.dim == 2 ? 5 : 9) * r.nodes * r.elem);
+  const size_t relem = r.dbl ? 8 : 4;  // arithmetic precision of tables and parameters
+  if (d.u_kind == LBM_CDE_U_SEPARABLE) r.utab = take((size_t)r.dim * (1 + d.nx + d.ny + d.nz) * relem);
+  if (d.u_kind == LBM_CDE_U_FIELD) r.ufield = take((size_t)r.dim * r.nodes * relem);
+  if (d.D_field) r.node_par = take((size_t)(r.dim == 2 ? 5 : 9) * r.nodes * relem);
   r.red_partial = (double*)take(sizeof(double) * 4 * RED_BLOCKS);
   r.red_out = (double*)take(sizeof(double) * 4);
   r.flags = (unsigned long long*)take(sizeof(unsigned long long) * 4);
@@ -373,11 +390,22 @@ int64_t tile_rows(const Run& r, const Variant& v) {
   return (r.d.ny + (int64_t)v.by * v.ny - 1) / ((int64_t)v.by * v.ny) * r.d.nz;
 }
 
+// Bytes of one state: the population planes (and, split storage, phi).
+size_t state_size(const Run& r) {
+  const size_t pb = (size_t)r.Q * r.plane * r.elem;
+  return r.split ? align_up(pb) + sizeof(float) * r.nodes : pb;
+}
+
 RunArgs make_args(const lbm_cde* h, const Run& r, int parity) {
   RunArgs a;
   std::memset(&a, 0, sizeof a);
   a.src = r.pop[parity];
   a.dst = r.pop[parity ^ 1];
+  a.src_phi = r.phi[parity];
+  a.dst_phi = r.phi[parity ^ 1];
+  a.fp16_scale = r.half ? r.fp16_scale : 1.0;
+  a.fp16_inv_scale = r.half ? 1.0 / r.fp16_scale : 1.0;
+  a.fp16_flags = r.flags ? (void*)&r.flags[1] : nullptr;
   a.nx = r.d.nx;
   a.ny = r.d.ny;
   a.nz = r.d.nz;
@@ -388,7 +416,7 @@ RunArgs make_args(const lbm_cde* h, const Run& r, int parity) {
   a.u_tab = r.utab;
   a.u_field = r.ufield;
   a.node_par = r.node_par;
-  a.phi_ref = r.dbl ? 0.0 : r.d.phi_ref;
+  a.phi_ref = (r.dbl || r.split) ? 0.0 : r.d.phi_ref;
   for (int k = 0; k < 15; ++k) a.s[k] = r.s[k];
   for (int i = 0; i < 3; ++i)
     for (int j = 0; j < 3; ++j) a.A[i][j] = r.A[i][j];
@@ -408,7 +436,7 @@ bool batch_eligible(const lbm_cde_run_desc* runs, int32_t nruns) {
   if (nruns < 2) return false;
   for (int i = 0; i < nruns; ++i)
     if (runs[i].lattice != LBM_CDE_D2Q9 || runs[i].precision != runs[0].precision ||
-        runs[i].precision == LBM_CDE_FP16_SPLIT)
+        runs[i].precision == LBM_CDE_FP16_SPLIT || runs[i].precision == LBM_CDE_FP16_SHIFTED)
       return false;
   return true;
 }
@@ -423,9 +451,11 @@ size_t batch_bytes(int32_t nruns) {
 // Default launch variants, from sweeps on MI355X: wide one-row tiles with
 // streaming stores and the hardware's round-robin XCD order were fastest
 // (the XCD-contiguous remap was 5-10% slower on 4096^2 D2Q9).
-Variant default_variant(int lattice, bool dbl) {
+Variant default_variant(int lattice, int precision) {
   if (lattice == LBM_CDE_D3Q15) return Variant{128, 1, 1, true, 0};
-  return dbl ? Variant{128, 2, 1, true, 0} : Variant{256, 1, 1, true, 0};
+  if (precision == LBM_CDE_FP16_SPLIT) return Variant{128, 4, 1, false, 0};
+  if (precision == LBM_CDE_FP16_SHIFTED) return Variant{256, 1, 1, false, 0};
+  return precision == LBM_CDE_FP64 ? Variant{128, 2, 1, true, 0} : Variant{256, 1, 1, true, 0};
 }
 
 using StepFn = void (*)(const RunArgs, hipStream_t);
@@ -489,8 +519,38 @@ const StepEntry kSteps[] = {
     STEP_ENTRY(128, 2, 2, true),  STEP_ENTRY(512, 1, 1, true),  STEP_ENTRY(128, 1, 1, true),
 };
 
+template <int BX, int BY, bool WALLS>
+void launch_split(const RunArgs a, hipStream_t s) {
+  const int64_t ntx = (a.nx + BX - 1) / BX, nty = (a.ny + BY - 1) / BY;
+  hipLaunchKernelGGL((k_step_d2q9_split<BX, BY, WALLS>), dim3((unsigned)(ntx * nty)), dim3(BX, BY), 0, s, a,
+                     (unsigned*)a.fp16_flags);
+}
+
+template <bool WALLS>
+void launch_half(const RunArgs a, hipStream_t s) {
+  const int64_t ntx = (a.nx + 255) / 256;
+  hipLaunchKernelGGL((k_step_d2q9_half<256, WALLS>), dim3((unsigned)(ntx * a.ny)), dim3(256), 0, s, a,
+                     (unsigned*)a.fp16_flags);
+}
+
+struct SplitEntry {
+  int bx, by;
+  StepFn fn[2];  // [walls?]
+};
+#define SPLIT_ENTRY(BX, BY) \
+  SplitEntry { BX, BY, {launch_split<BX, BY, false>, launch_split<BX, BY, true>} }
+const SplitEntry kSplit[] = {SPLIT_ENTRY(64, 4), SPLIT_ENTRY(128, 2), SPLIT_ENTRY(256, 1), SPLIT_ENTRY(64, 8),
+                             SPLIT_ENTRY(128, 4), SPLIT_ENTRY(256, 2)};
+
 StepFn find_step(const Run& r, const Variant& v) {
   const int p = r.dbl ? 1 : 0, w = r.walls ? 1 : 0;
+  if (r.split) {
+    for (const auto& e : kSplit)
+      if (e.bx == v.bx && e.by == v.by && v.ny == 1) return e.fn[w];
+    return nullptr;
+  }
+  if (r.half) return (v.bx == 256 && v.by == 1 && v.ny == 1) ? (r.walls ? launch_half<true> : launch_half<false>)
+                                                             : nullptr;
   if (r.d.lattice == LBM_CDE_D3Q15) {
     for (const auto& e : kSteps3)
       if (e.bx == v.bx && e.by == v.by && e.ny == v.ny && e.nt == v.nt) return e.fn[p][w];
@@ -503,7 +563,7 @@ StepFn find_step(const Run& r, const Variant& v) {
 
 StepFn pick_step(const lbm_cde* h, const Run& r) {
   StepFn f = find_step(r, r.var);
-  return f ? f : find_step(r, default_variant(r.d.lattice, r.dbl));
+  return f ? f : find_step(r, default_variant(r.d.lattice, r.d.precision));
 }
 
 int launch_steps(lbm_cde* h, hipStream_t s, int64_t n) {
@@ -574,6 +634,9 @@ int reduce_into(lbm_cde* h, Run& r, int kind, double x_ref, double* out_dev) {
   if (r.dbl)
     hipLaunchKernelGGL(k_reduce_partial<double>, dim3(RED_BLOCKS), dim3(RED_THREADS), 0, h->stream, a, r.Q, kind,
                        x_ref, r.red_partial);
+  else if (r.half)
+    hipLaunchKernelGGL(k_reduce_partial<__half>, dim3(RED_BLOCKS), dim3(RED_THREADS), 0, h->stream, a, r.Q, kind,
+                       x_ref, r.red_partial);
   else
     hipLaunchKernelGGL(k_reduce_partial<float>, dim3(RED_BLOCKS), dim3(RED_THREADS), 0, h->stream, a, r.Q, kind,
                        x_ref, r.red_partial);
@@ -596,6 +659,33 @@ void parse_env(lbm_cde* h) {
   h->env.xcd = h->env3.xcd = xcd ? std::atoi(xcd) : 0;
 }
 
+// Power-of-two scale of 16-bit storage: the given one, or one that puts the
+// largest magnitude to store at about 1/256 of the half range.  Half is a
+// floating-point format, so the headroom costs no relative precision for
+// values in the normal range; it absorbs later growth of the stored part
+// (the non-equilibrium part grows as gradients build up in compressive
+// flows).  The reduction partials of the run serve as scratch.
+int choose_fp16_scale(Run& r, lbm_cde* h, const double* phi0, hipStream_t s) {
+  if (r.d.fp16_scale > 0.0) {
+    r.fp16_scale = r.d.fp16_scale;
+    return LBM_CDE_OK;
+  }
+  const RunArgs a = make_args(h, r, 0);
+  float* partial = (float*)r.red_partial;
+  float* out = (float*)r.red_out;
+  hipLaunchKernelGGL(k_fp16_probe, dim3(RED_BLOCKS), dim3(256), 0, s, a, phi0, r.split ? 1 : 0, partial);
+  hipLaunchKernelGGL(k_max_final, dim3(1), dim3(256), 0, s, (const float*)partial, RED_BLOCKS, out);
+  float m = 0.0f;
+  HIP_TRY(nullptr, hipMemcpyAsync(&m, out, sizeof m, hipMemcpyDeviceToHost, s));
+  HIP_TRY(nullptr, hipStreamSynchronize(s));
+  if (!std::isfinite(m)) return fail_init(LBM_CDE_EINVAL, "init: non-finite initial state");
+  const double target = kHalfMax / 256.0;
+  int e = m > 0.0f ? (int)std::floor(std::log2(target / (double)m)) : 24;
+  e = std::max(-24, std::min(60, e));
+  r.fp16_scale = std::ldexp(1.0, e);
+  return LBM_CDE_OK;
+}
+
 // Per-run set-up of lbm_cde_init (errors go to the thread's init error text).
 int init_runs(lbm_cde* h, const lbm_cde_run_desc* runs, int32_t nruns, const double* const* phi0, char* workspace,
               size_t ws_bytes) {
@@ -613,8 +703,8 @@ int init_runs(lbm_cde* h, const lbm_cde_run_desc* runs, int32_t nruns, const dou
     if ((rc = derive(r, i)) || (rc = check_velocity(r, i))) return rc;
     r.walls = false;
     for (int a = 0; a < r.dim; ++a) r.walls |= r.d.bc[a] != LBM_CDE_PERIODIC;
-    r.var = default_variant(r.d.lattice, r.dbl);
-    if (h->env_variant) r.var = r.d.lattice == LBM_CDE_D3Q15 ? h->env3 : h->env;
+    r.var = default_variant(r.d.lattice, r.d.precision);
+    if (h->env_variant && !r.half) r.var = r.d.lattice == LBM_CDE_D3Q15 ? h->env3 : h->env;
     if (!find_step(r, r.var)) return fail_init(LBM_CDE_EINVAL, "run %d: launch variant not built", i);
     // host tables are copied during init; keep no pointer to caller memory
     r.d.u_tables = nullptr;
@@ -655,10 +745,22 @@ int init_runs(lbm_cde* h, const lbm_cde_run_desc* runs, int32_t nruns, const dou
       HIP_TRY(nullptr, hipStreamSynchronize(s));
       if (bad) return fail_init(LBM_CDE_ENOTSPD, "run %d: %llu nodes of D_field are not SPD", i, bad);
     }
+    HIP_TRY(nullptr, hipMemsetAsync(&r.flags[1], 0, sizeof(unsigned long long), s));
+    if (r.half) {
+      int rc2 = choose_fp16_scale(r, h, phi0[i], s);
+      if (rc2) return rc2;
+    }
     // initial populations: the equilibrium of phi0, written to buffer 0
     const RunArgs a = make_args(h, r, 1);
-    if (r.dbl) launch_init<double>(r, a, phi0[i], s);
-    else launch_init<float>(r, a, phi0[i], s);
+    if (r.half) {
+      const unsigned blocks = (unsigned)((r.nodes + 255) / 256);
+      hipLaunchKernelGGL(k_init_d2q9_fp16, dim3(blocks), dim3(256), 0, s, a, phi0[i], r.split ? 1 : 0,
+                         (unsigned*)&r.flags[1]);
+    } else if (r.dbl) {
+      launch_init<double>(r, a, phi0[i], s);
+    } else {
+      launch_init<float>(r, a, phi0[i], s);
+    }
     HIP_TRY(nullptr, hipGetLastError());
     h->runs.push_back(r);
   }
@@ -773,7 +875,8 @@ std::string tune_key(const Run& r) {
   if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess) arch = prop.gcnArchName;
   char buf[256];
   std::snprintf(buf, sizeof buf, "%s:%s:%s:%lldx%lldx%lld:%d%d%d", arch.c_str(),
-                r.d.lattice == LBM_CDE_D2Q9 ? "d2q9" : "d3q15", r.dbl ? "fp64" : "fp32", (long long)r.d.nx,
+                r.d.lattice == LBM_CDE_D2Q9 ? "d2q9" : "d3q15",
+                r.dbl ? "fp64" : r.split ? "fp16split" : r.half ? "fp16" : "fp32", (long long)r.d.nx,
                 (long long)r.d.ny, (long long)r.d.nz, r.d.bc[0], r.d.bc[1], r.d.bc[2]);
   return buf;
 }
@@ -837,7 +940,7 @@ namespace {
 
 int check_adjoint_run(lbm_cde* h, Run* r) {
   if (!r) return fail(h, LBM_CDE_EINVAL, "adjoint: bad handle or run");
-  if (r->d.lattice != LBM_CDE_D2Q9 || r->d.precision == LBM_CDE_FP16_SPLIT)
+  if (r->d.lattice != LBM_CDE_D2Q9 || r->half)
     return fail(h, LBM_CDE_EUNSUPPORTED, "adjoint: built for D2Q9 in FP64 or FP32 storage");
   if (r->d.heat_rule != LBM_CDE_HEAT_EXPLICIT)
     return fail(h, LBM_CDE_EUNSUPPORTED,
@@ -943,6 +1046,7 @@ int lbm_cde_moments(lbm_cde_handle h, int32_t run, double* phi_out) {
   const RunArgs a = make_args(h, *r, (int)(r->steps & 1));
   const unsigned blocks = (unsigned)((r->nodes + 255) / 256);
   if (r->dbl) hipLaunchKernelGGL(k_moments<double>, dim3(blocks), dim3(256), 0, h->stream, a, r->Q, phi_out);
+  else if (r->half) hipLaunchKernelGGL(k_moments<__half>, dim3(blocks), dim3(256), 0, h->stream, a, r->Q, phi_out);
   else hipLaunchKernelGGL(k_moments<float>, dim3(blocks), dim3(256), 0, h->stream, a, r->Q, phi_out);
   HIP_TRY(h, hipGetLastError());
   return LBM_CDE_OK;
@@ -958,17 +1062,20 @@ int lbm_cde_reduce(lbm_cde_handle h, int32_t run, int32_t kind, double x_ref, do
   int rc = reduce_into(h, *r, kind, x_ref, r->red_out);
   if (rc) return rc;
   double res[4];
+  unsigned long long over = 0;
   HIP_TRY(h, hipMemcpyAsync(res, r->red_out, sizeof res, hipMemcpyDeviceToHost, h->stream));
+  HIP_TRY(h, hipMemcpyAsync(&over, &r->flags[1], sizeof over, hipMemcpyDeviceToHost, h->stream));
   HIP_TRY(h, hipStreamSynchronize(h->stream));
   if (kind == LBM_CDE_RED_NONFINITE) {
     out[0] = res[3];
     out[1] = out[2] = 0.0;
-    return LBM_CDE_OK;
+  } else {
+    out[0] = res[0];
+    out[1] = kind == LBM_CDE_RED_XMOMENTS ? res[1] : 0.0;
+    out[2] = kind == LBM_CDE_RED_XMOMENTS ? res[2] : 0.0;
+    if (res[3] != 0.0) return fail(h, LBM_CDE_ENONFINITE, "reduce: %g non-finite values in the state", res[3]);
   }
-  out[0] = res[0];
-  out[1] = kind == LBM_CDE_RED_XMOMENTS ? res[1] : 0.0;
-  out[2] = kind == LBM_CDE_RED_XMOMENTS ? res[2] : 0.0;
-  if (res[3] != 0.0) return fail(h, LBM_CDE_ENONFINITE, "reduce: %g non-finite values in the state", res[3]);
+  if (over) return fail(h, LBM_CDE_EOVERFLOW, "reduce: 16-bit storage of run %d saturated", run);
   return LBM_CDE_OK;
 }
 
@@ -1056,6 +1163,24 @@ int lbm_cde_tune(lbm_cde_handle h, int32_t trials) {
     }
     double best = 1e300;
     Variant best_v = r.var;
+    if (r.half) {
+      if (r.split)
+        for (const auto& e : kSplit)
+          for (int xcd = 0; xcd < 3; ++xcd) {
+            const Variant c{e.bx, e.by, 1, false, xcd};
+            if (xcd == 2 && tile_rows(r, c) % 8 != 0) continue;
+            double ms = 0.0;
+            const int rc = time_variant(h, r, c, trials, &ms);
+            if (rc) return rc;
+            if (ms < best) {
+              best = ms;
+              best_v = c;
+            }
+          }
+      r.var = best_v;
+      if (r.split) cache_store(key, best_v, best);
+      continue;
+    }
     const int n = r.d.lattice == LBM_CDE_D3Q15 ? (int)(sizeof kSteps3 / sizeof kSteps3[0])
                                                : (int)(sizeof kSteps / sizeof kSteps[0]);
     for (int i = 0; i < n; ++i)
@@ -1093,15 +1218,18 @@ int lbm_cde_get_variant(lbm_cde_handle h, int32_t run, int32_t* out) {
 int lbm_cde_state_bytes(lbm_cde_handle h, int32_t run, size_t* bytes) {
   Run* r = get_run(h, run);
   if (!r || !bytes) return fail(h, LBM_CDE_EINVAL, "state_bytes: bad handle, run or pointer");
-  *bytes = (size_t)r->Q * (size_t)r->plane * r->elem;
+  *bytes = state_size(*r);
   return LBM_CDE_OK;
 }
 
 int lbm_cde_get_state(lbm_cde_handle h, int32_t run, void* dst) {
   Run* r = get_run(h, run);
   if (!r || !dst) return fail(h, LBM_CDE_EINVAL, "get_state: bad handle, run or pointer");
-  HIP_TRY(h, hipMemcpyAsync(dst, r->pop[r->steps & 1], (size_t)r->Q * r->plane * r->elem, hipMemcpyDeviceToDevice,
-                            h->stream));
+  const size_t pb = (size_t)r->Q * r->plane * r->elem;
+  HIP_TRY(h, hipMemcpyAsync(dst, r->pop[r->steps & 1], pb, hipMemcpyDeviceToDevice, h->stream));
+  if (r->split)
+    HIP_TRY(h, hipMemcpyAsync((char*)dst + align_up(pb), r->phi[r->steps & 1], sizeof(float) * r->nodes,
+                              hipMemcpyDeviceToDevice, h->stream));
   return LBM_CDE_OK;
 }
 
@@ -1112,8 +1240,11 @@ int lbm_cde_set_state(lbm_cde_handle h, int32_t run, const void* src, int64_t st
   if (r->d.max_steps >= 0 && steps > r->d.max_steps)
     return fail(h, LBM_CDE_EINVAL, "set_state: step count beyond the run's budget");
   r->steps = steps;
-  HIP_TRY(h, hipMemcpyAsync(r->pop[steps & 1], src, (size_t)r->Q * r->plane * r->elem, hipMemcpyDeviceToDevice,
-                            h->stream));
+  const size_t pb = (size_t)r->Q * r->plane * r->elem;
+  HIP_TRY(h, hipMemcpyAsync(r->pop[steps & 1], src, pb, hipMemcpyDeviceToDevice, h->stream));
+  if (r->split)
+    HIP_TRY(h, hipMemcpyAsync(r->phi[steps & 1], (const char*)src + align_up(pb), sizeof(float) * r->nodes,
+                              hipMemcpyDeviceToDevice, h->stream));
   return LBM_CDE_OK;
 }
 

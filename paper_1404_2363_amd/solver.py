@@ -13,7 +13,8 @@ import torch
 
 from . import _lib as L
 
-PRECISIONS = {"fp64": L.LBM_CDE_FP64, "fp32": L.LBM_CDE_FP32_SHIFTED, "fp16": L.LBM_CDE_FP16_SPLIT}
+PRECISIONS = {"fp64": L.LBM_CDE_FP64, "fp32": L.LBM_CDE_FP32_SHIFTED, "fp16": L.LBM_CDE_FP16_SPLIT,
+              "fp16_literal": L.LBM_CDE_FP16_SHIFTED}
 WALLS = {"periodic": L.LBM_CDE_PERIODIC, "bounce": L.LBM_CDE_BOUNCE_BACK, "specular": L.LBM_CDE_SPECULAR,
          False: L.LBM_CDE_PERIODIC, True: L.LBM_CDE_BOUNCE_BACK}
 LATTICES = {"d2q9": L.LBM_CDE_D2Q9, "d3q15": L.LBM_CDE_D3Q15}
