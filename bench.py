@@ -4,12 +4,16 @@ Headline workload: D2Q9 modified MRT on the 4096^2 periodic cellular-flow
 grid (rotated anisotropic D, 64 Gaussian hills), populations in FP32 shifted
 storage.  One step = one collide-and-stream pass over all nodes; `value` is
 million lattice updates per second with the populations resident in HBM.
-The same line carries the plain FP64 step on that grid, the D3Q15 256^3 step
-in FP64 and FP32, the roofline of the dominant kernel and the FP64 CPU
-oracle timed on the host cores.
+The same line carries the other forms measured the same way: the plain FP64
+and the FP16 split step on that grid, the D3Q15 256^3 step in FP64 and FP32,
+the 64-channel Taylor-Aris ensemble advanced by the batched persistent
+kernel, one adjoint gradient of the 512^2 inverse problem, the roofline of
+the dominant kernel and the FP64 CPU oracle timed on the host cores.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--only d2q9_fp32]
-                       [--no-cpu] [--copy-probe]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--only NAME]
+                       [--quick] [--no-cpu] [--no-tune] [--copy-probe]
+NAME: d2q9_4096_fp32 | d2q9_4096_fp64 | d2q9_4096_fp16 | d3q15_256_fp32 |
+      d3q15_256_fp64 | taylor_aris_batch | adjoint
 """
 import argparse
 import json
@@ -25,6 +29,28 @@ HBM_PEAK_GBS = 8000.0          # MI355X HBM3E peak
 BYTES_PER_LU = {("d2q9", "fp64"): 144, ("d2q9", "fp32"): 72, ("d2q9", "fp16"): 44,
                 ("d3q15", "fp64"): 240, ("d3q15", "fp32"): 120}
 COPY_PROBE_BYTES = 1 << 30     # bytes read (and written) by one calibration copy
+
+
+def profiled_traffic(name, launch):
+    """HBM bytes per launch from the committed PMC profile of this kernel, or
+    None when the kernel source or the launch variant has changed since the
+    counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        rec = json.load(open(path))[name]
+    except (OSError, KeyError, ValueError):
+        return None
+    h = hashlib.sha256()
+    for f in rec["source_files"]:
+        h.update(open(os.path.join(ROOT, "paper_1404_2363_amd", "csrc", f), "rb").read())
+    if h.hexdigest()[:16] != rec["source_sha"]:
+        return None
+    bx, by = launch["block"]
+    tag = f"<float, {bx}, {by}, {launch['rows_per_thread']}, false, {'true' if launch['nt_stores'] else 'false'}>"
+    if tag not in rec["kernel"]:
+        return None
+    return rec["traffic_bytes_per_launch"]
 
 
 def log(msg):
@@ -59,6 +85,52 @@ def gpu_variant(wl, precision, steps, warmup, tune=True):
     return {"precision": precision, "nodes": wl.nodes, "steps": steps, "ms_per_step": t_step * 1e3,
             "mlups": wl.nodes / t_step / 1e6, "achieved_gbs": gbs, "bytes_per_lu": bpl,
             "hbm_frac": gbs / HBM_PEAK_GBS, "wall_s": wall, "nonfinite": nonfinite, "launch": var}
+
+
+def batch_variant(runs, precision, steps, warmup):
+    """The Taylor-Aris ensemble: all channels in one persistent launch per step."""
+    from paper_1404_2363_amd.solver import Solver
+    per_run = [{"heat": [1 / r.meta["tau"]] * 2, "xref0": r.meta["x0"], "xref_drift": r.meta["U_node_mean"]}
+               for r in runs]
+    s = Solver(runs, precision, per_run=per_run)
+    ev, wall = time_steps(s, steps, warmup)
+    nonfinite = sum(s.nonfinite(i) for i in range(len(runs)))
+    s.close()
+    nodes = sum(r.nodes for r in runs)
+    t_step = ev / steps
+    bpl = BYTES_PER_LU[("d2q9", precision)]
+    gbs = nodes * bpl / t_step / 1e9
+    return {"precision": precision, "runs": len(runs), "nodes": nodes, "steps": steps,
+            "ms_per_step": t_step * 1e3, "mlups": nodes / t_step / 1e6, "achieved_gbs": gbs,
+            "bytes_per_lu": bpl, "hbm_frac": gbs / HBM_PEAK_GBS, "wall_s": wall, "nonfinite": nonfinite}
+
+
+def adjoint_variant(precision="fp32"):
+    """One gradient of the snapshot misfit for one initial condition of the
+    512^2 inverse problem (2000 steps, snapshots every 200, checkpoints every
+    100): forward, segment recomputation and reverse sweep."""
+    import torch
+    from paper_1404_2363_amd import workloads as W
+    from paper_1404_2363_amd.adjoint import RolloutSpec, misfit
+    inv = W.inverse_dfield()
+    ic = inv["ics"][0]
+    spec = RolloutSpec(ic, inv["steps"], inv["snap_every"], inv["ckpt_every"], precision, (1.0, 1.0))
+    dev = "cuda:0"
+    D = torch.tensor(inv["D_trial"], dtype=torch.float64, device=dev, requires_grad=True)
+    p0 = torch.tensor(ic.phi0(), dtype=torch.float64, device=dev)
+    obs = torch.zeros((inv["steps"] // inv["snap_every"],) + ic.grid, dtype=torch.float64, device=dev)
+    misfit(D, p0, obs, spec).backward()          # warm-up (compiles graphs, allocator)
+    D.grad = None
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    J = misfit(D, p0, obs, spec)
+    J.backward()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    lu = ic.nodes * inv["steps"]
+    return {"precision": precision, "nodes": ic.nodes, "steps": inv["steps"], "seconds_per_gradient": dt,
+            "forward_lu_per_s_equiv": lu / dt / 1e6, "note": "MLUPS of forward steps per second of "
+            "forward + recompute + reverse (3 passes)"}
 
 
 def copy_probe():
@@ -104,6 +176,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--copy-probe", action="store_true")
+    ap.add_argument("--quick", action="store_true", help="headline variant only")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (run with --gpus 1)", file=sys.stderr)
@@ -119,20 +192,38 @@ def main():
     wl2 = W.cellular()
     out = {}
     plan = [("d2q9_4096_fp32", wl2, "fp32", args.steps, args.warmup)]
-    if not args.only:
+    wl3 = None
+    if (not args.only and not args.quick) or args.only.startswith("d3q15"):
         wl3 = W.sine3d()
-        plan += [("d2q9_4096_fp64", wl2, "fp64", max(args.steps // 2, 1), max(args.warmup // 2, 1)),
-                 ("d3q15_256_fp32", wl3, "fp32", max(args.steps // 4, 1), max(args.warmup // 4, 1)),
-                 ("d3q15_256_fp64", wl3, "fp64", max(args.steps // 8, 1), max(args.warmup // 8, 1))]
+    plan += [("d2q9_4096_fp64", wl2, "fp64", max(args.steps // 2, 1), max(args.warmup // 2, 1)),
+             ("d2q9_4096_fp16", wl2, "fp16", args.steps, args.warmup),
+             ("d3q15_256_fp32", wl3, "fp32", max(args.steps // 4, 1), max(args.warmup // 4, 1)),
+             ("d3q15_256_fp64", wl3, "fp64", max(args.steps // 8, 1), max(args.warmup // 8, 1))]
     for name, wl, prec, k, w in plan:
         if args.only and name != args.only:
+            continue
+        if name != "d2q9_4096_fp32" and not args.only and args.quick:
             continue
         log(f"{name}: {k} steps")
         out[name] = gpu_variant(wl, prec, k, w, tune)
         log(f"{name}: {out[name]['mlups']:.0f} MLUPS, {out[name]['achieved_gbs']:.0f} GB/s")
+    if (not args.only and not args.quick) or args.only == "taylor_aris_batch":
+        runs = W.taylor_aris_batch()
+        k = max(args.steps // 4, 1)
+        log(f"taylor_aris_batch: {len(runs)} channels, {k} steps")
+        out["taylor_aris_batch_fp32"] = batch_variant(runs, "fp32", k, max(args.warmup // 4, 1))
+        log(f"taylor_aris_batch: {out['taylor_aris_batch_fp32']['mlups']:.0f} MLUPS")
+    if (not args.only and not args.quick) or args.only == "adjoint":
+        log("adjoint: one 512^2 x 2000-step gradient")
+        out["inverse_adjoint_fp32"] = adjoint_variant("fp32")
+        log(f"adjoint: {out['inverse_adjoint_fp32']['seconds_per_gradient']:.3f} s per gradient")
+    if "d2q9_4096_fp32" not in out:
+        out["d2q9_4096_fp32"] = gpu_variant(wl2, "fp32", args.steps, args.warmup, tune)
     main_v = out["d2q9_4096_fp32"]
     if "d2q9_4096_fp64" in out:
         out["speedup_fp32_over_fp64_d2q9"] = main_v["mlups"] / out["d2q9_4096_fp64"]["mlups"]
+    if "d2q9_4096_fp16" in out and "d2q9_4096_fp64" in out:
+        out["speedup_fp16_over_fp64_d2q9"] = out["d2q9_4096_fp16"]["mlups"] / out["d2q9_4096_fp64"]["mlups"]
     if "d3q15_256_fp64" in out:
         out["speedup_fp32_over_fp64_d3q15"] = out["d3q15_256_fp32"]["mlups"] / out["d3q15_256_fp64"]["mlups"]
     cpu = None if args.no_cpu else cpu_baseline(wl2)
@@ -153,8 +244,9 @@ def main():
                                "0.01/0.1 rotated 30 deg, 64 Gaussian hills sigma=32, FP32 shifted storage",
                    "nodes": wl2.nodes},
         "roofline": {"bound": "hbm", "achieved": main_v["achieved_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": main_v["hbm_frac"], "traffic": None, "kernel": "k_step_d2q9<float>",
-                     "bytes_per_launch": 72 * wl2.nodes},
+                     "frac": main_v["hbm_frac"],
+                     "traffic": profiled_traffic("d2q9_4096_fp32", main_v["launch"]),
+                     "kernel": "k_step_d2q9<float>", "bytes_per_launch": 72 * wl2.nodes},
         "variants": out,
         "cpu_baseline": cpu,
     }

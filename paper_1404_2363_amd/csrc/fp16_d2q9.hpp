@@ -5,9 +5,10 @@
 // h_i = half(2^k (p_i - f_eq_i(phi, u))).  The pull step rebuilds each
 // incoming population at its source node s as f_eq_j(phi(s), u(s)) + 2^-k h_j(s)
 // (j = i, or the population the wall rule takes), collides in FP32 and splits
-// the result again; 4 + 18 bytes are read and written per node.  The phi
-// plane of a tile and its one-node halo is staged through LDS, so each phi is
-// fetched from memory about (BY + 2) / BY times instead of nine.
+// the result again; 4 + 18 bytes are read and written per node.  phi, phi ux
+// and phi uy of a tile and its one-node halo are staged through LDS, so each
+// phi is fetched from memory about (BY + 2) / BY times instead of nine and u
+// is evaluated once per node of the halo tile instead of at nine sources.
 //
 // Literal storage: g_i = f_i - w_i phi_ref (as FP32 shifted storage) kept as
 // half(2^k g_i).
@@ -84,21 +85,36 @@ LBM_FORCEINLINE void pull_source_d2q9(const RunArgs& a, int64_t x, int64_t y, in
   pop = pop_of_d2q9(vx, vy);
 }
 
+// Halo coordinate: periodic axes wrap (one conditional step when the axis is
+// longer than the tile, a modulo otherwise), other axes clamp (the value of
+// a node beyond a wall is never used).
+LBM_FORCEINLINE int64_t halo_coord(int64_t g, int64_t n, bool periodic, bool long_axis) {
+  if (!periodic) return g < 0 ? 0 : (g >= n ? n - 1 : g);
+  if (long_axis) return g < 0 ? g + n : (g >= n ? g - n : g);
+  return wrap_any(g, n);
+}
+
 template <int BX, int BY, bool WALLS>
 __global__ __launch_bounds__(BX * BY) void k_step_d2q9_split(const RunArgs a, unsigned* __restrict__ overflow) {
-  __shared__ float sphi[BY + 2][BX + 2];
+  // phi, phi ux, phi uy of the tile and its one-node halo
+  __shared__ float sphi[BY + 2][BX + 2], sjx[BY + 2][BX + 2], sjy[BY + 2][BX + 2];
   const int64_t ntx = (a.nx + BX - 1) / BX;
   const int64_t b = tile_of_block(blockIdx.x, gridDim.x, ntx, a.xcd_remap);
   const int64_t tx0 = (b % ntx) * BX, ty0 = (b / ntx) * BY;
   const float* __restrict__ phis = (const float*)a.src_phi;
   const int tid = threadIdx.y * BX + threadIdx.x;
+  const bool px = a.bc[0] == LBM_CDE_PERIODIC, py = a.bc[1] == LBM_CDE_PERIODIC;
+  const bool lx_long = a.nx > BX, ly_long = a.ny > BY;
   for (int k = tid; k < (BX + 2) * (BY + 2); k += BX * BY) {
     const int lx = k % (BX + 2), ly = k / (BX + 2);
-    int64_t gx = tx0 + lx - 1, gy = ty0 + ly - 1;
-    // periodic axes wrap; elsewhere the value is never used, any in-range node will do
-    gx = a.bc[0] == LBM_CDE_PERIODIC ? wrap_any(gx, a.nx) : (gx < 0 ? 0 : (gx >= a.nx ? a.nx - 1 : gx));
-    gy = a.bc[1] == LBM_CDE_PERIODIC ? wrap_any(gy, a.ny) : (gy < 0 ? 0 : (gy >= a.ny ? a.ny - 1 : gy));
-    sphi[ly][lx] = phis[gy * a.nx + gx];
+    const int64_t gx = halo_coord(tx0 + lx - 1, a.nx, px, lx_long);
+    const int64_t gy = halo_coord(ty0 + ly - 1, a.ny, py, ly_long);
+    const float ph = phis[gy * a.nx + gx];
+    float ux, uy;
+    velocity2<float>(a, gx, gy, ux, uy);
+    sphi[ly][lx] = ph;
+    sjx[ly][lx] = ph * ux;
+    sjy[ly][lx] = ph * uy;
   }
   __syncthreads();
   const int64_t x = tx0 + threadIdx.x, y = ty0 + threadIdx.y;
@@ -106,6 +122,7 @@ __global__ __launch_bounds__(BX * BY) void k_step_d2q9_split(const RunArgs a, un
   const __half* __restrict__ src = (const __half*)a.src;
   const float inv = (float)a.fp16_inv_scale;
   float f[9];
+  // f_i = f_eq_j(phi(s), u(s)) + h_j(s) / scale with f_eq_j = w phi + c e_j.(phi u)
 #define LBM_SPLIT_PULL(I, EX, EY)                                                        \
   {                                                                                      \
     int pop, dx, dy;                                                                     \
@@ -119,11 +136,17 @@ __global__ __launch_bounds__(BX * BY) void k_step_d2q9_split(const RunArgs a, un
       sx = (EX) == 1 ? wrap_m(x, a.nx) : (EX) == -1 ? wrap_p(x, a.nx) : x;               \
       sy = (EY) == 1 ? wrap_m(y, a.ny) : (EY) == -1 ? wrap_p(y, a.ny) : y;               \
     }                                                                                    \
-    const float ph = sphi[threadIdx.y + 1 + dy][threadIdx.x + 1 + dx];                   \
-    float ux, uy;                                                                        \
-    velocity2<float>(a, sx, sy, ux, uy);                                                 \
-    f[I] = feq_d2q9(pop, ph, ux, uy) +                                                   \
-           __half2float(src[(int64_t)pop * a.plane + sy * a.nx + sx]) * inv;             \
+    const int ly = threadIdx.y + 1 + dy, lx = threadIdx.x + 1 + dx;                      \
+    const float ph = sphi[ly][lx], jx = sjx[ly][lx], jy = sjy[ly][lx];                   \
+    float feq;                                                                           \
+    if (pop == 0) feq = ph * (5.0f / 9.0f);                                              \
+    else {                                                                               \
+      const int ex = (pop == 1 || pop == 5 || pop == 8) ? 1 : (pop == 3 || pop == 6 || pop == 7) ? -1 : 0; \
+      const int ey = (pop == 2 || pop == 5 || pop == 6) ? 1 : (pop == 4 || pop == 7 || pop == 8) ? -1 : 0; \
+      const float ej = (float)ex * jx + (float)ey * jy;                                  \
+      feq = ph * (1.0f / 18.0f) + ej * (pop <= 4 ? (1.0f / 3.0f) : (1.0f / 12.0f));      \
+    }                                                                                    \
+    f[I] = feq + __half2float(src[(int64_t)pop * a.plane + sy * a.nx + sx]) * inv;       \
   }
   LBM_SPLIT_PULL(0, 0, 0)
   LBM_SPLIT_PULL(1, 1, 0)
