@@ -171,8 +171,15 @@ class Workload:
         return self.D_field[(slice(None),) + np.ix_(*reversed([np.asarray(i) for i in idx]))]
 
     def phi_ref(self) -> float:
-        """Background level used by shifted storage: the mean of phi0."""
-        return float(self.phi0().mean())
+        """Background level used by shifted storage: the minimum of phi0.
+
+        Shifted storage keeps f - w phi_ref; the shift should remove the
+        uniform background (where every node would otherwise store the same
+        value and round the same way each step), which for hills on an empty
+        field is zero."""
+        if "phi_ref" in self.meta:
+            return float(self.meta["phi_ref"])
+        return float(self.phi0().min())
 
 
 def tensor_components(D: np.ndarray) -> np.ndarray:
@@ -425,6 +432,19 @@ def inverse_dfield(n: int = 512, ny: Optional[int] = None, n_ic: int = 10, steps
     return {"D_true": D_true, "D_pert": D_pert, "D_trial": D_trial, "ics": ics,
             "snap_every": snap_every, "ckpt_every": ckpt_every, "steps": steps,
             "u": np.asarray(u, np.float64), "fd_nodes": fd_nodes, "shape": (nx, ny)}
+
+
+def with_background(wl: Workload, level: float) -> Workload:
+    """The same workload on a uniform background: phi0 + level."""
+    spec = wl.phi0_spec
+
+    class _Shifted(type(spec)):
+        def window(self, idx):
+            return spec.window(idx) + level
+
+    shifted = _Shifted.__new__(_Shifted)
+    shifted.__dict__.update(spec.__dict__)
+    return dataclasses.replace(wl, phi0_spec=shifted, meta=dict(wl.meta, background=level))
 
 
 def with_steps(wl: Workload, steps: int) -> Workload:

@@ -106,3 +106,16 @@ def test_mixed_precisions_fall_back_to_separate_launches():
         ref, _ = O.run_workload(wl, steps=40)
         err = float(np.abs(s.phi(i).cpu().numpy() - ref).max() / np.abs(ref).max())
         assert err <= TOL["fp64" if i == 0 else "fp32"]
+
+
+def test_taylor_aris_ensemble_dispersion():
+    """The three cheapest channels of the seeded ensemble, run batched to
+    their own horizons: K / (D (1 + Pe^2/210)) - 1 within 1 %."""
+    from paper_1404_2363_amd.taylor_aris import run_ensemble
+    runs = sorted(W.taylor_aris_batch(), key=lambda r: r.nodes * r.steps)[:3]
+    res, info = run_ensemble(runs, "fp32", every=100)
+    for r in res:
+        print(f"h={r['h']} Pe={r['Pe']:.1f} tau={r['tau']:.2f} steps={r['steps']}: K/K_TA - 1 = {r['rel_err']:.4%}",
+              flush=True)
+        assert abs(r["rel_err"]) <= 1e-2, r
+    assert info["nonfinite"] == 0

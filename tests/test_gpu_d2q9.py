@@ -254,3 +254,16 @@ def test_autotuner_keeps_state_and_results(tmp_path, monkeypatch):
     s3.tune(3)
     assert len((tmp_path / "tune.txt").read_text().splitlines()) == 2
     s3.close()
+
+
+def test_shift_removes_background_rounding():
+    """On a field with a uniform background, storing f - w phi_ref with
+    phi_ref = the background is more accurate than storing f."""
+    base = W.cellular(nx=120, ny=90, steps=300, n_hills=5, sigma=8.0)
+    wl = W.with_background(base, 5.0)
+    ref, _ = O.run_workload(wl)
+    e_shift = rel_err(gpu_phi(wl, "fp32", 300), ref)
+    e_none = rel_err(gpu_phi(wl, "fp32", 300, phi_ref=0.0), ref)
+    print(f"fp32 on background 5: shifted {e_shift:.2e}, unshifted {e_none:.2e}", flush=True)
+    assert e_shift <= 1e-5
+    assert e_shift < e_none
