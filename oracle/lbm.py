@@ -324,8 +324,9 @@ class Problem:
     ----------
     lattice : "d2q9" | "d3q15"
     shape   : (nx, ny) or (nx, ny, nz)
-    walls   : per axis "periodic", "bounce" (halfway bounce-back, True) or
-              "specular" (halfway mirror) on both faces
+    walls   : per axis "periodic", "bounce" (halfway bounce-back, True),
+              "specular" (halfway mirror) or "node" (the plate rule of
+              Sec. 3.2, with the first and last node on the plates) on both faces
     u       : (dim, *grid) velocity at the nodes (steady)
     D       : constant (dim, dim) tensor, or per-node components (ncomp, *grid)
     model   : "A" (modified, the paper's method) or "B1" | "B2" | "B3"
@@ -354,6 +355,10 @@ class Problem:
         self.S = relaxation_matrix(self.lat, self.A, self.rates, self.heat, self.modified)
         # equilibrium moments per unit phi (m^eq is linear in phi for fixed u)
         self.E = equilibrium_moments(self.lat, model, np.ones(self.grid), self.u)
+        self.node_axes = [a for a, w in enumerate(self.walls) if w == "node"]
+        if self.node_axes and (self.lat.name != "d2q9" or len(self.node_axes) != 1
+                               or any(w != "periodic" for a, w in enumerate(self.walls) if a not in self.node_axes)):
+            raise ValueError("the plate rule is defined for D2Q9 with one plate axis and the other periodic")
         self._dest = [self._destinations(i) for i in range(self.lat.Q)]
 
     # -- helpers -------------------------------------------------------------
@@ -363,12 +368,14 @@ class Problem:
         Periodic axes wrap.  If x + e_i leaves the fluid across a wall:
         "bounce" reverses the whole velocity and keeps the node (halfway
         bounce-back); "specular" reverses only the normal component and keeps
-        the normal coordinate, moving on along the wall (halfway mirror)."""
+        the normal coordinate, moving on along the wall (halfway mirror);
+        "node" drops the population (population -1), its replacement is set
+        by ``stream`` from the plate rule."""
         dim = self.lat.dim
         coords = np.meshgrid(*[np.arange(n) for n in self.shape], indexing="ij")   # axis order x, y[, z]
         coords = [c.transpose(tuple(reversed(range(dim)))) for c in coords]        # to grid order
         e = self.lat.e[i, :dim]
-        crossed = {k: np.zeros(self.grid, dtype=bool) for k in ("bounce", "specular")}
+        crossed = {k: np.zeros(self.grid, dtype=bool) for k in ("bounce", "specular", "node")}
         per_axis_cross = []
         for a in range(dim):
             raw = coords[a] + e[a]
@@ -394,6 +401,7 @@ class Problem:
         vel = np.stack(vel, -1)
         table = {tuple(self.lat.e[j, :dim]): j for j in range(self.lat.Q)}
         pop = np.vectorize(lambda *v: table[v])(*[vel[..., a] for a in range(dim)]) if vel.size else vel
+        pop = np.where(crossed["node"], -1, pop)
         return np.asarray(pop, dtype=np.int64).ravel(), node.ravel()
 
     def _roll(self, arr: np.ndarray, e: np.ndarray, sign: int) -> np.ndarray:
@@ -421,12 +429,33 @@ class Problem:
         return np.tensordot(self.lat.Minv, m_post, axes=(1, 0))    # Eq. (14)
 
     def stream(self, fpost: np.ndarray) -> np.ndarray:
-        """Eq. (5) push: f_i(x + e_i) = f'_i(x), with the wall rule where x + e_i is solid."""
+        """Eq. (5) push: f_i(x + e_i) = f'_i(x), with the wall rule where x + e_i is solid.
+
+        On a "node" axis (Sec. 3.2) populations leaving the domain are lost,
+        and at the plate nodes each population pointing into the fluid is
+        then set to its mirror image (normal component reversed) at the same
+        node: f2 = f4, f5 = f8, f6 = f7 on the low plate, the reverse on the
+        high one."""
         out = np.zeros_like(fpost).reshape(self.lat.Q, -1)
         for i in range(self.lat.Q):
             pop, node = self._dest[i]
-            out[pop, node] = fpost[i].ravel()
-        return out.reshape(fpost.shape)
+            keep = pop >= 0
+            out[pop[keep], node[keep]] = fpost[i].ravel()[keep]
+        out = out.reshape(fpost.shape)
+        for a in self.node_axes:
+            ax = self.lat.dim - 1 - a                      # grid axis of coordinate a
+            for i in range(self.lat.Q):
+                ea = self.lat.e[i, a]
+                if ea == 0:
+                    continue
+                v = self.lat.e[i, :self.lat.dim].copy()
+                v[a] = -ea
+                j = int(np.where((self.lat.e[:, :self.lat.dim] == v).all(1))[0][0])
+                plate = 0 if ea > 0 else self.shape[a] - 1
+                sl = [slice(None)] * self.lat.dim
+                sl[ax] = plate
+                out[(i,) + tuple(sl)] = out[(j,) + tuple(sl)]
+        return out
 
     def step(self, f: np.ndarray) -> np.ndarray:
         return self.stream(self.collide(f))
@@ -450,6 +479,8 @@ class Problem:
 
     def stream_T(self, lam: np.ndarray) -> np.ndarray:
         """Transpose of ``stream`` (a permutation): (P^T lam)_i(x) = lam at the destination of (i, x)."""
+        if self.node_axes:
+            raise ValueError("no adjoint is defined for the plate rule")
         flat = lam.reshape(self.lat.Q, -1)
         out = np.empty_like(flat)
         for i in range(self.lat.Q):
@@ -478,12 +509,12 @@ class Problem:
 
 
 def _wall_kind(w) -> str:
-    """Boundary of one axis: "periodic", "bounce" (True) or "specular"."""
+    """Boundary of one axis: "periodic", "bounce" (True), "specular" or "node"."""
     if w is True or w == 1:
         return "bounce"
     if w is False or w == 0 or w is None:
         return "periodic"
-    if w in ("periodic", "bounce", "specular"):
+    if w in ("periodic", "bounce", "specular", "node"):
         return w
     raise ValueError(f"unknown wall kind {w!r}")
 

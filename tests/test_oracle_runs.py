@@ -239,3 +239,70 @@ def test_deviation_term_vanishes_for_varying_u():
     assert a1 <= 0.5 * a29, (a1, a29)       # modified model follows Eq. (1)
     assert b29 <= 0.2 * b1, (b29, b1)       # MRT-B3 follows Eq. (29)
     assert a1 < b1
+
+
+def _plate_vs_doubled(model, nx=10, ny=7, steps=40, axis=1):
+    """The plate rule (Sec. 3.2) on nodes 0..n-1 of one axis against the
+    periodic scheme on 2(n-1) nodes with data reflected evenly about node 0.
+
+    Reflection y -> -y maps population i to its mirror and commutes with the
+    collision when D_xy = 0 and u_y = 0 (u_x even in y), so the doubled
+    periodic run stays even; its populations arriving at y = 0 from y = -1
+    are then the mirrors of those arriving from y = +1, which is the plate
+    rule.  The two runs must agree to rounding."""
+    rng = np.random.default_rng(11)
+    n = (nx, ny)[axis]
+    m = 2 * (n - 1)
+    shape_p = (nx, ny)
+    shape_d = (nx, m) if axis == 1 else (m, ny)
+    idx = np.arange(m)
+    fold = np.minimum(idx, m - idx)                 # doubled coordinate -> plate coordinate
+    phi_p = 1.0 + rng.random((ny, nx))
+    prof = 0.08 * np.sin(np.pi * np.arange(n) / (n - 1)) * (1.0 + 0.5 * np.cos(2 * np.pi * np.arange(n) / (n - 1)))
+    u_p = np.zeros((2, ny, nx))
+    tang = 0 if axis == 1 else 1
+    if axis == 1:
+        u_p[tang] = prof[:, None]
+    else:
+        u_p[tang] = prof[None, :]
+    D = np.array([[0.09, 0.0], [0.0, 0.05]])
+    if axis == 1:
+        phi_d, u_d = phi_p[fold, :], u_p[:, fold, :]
+    else:
+        phi_d, u_d = phi_p[:, fold], u_p[:, :, fold]
+    walls = ["periodic", "periodic"]
+    walls[axis] = "node"
+    prob_p = O.Problem("d2q9", shape_p, walls, u_p, D, model=model)
+    prob_d = O.Problem("d2q9", shape_d, ("periodic", "periodic"), u_d, D, model=model)
+    fp, _ = prob_p.run(prob_p.equilibrium(phi_p), steps)
+    fd, _ = prob_d.run(prob_d.equilibrium(phi_d), steps)
+    a = O.phi_of(fp)
+    b = O.phi_of(fd)[:n, :] if axis == 1 else O.phi_of(fd)[:, :n]
+    return a, b, fp, fd, n
+
+
+@pytest.mark.parametrize("model", ["A", "B1", "B2", "B3"])
+@pytest.mark.parametrize("axis", [1, 0])
+def test_plate_rule_equals_even_doubled_periodic(model, axis):
+    a, b, fp, fd, n = _plate_vs_doubled(model, axis=axis)
+    np.testing.assert_allclose(a, b, rtol=0, atol=1e-13)
+    # every population, not only phi
+    fdn = fd[:, :n, :] if axis == 1 else fd[:, :, :n]
+    np.testing.assert_allclose(fp, fdn, rtol=0, atol=1e-13)
+
+
+def test_plate_rule_conserves_trapezoid_mass():
+    """The plate rows count half: sum' phi is the half-sum of the doubled
+    periodic domain's conserved total."""
+    rng = np.random.default_rng(3)
+    nx, ny = 9, 8
+    phi0 = rng.random((ny, nx))
+    u = np.zeros((2, ny, nx))
+    u[0] = 0.05 * np.sin(np.pi * np.arange(ny) / (ny - 1))[:, None]
+    prob = O.Problem("d2q9", (nx, ny), ("periodic", "node"), u, np.array([[0.1, 0.0], [0.0, 0.1]]), model="A")
+    w = np.ones(ny)
+    w[0] = w[-1] = 0.5
+    f = prob.equilibrium(phi0)
+    m0 = (phi0 * w[:, None]).sum()
+    f, _ = prob.run(f, 60)
+    np.testing.assert_allclose((O.phi_of(f) * w[:, None]).sum(), m0, rtol=1e-13)
