@@ -26,8 +26,9 @@
  * Streams
  *   Every call enqueues its GPU work on the stream given to lbm_cde_init()
  *   (a hipStream_t; NULL = the null stream) and returns without waiting,
- *   except lbm_cde_reduce() and lbm_cde_read_samples(), which copy results
- *   to host memory and wait for that stream.
+ *   except lbm_cde_init() (which waits for its initialisation), lbm_cde_reduce()
+ *   (which copies results to host memory) and lbm_cde_tune() (which times
+ *   launches); these wait for that stream.
  *
  * Errors
  *   Every function returns LBM_CDE_OK (0) or a negative status.  The text of
@@ -92,8 +93,23 @@ enum { LBM_CDE_FP64 = 0, LBM_CDE_FP32_SHIFTED = 1, LBM_CDE_FP16_SPLIT = 2, LBM_C
  *   SPECULAR     a mirror: only the velocity component normal to the wall is
  *                reversed, the population moves on along the wall; the
  *                halfway analog of the zero-flux plate rule f2 = f4,
- *                f5 = f8, f6 = f7 of Sec. 3.2. */
-enum { LBM_CDE_PERIODIC = 0, LBM_CDE_BOUNCE_BACK = 1, LBM_CDE_SPECULAR = 2 };
+ *                f5 = f8, f6 = f7 of Sec. 3.2.
+ *   NODE_MIRROR  the paper's plate rule of Sec. 3.2 (f2 = f4, f5 = f8, f6 = f7
+ *                on a bottom wall): the first and last nodes lie on the walls
+ *                and each population arriving from outside equals its mirror
+ *                image arriving at the same node.  D2Q9 only, on one axis with
+ *                every other axis periodic, at least 2 nodes across.  Not a
+ *                permutation, so no adjoint is built.  With D_xy = 0 and u
+ *                mirror-symmetric about each plate (e.g. parallel to it) the
+ *                run equals the even reflection of a periodic domain and
+ *                conserves sum phi with the plate rows weighted 1/2. */
+enum { LBM_CDE_PERIODIC = 0, LBM_CDE_BOUNCE_BACK = 1, LBM_CDE_SPECULAR = 2, LBM_CDE_NODE_MIRROR = 3 };
+
+/* Collision model (Sec. 3): MRT_A is the paper's modified model (S of
+ * Eq. 31, m_eq of Eq. 37) and the default; MRT_B1/B2/B3 are the unmodified
+ * anisotropic model (S of Eq. 24) with the equilibria of Eq. (38), (39) and
+ * (37).  The B models are D2Q9 only, FP64/FP32 storage, no adjoint. */
+enum { LBM_CDE_MRT_A = 0, LBM_CDE_MRT_B1 = 1, LBM_CDE_MRT_B2 = 2, LBM_CDE_MRT_B3 = 3 };
 
 /* Velocity field u(x) (steady):
  *   CONST      u_const[0..dim-1].
@@ -110,7 +126,9 @@ enum { LBM_CDE_U_CONST = 0, LBM_CDE_U_SEPARABLE = 1, LBM_CDE_U_FIELD = 2 };
  *   EXPLICIT    heat_rates[]. */
 enum { LBM_CDE_HEAT_LAMBDA_MIN = 0, LBM_CDE_HEAT_PAPER = 1, LBM_CDE_HEAT_EXPLICIT = 2 };
 
-/* Reductions (all FP64): */
+/* Reductions (all FP64).  Sums over nodes weight the nodes of an on-node
+ * plate (NODE_MIRROR) by 1/2, the quadrature that the plate rule conserves;
+ * every other node has weight 1. */
 enum {
   LBM_CDE_RED_MASS = 0,      /* out[0] = sum_x phi(x)                                   */
   LBM_CDE_RED_XMOMENTS = 1,  /* out[0..2] = S0, S1, S2 of phibar(x) = sum over y, z of
@@ -143,6 +161,7 @@ typedef struct lbm_cde_run_desc {
   double xref0, xref_drift; /* sampled x-moments use x_ref(t) = xref0 + xref_drift * t  */
   int64_t max_steps;        /* per-run step budget (< 0: unlimited); a run that has
                                used it is left unchanged by further steps               */
+  int32_t model;            /* LBM_CDE_MRT_A (0, default) | _MRT_B1 | _MRT_B2 | _MRT_B3    */
 } lbm_cde_run_desc;
 
 typedef struct lbm_cde* lbm_cde_handle;

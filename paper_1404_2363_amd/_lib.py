@@ -27,7 +27,8 @@ STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "ENOTSPD", -3: "EUNSTABLE", -4: "EHIP
 
 LBM_CDE_D2Q9, LBM_CDE_D3Q15 = 0, 1
 LBM_CDE_FP64, LBM_CDE_FP32_SHIFTED, LBM_CDE_FP16_SPLIT, LBM_CDE_FP16_SHIFTED = 0, 1, 2, 3
-LBM_CDE_PERIODIC, LBM_CDE_BOUNCE_BACK, LBM_CDE_SPECULAR = 0, 1, 2
+LBM_CDE_PERIODIC, LBM_CDE_BOUNCE_BACK, LBM_CDE_SPECULAR, LBM_CDE_NODE_MIRROR = 0, 1, 2, 3
+LBM_CDE_MRT_A, LBM_CDE_MRT_B1, LBM_CDE_MRT_B2, LBM_CDE_MRT_B3 = 0, 1, 2, 3
 LBM_CDE_U_CONST, LBM_CDE_U_SEPARABLE, LBM_CDE_U_FIELD = 0, 1, 2
 LBM_CDE_HEAT_LAMBDA_MIN, LBM_CDE_HEAT_PAPER, LBM_CDE_HEAT_EXPLICIT = 0, 1, 2
 LBM_CDE_RED_MASS, LBM_CDE_RED_XMOMENTS, LBM_CDE_RED_NONFINITE = 0, 1, 2
@@ -55,6 +56,7 @@ class lbm_cde_run_desc(ctypes.Structure):
         ("xref0", ctypes.c_double),
         ("xref_drift", ctypes.c_double),
         ("max_steps", ctypes.c_int64),
+        ("model", ctypes.c_int32),
     ]
 
 

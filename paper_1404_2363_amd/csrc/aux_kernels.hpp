@@ -39,7 +39,7 @@ __global__ __launch_bounds__(256) void k_init_d2q9(const RunArgs a, const double
   double u[3];
   velocity_at<R>(a, 2, x, y, 0, u);
   double f[9];
-  equilibrium_d2q9(f, phi0[node], u[0], u[1], a.phi_ref);
+  equilibrium_d2q9(f, phi0[node], u[0], u[1], a.phi_ref, a.model);
   R* dst = (R*)a.dst;
   for (int i = 0; i < 9; ++i) dst[i * a.plane + node] = (R)f[i];
 }
@@ -84,6 +84,22 @@ LBM_FORCEINLINE double node_phi(const RunArgs& a, int Q, int64_t node, int& nonf
   return s + a.phi_ref;
 }
 
+// Quadrature weight of a node in domain sums: nodes on an on-node plate
+// (the first and last node of a NODE_MIRROR axis) stand for half a cell, so
+// the weighted sum of phi is the quantity the plate rule conserves.
+LBM_FORCEINLINE double plate_weight(const RunArgs& a, int64_t node) {
+  double w = 1.0;
+  if (a.bc[0] == LBM_CDE_NODE_MIRROR) {
+    const int64_t x = node % a.nx;
+    if (x == 0 || x == a.nx - 1) w *= 0.5;
+  }
+  if (a.bc[1] == LBM_CDE_NODE_MIRROR) {
+    const int64_t y = (node / a.nx) % a.ny;
+    if (y == 0 || y == a.ny - 1) w *= 0.5;
+  }
+  return w;
+}
+
 // phi = sum_i f_i (+ phi_ref for shifted storage), FP64.
 template <typename S>
 __global__ __launch_bounds__(256) void k_moments(const RunArgs a, int Q, double* __restrict__ phi) {
@@ -107,7 +123,7 @@ __global__ __launch_bounds__(RED_THREADS) void k_reduce_partial(const RunArgs a,
   for (int64_t node = (int64_t)blockIdx.x * RED_THREADS + threadIdx.x; node < N;
        node += (int64_t)gridDim.x * RED_THREADS) {
     int nonfinite = 0;
-    const double phi = node_phi<S>(a, Q, node, nonfinite);
+    const double phi = node_phi<S>(a, Q, node, nonfinite) * plate_weight(a, node);
     bad += (double)nonfinite;
     if (kind == LBM_CDE_RED_XMOMENTS) {
       double d = (double)(node % a.nx) - x_ref;
@@ -173,7 +189,7 @@ __global__ __launch_bounds__(RED_THREADS) void k_batch_xmom_partial(const RunArg
        node += (int64_t)gridDim.x * RED_THREADS) {
     double phi = 0.0;
     for (int i = 0; i < Q; ++i) phi += (double)src[i * a.plane + node];
-    phi += a.phi_ref;
+    phi = (phi + a.phi_ref) * plate_weight(a, node);
     double d = (double)(node % a.nx) - x_ref;
     d -= nxd * floor(d / nxd + 0.5);
     s0 += phi;

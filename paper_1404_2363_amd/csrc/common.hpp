@@ -25,6 +25,7 @@ struct RunArgs {
   int64_t nx, ny, nz;
   int64_t plane;            // elements between two population planes
   int32_t bc[3];
+  int32_t model;            // LBM_CDE_MRT_A (modified) or an unmodified MRT-B variant
   int32_t u_kind;
   double u_const[3];
   const void* u_tab;        // SEPARABLE: per component: amp, X[nx], Y[ny], Z[nz] (type R)

@@ -19,8 +19,14 @@
 // Because M w = (1, -2, 2, 0, ...) equals m_eq(1, 0), the background cancels in
 // n except in the velocity moments: n1 = m1(g) + 2 phi_g, n2 = m2(g) - 2 phi_g,
 // n3 = m3(g) - phi ux, ... with phi = phi_g + phi_ref; and g' = g - M^-1 d.
-// Streaming and both wall rules map populations to populations of equal
+// Streaming and every wall rule map populations to populations of equal
 // weight, so the uniform shift is preserved.
+//
+// The unmodified models MRT-B1/B2/B3 (Sec. 3) use the same kernel: S of
+// Eq. (24) has no coupling of j to q (the c coefficients vanish), and the
+// equilibria of Eq. (38)/(39) add 3 phi u^2 to n1 and n2 and phi (ux^2 - uy^2),
+// phi ux uy to m7_eq, m8_eq.  For MRT-B1, m2_eq(phi, 0) = phi, and the shift
+// uses its own w = (4/9, 1/9 x 4, 1/36 x 4) so that n2 = m2(g) - phi_g again.
 #pragma once
 
 #include "common.hpp"
@@ -31,7 +37,9 @@ template <typename R>
 struct Rel2 {
   R s1, s2, s7, s8, s4, s6;
   R axx, axy, ayy;
-  R c34, c36, c54, c56;  // coupling coefficients of Eq. (31)
+  R c34, c36, c54, c56;  // coupling coefficients of Eq. (31); zero for the standard S (Eq. 24)
+  R nl;                  // 1 for the equilibria with u^2 terms (Eq. 38, 39), else 0
+  R c2;                  // m2_eq(phi, 0) / phi: 1 for Eq. (38), else 2
 };
 
 template <typename R>
@@ -46,10 +54,13 @@ LBM_FORCEINLINE Rel2<R> make_rel2(R axx, R axy, R ayy, R s4, R s6, const RunArgs
   r.axx = axx;
   r.axy = axy;
   r.ayy = ayy;
-  r.c34 = (axx * (R)0.5 - (R)1) * s4;
-  r.c36 = (axy * (R)0.5) * s6;
-  r.c54 = (axy * (R)0.5) * s4;
-  r.c56 = (ayy * (R)0.5 - (R)1) * s6;
+  const bool modified = a.model == LBM_CDE_MRT_A;
+  r.c34 = modified ? (axx * (R)0.5 - (R)1) * s4 : (R)0;
+  r.c36 = modified ? (axy * (R)0.5) * s6 : (R)0;
+  r.c54 = modified ? (axy * (R)0.5) * s4 : (R)0;
+  r.c56 = modified ? (ayy * (R)0.5 - (R)1) * s6 : (R)0;
+  r.nl = (a.model == LBM_CDE_MRT_B1 || a.model == LBM_CDE_MRT_B2) ? (R)1 : (R)0;
+  r.c2 = a.model == LBM_CDE_MRT_B1 ? (R)1 : (R)2;
   return r;
 }
 
@@ -86,10 +97,12 @@ LBM_FORCEINLINE void collide_d2q9(R (&f)[9], R ux, R uy, R phi_ref, const Rel2<R
   const R m6 = dy56 - (R)2 * dy24;
   const R m7 = f[1] - f[2] + f[3] - f[4];
   const R m8 = f[5] - f[6] + f[7] - f[8];
-  // non-equilibrium parts
+  // non-equilibrium parts (the u^2 terms only for the MRT-B1/B2 equilibria)
   const R jx = phi * ux, jy = phi * uy;
-  const R n1 = m1 + (R)2 * phig;
-  const R n2 = m2 - (R)2 * phig;
+  const R q = r.nl * phi;
+  const R u2 = ux * ux + uy * uy;
+  const R n1 = m1 + (R)2 * phig - (R)3 * q * u2;
+  const R n2 = m2 - r.c2 * phig + (R)3 * q * u2;
   const R n3 = m3 - jx;
   const R n4 = m4 + jx;
   const R n5 = m5 - jy;
@@ -101,8 +114,8 @@ LBM_FORCEINLINE void collide_d2q9(R (&f)[9], R ux, R uy, R phi_ref, const Rel2<R
   const R a4 = r.s4 * n4 * (R)(1.0 / 12.0);
   const R a5 = (r.axy * n3 + r.c54 * n4 + r.ayy * n5 + r.c56 * n6) * (R)(1.0 / 6.0);
   const R a6 = r.s6 * n6 * (R)(1.0 / 12.0);
-  const R a7 = r.s7 * m7 * (R)0.25;
-  const R a8 = r.s8 * m8 * (R)0.25;
+  const R a7 = r.s7 * (m7 - q * (ux * ux - uy * uy)) * (R)0.25;
+  const R a8 = r.s8 * (m8 - q * ux * uy) * (R)0.25;
   // f' = f - M^T a
   const R ax = -a1 - (R)2 * a2;          // common to the axis populations
   const R dg = (R)2 * a1 + a2;           // common to the diagonals
@@ -119,23 +132,41 @@ LBM_FORCEINLINE void collide_d2q9(R (&f)[9], R ux, R uy, R phi_ref, const Rel2<R
   f[8] -= dg + p3 - p5 - a8;
 }
 
-// f_eq(phi, u) - w phi_ref, in double (initialisation).
-LBM_FORCEINLINE void equilibrium_d2q9(double (&f)[9], double phi, double ux, double uy, double phi_ref) {
-  // M^-1 m_eq with m_eq = phi (1, -2, 2, ux, -ux, uy, -uy, 0, 0)
-  const double a0 = phi / 9.0, a1 = -2.0 * phi / 36.0, a2 = 2.0 * phi / 36.0;
+// f_eq(phi, u) of the model, in double: m_eq is Eq. (37) for MRT-A and
+// MRT-B3, Eq. (38) for MRT-B1 and Eq. (39) for MRT-B2.
+LBM_FORCEINLINE void feq_model_d2q9(double (&f)[9], double phi, double ux, double uy, int model) {
+  const bool nl = model == LBM_CDE_MRT_B1 || model == LBM_CDE_MRT_B2;
+  const double u2 = ux * ux + uy * uy;
+  const double e1 = nl ? phi * (-2.0 + 3.0 * u2) : -2.0 * phi;
+  const double e2 = (model == LBM_CDE_MRT_B1 ? phi : 2.0 * phi) - (nl ? 3.0 * phi * u2 : 0.0);
+  const double e7 = nl ? phi * (ux * ux - uy * uy) : 0.0;
+  const double e8 = nl ? phi * ux * uy : 0.0;
+  // M^-1 m_eq = M^T diag(1/norm^2) m_eq
+  const double a0 = phi / 9.0, a1 = e1 / 36.0, a2 = e2 / 36.0;
   const double a3 = phi * ux / 6.0, a4 = -phi * ux / 12.0;
   const double a5 = phi * uy / 6.0, a6 = -phi * uy / 12.0;
+  const double a7 = e7 / 4.0, a8 = e8 / 4.0;
   const double ax = a0 - a1 - 2.0 * a2, dg = a0 + 2.0 * a1 + a2;
   const double q3 = a3 - 2.0 * a4, q5 = a5 - 2.0 * a6, p3 = a3 + a4, p5 = a5 + a6;
-  f[0] = a0 - 4.0 * a1 + 4.0 * a2 - phi_ref * (5.0 / 9.0);
-  f[1] = ax + q3 - phi_ref / 18.0;
-  f[2] = ax + q5 - phi_ref / 18.0;
-  f[3] = ax - q3 - phi_ref / 18.0;
-  f[4] = ax - q5 - phi_ref / 18.0;
-  f[5] = dg + p3 + p5 - phi_ref / 18.0;
-  f[6] = dg - p3 + p5 - phi_ref / 18.0;
-  f[7] = dg - p3 - p5 - phi_ref / 18.0;
-  f[8] = dg + p3 - p5 - phi_ref / 18.0;
+  f[0] = a0 - 4.0 * a1 + 4.0 * a2;
+  f[1] = ax + q3 + a7;
+  f[2] = ax + q5 - a7;
+  f[3] = ax - q3 + a7;
+  f[4] = ax - q5 - a7;
+  f[5] = dg + p3 + p5 + a8;
+  f[6] = dg - p3 + p5 - a8;
+  f[7] = dg - p3 - p5 + a8;
+  f[8] = dg + p3 - p5 - a8;
+}
+
+// Stored initial populations f_eq(phi, u) - w phi_ref with w = f_eq(1, 0) of
+// the model (5/9, 1/18 x 8 for MRT-A/B2/B3; 4/9, 1/9 x 4, 1/36 x 4 for B1).
+LBM_FORCEINLINE void equilibrium_d2q9(double (&f)[9], double phi, double ux, double uy, double phi_ref,
+                                      int model = LBM_CDE_MRT_A) {
+  double w[9];
+  feq_model_d2q9(f, phi, ux, uy, model);
+  feq_model_d2q9(w, 1.0, 0.0, 0.0, model);
+  for (int i = 0; i < 9; ++i) f[i] -= w[i] * phi_ref;
 }
 
 // Velocity at node (x, y).
@@ -169,8 +200,11 @@ LBM_FORCEINLINE int pop_of_d2q9(int vx, int vy) {
 // Index (population plane * plane + node) that the pull of population (EX, EY)
 // reads at node (x, y), honouring each axis' boundary kind.  Periodic axes
 // wrap; if the source lies beyond a wall, bounce-back takes the opposite
-// population of the same node and the mirror takes the population with the
-// normal component reversed from the neighbour along the wall.
+// population of the same node, the halfway mirror takes the population with
+// the normal component reversed from the neighbour along the wall, and the
+// on-node mirror (Sec. 3.2: f2 = f4, f5 = f8, f6 = f7 at a bottom wall node)
+// takes that reversed population as it arrives at the wall node, i.e. from
+// the node's inner neighbour.
 template <int EX, int EY>
 LBM_FORCEINLINE int64_t pull_index_d2q9(const RunArgs& a, int64_t x, int64_t y) {
   int64_t sx = x - EX, sy = y - EY;
@@ -193,8 +227,10 @@ LBM_FORCEINLINE int64_t pull_index_d2q9(const RunArgs& a, int64_t x, int64_t y) 
     sx = x;
     sy = y;
   } else {
-    if (cx) { vx = -EX; sx = x; }
-    if (cy) { vy = -EY; sy = y; }
+    // mirror: at a halfway wall the source is the node itself, at an on-node
+    // wall (the wall passes through the first node) the node's inner neighbour
+    if (cx) { vx = -EX; sx = a.bc[0] == LBM_CDE_NODE_MIRROR ? x + EX : x; }
+    if (cy) { vy = -EY; sy = a.bc[1] == LBM_CDE_NODE_MIRROR ? y + EY : y; }
   }
   return (int64_t)pop_of_d2q9(vx, vy) * a.plane + sy * a.nx + sx;
 }

@@ -244,8 +244,24 @@ int validate(const lbm_cde_run_desc& d, int idx) {
     return fail_init(LBM_CDE_EINVAL, "run %d: grid too large", idx);
   const int dim = d.lattice == LBM_CDE_D2Q9 ? 2 : 3;
   for (int a = 0; a < dim; ++a)
-    if (d.bc[a] < LBM_CDE_PERIODIC || d.bc[a] > LBM_CDE_SPECULAR)
+    if (d.bc[a] < LBM_CDE_PERIODIC || d.bc[a] > LBM_CDE_NODE_MIRROR)
       return fail_init(LBM_CDE_EINVAL, "run %d: unknown boundary kind %d on axis %d", idx, d.bc[a], a);
+  if (d.model < LBM_CDE_MRT_A || d.model > LBM_CDE_MRT_B3)
+    return fail_init(LBM_CDE_EINVAL, "run %d: unknown collision model %d", idx, d.model);
+  int plates = 0, other_walls = 0;
+  for (int a = 0; a < dim; ++a) {
+    plates += d.bc[a] == LBM_CDE_NODE_MIRROR;
+    other_walls += d.bc[a] != LBM_CDE_NODE_MIRROR && d.bc[a] != LBM_CDE_PERIODIC;
+  }
+  const bool half16 = d.precision == LBM_CDE_FP16_SPLIT || d.precision == LBM_CDE_FP16_SHIFTED;
+  if (plates && (d.lattice != LBM_CDE_D2Q9 || plates > 1 || other_walls || half16))
+    return fail_init(LBM_CDE_EUNSUPPORTED,
+                     "run %d: the on-node plate rule is built for D2Q9, FP64/FP32, on one axis with the other periodic",
+                     idx);
+  if ((d.bc[0] == LBM_CDE_NODE_MIRROR && d.nx < 2) || (d.bc[1] == LBM_CDE_NODE_MIRROR && d.ny < 2))
+    return fail_init(LBM_CDE_EINVAL, "run %d: the plate rule needs at least 2 nodes across", idx);
+  if (d.model != LBM_CDE_MRT_A && (d.lattice != LBM_CDE_D2Q9 || half16))
+    return fail_init(LBM_CDE_EUNSUPPORTED, "run %d: the unmodified MRT-B models are built for D2Q9, FP64/FP32", idx);
   if (d.u_kind < LBM_CDE_U_CONST || d.u_kind > LBM_CDE_U_FIELD)
     return fail_init(LBM_CDE_EINVAL, "run %d: unknown velocity kind %d", idx, d.u_kind);
   if (d.u_kind == LBM_CDE_U_SEPARABLE && !d.u_tables)
@@ -411,6 +427,7 @@ RunArgs make_args(const lbm_cde* h, const Run& r, int parity) {
   a.nz = r.d.nz;
   a.plane = r.plane;
   for (int i = 0; i < 3; ++i) a.bc[i] = r.d.bc[i];
+  a.model = r.d.model;
   a.u_kind = r.d.u_kind;
   for (int i = 0; i < 3; ++i) a.u_const[i] = r.d.u_const[i];
   a.u_tab = r.utab;
@@ -942,6 +959,11 @@ int check_adjoint_run(lbm_cde* h, Run* r) {
   if (!r) return fail(h, LBM_CDE_EINVAL, "adjoint: bad handle or run");
   if (r->d.lattice != LBM_CDE_D2Q9 || r->half)
     return fail(h, LBM_CDE_EUNSUPPORTED, "adjoint: built for D2Q9 in FP64 or FP32 storage");
+  if (r->d.model != LBM_CDE_MRT_A)
+    return fail(h, LBM_CDE_EUNSUPPORTED, "adjoint: built for the modified model MRT-A");
+  for (int a = 0; a < 2; ++a)
+    if (r->d.bc[a] == LBM_CDE_NODE_MIRROR)
+      return fail(h, LBM_CDE_EUNSUPPORTED, "adjoint: the plate rule is not a permutation, no adjoint is built");
   if (r->d.heat_rule != LBM_CDE_HEAT_EXPLICIT)
     return fail(h, LBM_CDE_EUNSUPPORTED,
                 "adjoint: needs explicit heat-flux rates (the other rules make them depend on D)");

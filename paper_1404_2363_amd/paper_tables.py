@@ -1,0 +1,166 @@
+"""The paper's accuracy tables on the GPU path (FP64 storage).
+
+Tables 1-2 (Sec. 3.1): a Gaussian hill on [-1, 1]^2 (512^2 nodes,
+dx = dt = 1/256), the three D of Eq. (42), u = 0 (Table 1) and
+u = (0.05, 0.05) (Table 2), run to the time t_m at which the exact peak
+halves; Er_2 and Er_inf of Eq. (43) against the exact solution Eq. (41)
+(summed over periodic images).  Heat-flux rates s4 = s_xx, s6 = s_yy, the
+other rates s1 = s2 = 1.1, s7 = s8 = 1.2 as stated for Fig. 3.
+
+Tables 3-5 (Sec. 3.2): Taylor-Aris dispersion between on-node plates
+(W = 32 lattices, L = 4800, top-hat pulse); the longitudinal dispersion
+coefficient of Eq. (46)-(47) from the FP64 x-moments of the plate-weighted
+cross-section sum, sampled inside the captured graph every 100 steps, and
+Er of Eq. (48).  Er is reported where the convergence test of Eq. (49)
+first passes and at the end of the horizon.
+
+Every (case, model) pair of a table runs in one batched persistent launch.
+
+    python -m paper_1404_2363_amd.paper_tables [--tables 1 2 3 4 5]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import sys
+import time
+
+import numpy as np
+import torch
+
+from . import workloads as W
+from .solver import Solver
+
+MODELS = ("A", "B1", "B2", "B3")
+# (tau, Pe) cases of Tables 3, 4, 5.
+PLATE_TABLES = {3: (2.0, (2.0, 4.0, 8.0, 16.0)), 4: (1.0, (4.0, 8.0, 16.0, 32.0)),
+                5: (0.55, (16.0, 32.0, 64.0, 128.0))}
+HILL_TABLES = {1: (0.0, 0.0), 2: (0.05, 0.05)}
+
+
+def hill_exact(wl: W.Workload, t: float, images: int = 1) -> np.ndarray:
+    """Eq. (41) in lattice units with peak 1 at t = 0, summed over images."""
+    n = wl.shape[0]
+    sig = wl.meta["sigma0"]
+    D = np.asarray(wl.D, np.float64)
+    u = np.asarray(wl.u_const, np.float64)
+    S = sig * sig * np.eye(2) + 2.0 * t * D
+    Si = np.linalg.inv(S)
+    amp = sig * sig / math.sqrt(np.linalg.det(S))
+    xs = np.arange(n, dtype=np.float64)
+    X, Y = np.meshgrid(xs, xs)
+    cx, cy = wl.meta["centre"]
+    out = np.zeros((n, n))
+    for ix in range(-images, images + 1):
+        for iy in range(-images, images + 1):
+            rx = X - cx - u[0] * t + ix * n
+            ry = Y - cy - u[1] * t + iy * n
+            out += amp * np.exp(-0.5 * (Si[0, 0] * rx * rx + 2.0 * Si[0, 1] * rx * ry + Si[1, 1] * ry * ry))
+    return out
+
+
+def run_hill_tables(tables=(1, 2), models=MODELS, precision: str = "fp64", device: str = "cuda:0", n: int = 512):
+    runs, tags = [], []
+    for tab in tables:
+        for kind in W.PAPER_HILL_D:
+            for m in models:
+                runs.append(W.paper_hill(kind, HILL_TABLES[tab], n=n))
+                tags.append((tab, kind, m))
+    per_run = [{"model": m, "heat": "paper", "max_steps": int(r.steps), "phi_ref": 0.0}
+               for r, (_, _, m) in zip(runs, tags)]
+    s = Solver(runs, precision, device=device, per_run=per_run)
+    t0 = time.perf_counter()
+    s.step(max(int(r.steps) for r in runs))
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    out = []
+    for i, (r, (tab, kind, m)) in enumerate(zip(runs, tags)):
+        assert s.steps_done(i) == r.steps
+        phi = s.phi(i).cpu().numpy()
+        ex = hill_exact(r, float(r.steps))
+        out.append({"table": tab, "D": kind, "model": m, "steps": int(r.steps), "t_m": r.meta["t_m"],
+                    "Er2": float(np.sqrt(np.mean((phi - ex) ** 2))), "Erinf": float(np.abs(phi - ex).max()),
+                    "peak": float(phi.max())})
+    s.close()
+    lu = sum(r.nodes * r.steps for r in runs)
+    return out, {"wall_s": wall, "lattice_updates": lu}
+
+
+def plate_alpha_history(hist_run: np.ndarray, every: int) -> np.ndarray:
+    """alpha^L at the sample times from consecutive variances (Eq. 46-47):
+    alpha_k = (sigma^2(t_{k+1}) - sigma^2(t_k)) / (2 every)."""
+    S0, S1, S2 = hist_run[:, 0], hist_run[:, 1], hist_run[:, 2]
+    var = S2 / S0 - (S1 / S0) ** 2
+    return np.diff(var) / (2.0 * every)
+
+
+def run_plate_tables(tables=(3, 4, 5), models=MODELS, precision: str = "fp64", every: int = 100,
+                     device: str = "cuda:0", chunk_rows: int = 100, progress: bool = False, rates=None):
+    runs, tags = [], []
+    for tab in tables:
+        tau, pes = PLATE_TABLES[tab]
+        for Pe in pes:
+            for m in models:
+                runs.append(W.plate_channel(tau, Pe, name=f"plate_tau{tau}_Pe{Pe}_{m}"))
+                tags.append((tab, tau, Pe, m))
+    per_run = []
+    for r, (_, tau, Pe, m) in zip(runs, tags):
+        d = {"heat": [1.0 / tau] * 2, "max_steps": int(r.steps), "xref0": r.meta["x0"],
+             "xref_drift": r.meta["U_node_mean"], "model": m, "phi_ref": 0.0}
+        if rates is not None:
+            d["rates"] = rates
+        per_run.append(d)
+    s = Solver(runs, precision, device=device, per_run=per_run)
+    rows = max(int(r.steps) for r in runs) // every
+    hist = torch.zeros((rows, len(runs), 3), dtype=torch.float64, device=device)
+    t0 = time.perf_counter()
+    done = 0
+    while done < rows:
+        k = min(chunk_rows, rows - done)
+        s.run_sampled(k * every, every, hist)
+        done += k
+        if progress:
+            torch.cuda.synchronize()
+            print(f"plates: {done}/{rows} samples, {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    nonfinite = sum(s.nonfinite(i) for i in range(len(runs)))
+    s.close()
+    h = hist.cpu().numpy()
+    out = []
+    for i, (r, (tab, tau, Pe, m)) in enumerate(zip(runs, tags)):
+        a = plate_alpha_history(h[: int(r.steps) // every, i], every)
+        ana = r.meta["K"]
+        conv = next((k for k in range(len(a) - 1) if abs(a[k + 1] - a[k]) <= 1e-6 * abs(a[k])), None)
+        out.append({"table": tab, "tau": tau, "Pe": Pe, "model": m, "steps": int(r.steps),
+                    "alpha_end": float(a[-1]), "alpha_analytic": ana,
+                    "Er_end": float(abs(a[-1] - ana) / ana), "signed_end": float((a[-1] - ana) / ana),
+                    "t_eq49": None if conv is None else int((conv + 2) * every),
+                    "Er_eq49": None if conv is None else float(abs(a[conv + 1] - ana) / ana),
+                    "drift_last": float(abs(a[-1] - a[-2]) / abs(a[-2]))})
+    lu = sum(r.nodes * r.steps for r in runs)
+    return out, {"wall_s": wall, "lattice_updates": lu, "nonfinite": nonfinite}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--tables", type=int, nargs="*", default=[1, 2, 3, 4, 5])
+    args = ap.parse_args()
+    hill = [t for t in args.tables if t in HILL_TABLES]
+    plate = [t for t in args.tables if t in PLATE_TABLES]
+    if hill:
+        res, info = run_hill_tables(hill)
+        for r in res:
+            print(json.dumps(r), flush=True)
+        print(json.dumps({"hill": info}), flush=True)
+    if plate:
+        res, info = run_plate_tables(plate, progress=True)
+        for r in res:
+            print(json.dumps(r), flush=True)
+        print(json.dumps({"plates": info}), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -16,7 +16,8 @@ from . import _lib as L
 PRECISIONS = {"fp64": L.LBM_CDE_FP64, "fp32": L.LBM_CDE_FP32_SHIFTED, "fp16": L.LBM_CDE_FP16_SPLIT,
               "fp16_literal": L.LBM_CDE_FP16_SHIFTED}
 WALLS = {"periodic": L.LBM_CDE_PERIODIC, "bounce": L.LBM_CDE_BOUNCE_BACK, "specular": L.LBM_CDE_SPECULAR,
-         False: L.LBM_CDE_PERIODIC, True: L.LBM_CDE_BOUNCE_BACK}
+         "node": L.LBM_CDE_NODE_MIRROR, False: L.LBM_CDE_PERIODIC, True: L.LBM_CDE_BOUNCE_BACK}
+MODELS = {"A": L.LBM_CDE_MRT_A, "B1": L.LBM_CDE_MRT_B1, "B2": L.LBM_CDE_MRT_B2, "B3": L.LBM_CDE_MRT_B3}
 LATTICES = {"d2q9": L.LBM_CDE_D2Q9, "d3q15": L.LBM_CDE_D3Q15}
 Q_OF = {"d2q9": 9, "d3q15": 15}
 
@@ -33,8 +34,10 @@ def _heat(desc, heat):
 
 def make_desc(wl, precision: str = "fp64", device="cuda:0", heat="lambda_min", rates=None,
               phi_ref: Optional[float] = None, max_steps: int = -1, xref0: float = 0.0,
-              xref_drift: float = 0.0, fp16_scale: float = 0.0):
-    """Descriptor of one workload, plus the objects that must outlive init."""
+              xref_drift: float = 0.0, fp16_scale: float = 0.0, model: str = "A"):
+    """Descriptor of one workload, plus the objects that must outlive init.
+
+    ``model`` is "A" (the modified model) or "B1" | "B2" | "B3" (unmodified)."""
     keep = []
     d = L.lbm_cde_run_desc()
     d.lattice = LATTICES[wl.lattice]
@@ -74,6 +77,7 @@ def make_desc(wl, precision: str = "fp64", device="cuda:0", heat="lambda_min", r
     d.fp16_scale = float(fp16_scale)
     d.xref0, d.xref_drift = float(xref0), float(xref_drift)
     d.max_steps = int(max_steps)
+    d.model = MODELS[model]
     return d, keep
 
 

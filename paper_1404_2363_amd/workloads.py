@@ -24,7 +24,11 @@ Workloads (shapes and distributions follow the paper's tests, Sec. 3):
                       64 random Gaussian hills (the spatially varying u the
                       paper's deviation-term argument is about, Sec. 2).
   taylor_aris_batch   Sec. 3.2 analog: 64 plane Poiseuille channels with
-                      bounce-back walls, uneven gaps h, Pe and tau.
+                      halfway mirror walls, uneven gaps h, Pe and tau.
+  plate_channel       Sec. 3.2 as printed: W = 32 lattices between on-node
+                      plates, L = 150 W, top-hat pulse, u_x = 4Uy(W-y)/W^2.
+  paper_hill          Sec. 3.1 as printed: [-1, 1]^2 on 512^2 nodes,
+                      dx = dt = 1/256, sigma0 = 0.05, D of Eq. (42).
   sine3d              Appendix A analog: 256^3 D3Q15, 3D sine flow, random D.
   inverse_dfield      512^2 periodic, constant u, smooth per-node D field,
                       10 Gaussian-hill initial conditions.
@@ -378,6 +382,77 @@ def taylor_aris_batch(n_runs: int = 64, nx: int = 4096, seed_id: int = 2, u_max_
             continue
         runs.append(taylor_aris_channel(h, Pe, tau, nx=nx, name=f"taylor_aris_{len(runs)}", wall=wall))
     return runs
+
+
+# D x 10^4 of Eq. (42): isotropic, diagonal anisotropic, full anisotropic.
+PAPER_HILL_D = {"isotropic": ((2.0, 0.0), (0.0, 2.0)), "diagonal": ((1.0, 0.0), (0.0, 4.0)),
+                "full": ((1.0, 1.0), (1.0, 4.0))}
+
+
+def paper_hill(kind: str = "isotropic", u=(0.0, 0.0), n: int = 512) -> Workload:
+    """Gaussian hill of Sec. 3.1: the domain [-1, 1]^2 on n^2 periodic nodes
+    x_i = -1 + i dx with dx = dt = 2/n (1/256 for n = 512), peak 1 at the
+    origin (phi0 = 2 pi sigma0^2 in Eq. 40, sigma0 = 0.05), D of Eq. (42) and
+    a constant u, all converted to lattice units (D dt/dx^2, u dt/dx).
+
+    meta["t_m"] is the time at which the exact peak halves,
+    sigma0^2 / sqrt(det(sigma0^2 I + 2 D t)) = 1/2, and meta["steps"] its
+    nearest step."""
+    dx = 2.0 / n
+    dt = dx
+    sig = 0.05 / dx
+    D = np.asarray(PAPER_HILL_D[kind], np.float64) * 1e-4 * dt / dx ** 2
+    u_lat = np.asarray(u, np.float64) * dt / dx
+    # det(s^2 I + 2 D t) = 4 s^4  ->  4 det(D) t^2 + 2 s^2 tr(D) t - 3 s^4 = 0
+    a, b, c = 4.0 * np.linalg.det(D), 2.0 * sig ** 2 * np.trace(D), -3.0 * sig ** 4
+    t_m = (-b + math.sqrt(b * b - 4.0 * a * c)) / (2.0 * a) if a > 0 else -c / b
+    centre = np.array([[n / 2.0, n / 2.0]])
+    spec = GaussianSum(centre, np.ones(1), np.array([sig]), (float(n), float(n)))
+    steps = int(round(t_m))
+    return Workload(f"paper_hill_{kind}", "d2q9", (n, n), ("periodic", "periodic"), steps, spec,
+                    D=D, u_const=u_lat, meta={"kind": kind, "sigma0": sig, "t_m": t_m, "centre": (n / 2.0, n / 2.0),
+                                              "phi_ref": 0.0})
+
+
+class TopHatX:
+    """phi0 = 1 on the nodes with lo <= x <= hi, 0 elsewhere, uniform in y."""
+
+    def __init__(self, lo: float, hi: float):
+        self.lo, self.hi = float(lo), float(hi)
+
+    def window(self, idx):
+        x = np.asarray(idx[0], dtype=np.float64)
+        row = ((x >= self.lo) & (x <= self.hi)).astype(np.float64)
+        return np.repeat(row[None, :], len(idx[1]), axis=0)
+
+
+def plate_channel(tau: float, Pe: float, W_lat: int = 32, length: int = 150, name: str = "plate_channel",
+                  steps: Optional[int] = None) -> Workload:
+    """Taylor-Aris set-up of Sec. 3.2: the gap W is W_lat lattices with the
+    plates on the first and last node (ny = W_lat + 1, walls "node"), the
+    length L = length * W_lat nodes (periodic), u_x = 4 U y (W - y) / W^2,
+    D = alpha I with alpha = (tau - 1/2)/3 (dx = dt = 1 in lattice units),
+    U from Pe = 2 U W / (3 alpha), and a top-hat pulse on x in [0.197 L, 0.203 L].
+
+    The default horizon lets the slowest transient that a y-symmetric pulse
+    excites, the second plate mode with rate 4 pi^2 alpha / W^2, decay by
+    e^-25 (rounded up to 100 steps)."""
+    nx, ny = length * W_lat, W_lat + 1
+    alpha = (tau - 0.5) / 3.0
+    U = 3.0 * alpha * Pe / (2.0 * W_lat)
+    y = np.arange(ny, dtype=np.float64)
+    prof = 4.0 * y * (W_lat - y) / (W_lat * W_lat)
+    wy = np.ones(ny)
+    wy[0] = wy[-1] = 0.5
+    u_node_mean = float(U * (prof * wy).sum() / wy.sum())
+    u_sep = SeparableU(np.array([U, 0.0]), [[np.ones(nx), prof, np.ones(1)], [np.ones(nx), np.zeros(ny), np.ones(1)]])
+    lam = 4.0 * math.pi ** 2 * alpha / W_lat ** 2
+    horizon = int(math.ceil(25.0 / lam / 100.0)) * 100
+    lo, hi = 0.197 * nx, 0.203 * nx
+    return Workload(name, "d2q9", (nx, ny), ("periodic", "node"), horizon if steps is None else steps,
+                    TopHatX(lo, hi), D=alpha * np.eye(2), u_sep=u_sep,
+                    meta={"tau": tau, "Pe": Pe, "W": W_lat, "alpha": alpha, "U": U, "U_node_mean": u_node_mean,
+                          "K": alpha * (1.0 + Pe * Pe / 210.0), "x0": 0.5 * (lo + hi), "phi_ref": 0.0})
 
 
 # ---- inverse problem with a per-node D field ------------------------------

@@ -52,7 +52,7 @@ def test_workspace_bytes_layout():
 
 
 @pytest.mark.parametrize("field,value", [("nx", 0), ("ny", -3), ("nz", 2), ("lattice", 7), ("precision", 9),
-                                         ("u_kind", 5), ("heat_rule", 4)])
+                                         ("u_kind", 5), ("heat_rule", 4), ("model", 4), ("model", -1)])
 def test_invalid_descriptors_rejected(field, value):
     d, keep = _desc(**{field: value})
     with pytest.raises(L.LbmCdeError) as e:
@@ -63,7 +63,7 @@ def test_invalid_descriptors_rejected(field, value):
 
 def test_bad_boundary_and_missing_tables():
     d, keep = _desc()
-    d.bc[1] = 3
+    d.bc[1] = 4
     with pytest.raises(L.LbmCdeError):
         L.lbm_cde_workspace_bytes([d])
     d, keep = _desc()
@@ -77,3 +77,59 @@ def test_null_arguments():
     assert lib.lbm_cde_workspace_bytes(None, 1, None) == L.LBM_CDE_EINVAL
     assert lib.lbm_cde_step(None, 1) == L.LBM_CDE_EINVAL
     assert lib.lbm_cde_destroy(None) == L.LBM_CDE_EINVAL
+
+
+def _plate_desc(**over):
+    d, keep = _desc(**over)
+    d.bc[0], d.bc[1] = L.LBM_CDE_PERIODIC, L.LBM_CDE_NODE_MIRROR
+    return d, keep
+
+
+def test_plate_rule_and_models_accepted():
+    for model in (L.LBM_CDE_MRT_A, L.LBM_CDE_MRT_B1, L.LBM_CDE_MRT_B2, L.LBM_CDE_MRT_B3):
+        for prec in (L.LBM_CDE_FP64, L.LBM_CDE_FP32_SHIFTED):
+            d, keep = _plate_desc(model=model, precision=prec)
+            assert L.lbm_cde_workspace_bytes([d]) > 0
+    d, keep = _plate_desc()
+    d.bc[0], d.bc[1] = L.LBM_CDE_NODE_MIRROR, L.LBM_CDE_PERIODIC
+    assert L.lbm_cde_workspace_bytes([d]) > 0
+
+
+@pytest.mark.parametrize("case", ["both_axes", "other_wall", "fp16", "fp16_literal", "d3q15", "thin"])
+def test_plate_rule_limits(case):
+    """The plate rule is built for D2Q9 in FP64/FP32 storage, on one axis with
+    the other periodic and at least 2 nodes across."""
+    d, keep = _plate_desc()
+    code = L.LBM_CDE_EUNSUPPORTED
+    if case == "both_axes":
+        d.bc[0] = L.LBM_CDE_NODE_MIRROR
+    elif case == "other_wall":
+        d.bc[0] = L.LBM_CDE_SPECULAR
+    elif case == "fp16":
+        d.precision = L.LBM_CDE_FP16_SPLIT
+    elif case == "fp16_literal":
+        d.precision = L.LBM_CDE_FP16_SHIFTED
+    elif case == "d3q15":
+        d.lattice, d.nz = L.LBM_CDE_D3Q15, 4
+        d.bc[2] = L.LBM_CDE_PERIODIC
+    elif case == "thin":
+        d.ny = 1
+        code = L.LBM_CDE_EINVAL
+    with pytest.raises(L.LbmCdeError) as e:
+        L.lbm_cde_workspace_bytes([d])
+    assert e.value.code == code, L.lbm_cde_last_error(None)
+
+
+@pytest.mark.parametrize("precision", [L.LBM_CDE_FP16_SPLIT, L.LBM_CDE_FP16_SHIFTED])
+def test_unmodified_models_need_wide_storage(precision):
+    d, keep = _desc(model=L.LBM_CDE_MRT_B1, precision=precision)
+    with pytest.raises(L.LbmCdeError) as e:
+        L.lbm_cde_workspace_bytes([d])
+    assert e.value.code == L.LBM_CDE_EUNSUPPORTED
+
+
+def test_unmodified_models_are_d2q9_only():
+    d, keep = _desc(model=L.LBM_CDE_MRT_B3, lattice=L.LBM_CDE_D3Q15, nz=4)
+    with pytest.raises(L.LbmCdeError) as e:
+        L.lbm_cde_workspace_bytes([d])
+    assert e.value.code == L.LBM_CDE_EUNSUPPORTED
