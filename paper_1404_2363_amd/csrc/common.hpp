@@ -38,6 +38,10 @@ struct RunArgs {
   double s[15];             // s[k] by moment index (flux-row entries unused)
   double A[3][3];           // flux block s_ab
   double heat[3];           // s4, s6, s8
+  // the D2Q9 FP32 relaxation coefficients of a constant-D run, rounded on the
+  // host exactly as the kernels' own FP32 set-up rounds them: s1 s2 s7 s8 s4
+  // s6 axx axy ayy c34 c36 c54 c56 nl c2 (the FP16 split kernels read these)
+  float relf[16];
   int32_t xcd_remap;        // block order (see tile_of_block)
   int32_t active;           // 0: run has used its step budget
   int64_t max_steps;        // step budget (< 0: unlimited), used by batched launches

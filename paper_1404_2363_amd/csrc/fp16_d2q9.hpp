@@ -4,8 +4,9 @@
 // non-equilibrium part of the post-collision populations,
 // h_i = half(2^k (p_i - f_eq_i(phi, u))).  The pull step rebuilds each
 // incoming population at its source node s as f_eq_j(phi(s), u(s)) + 2^-k h_j(s)
-// (j = i, or the population the wall rule takes), collides in FP32 and splits
-// the result again; 4 + 18 bytes are read and written per node.  phi, phi ux
+// (j = i, or the population the wall rule takes), collides in FP32 and keeps
+// the new non-equilibrium part, computed in moment space as M^-1 (n - S n);
+// 4 + 18 bytes are read and written per node.  phi, phi ux
 // and phi uy of a tile and its one-node halo are staged through LDS, so each
 // phi is fetched from memory about (BY + 2) / BY times instead of nine and u
 // is evaluated once per node of the halo tile instead of at nine sources.
@@ -35,6 +36,24 @@ LBM_FORCEINLINE float feq_d2q9(int i, float phi, float ux, float uy) {
   return i <= 4 ? phi * (1.0f / 18.0f + eu * (1.0f / 3.0f)) : phi * (1.0f / 18.0f + eu * (1.0f / 12.0f));
 }
 
+// FP32 rest weights of the split rebuild, 1/18 and 5/9 to 6e-8 and chosen so
+// that kW0 + 8 kW1 == 1 exactly: the stored part h sums to zero over a node,
+// so the rebuilt populations carry exactly phi times the sum of these
+// weights, and weights rounded independently (5/9 and 1/18 each to nearest)
+// would add 3e-8 phi per node and step.
+constexpr float kW1 = 0x1.c71c7p-5f;  // 0.05555555224...
+constexpr float kW0 = 0x1.1c71c8p-1f;  // 0.55555558204... = 1 - 8 kW1
+static_assert(kW0 + 8.0f * kW1 == 1.0f, "split rest weights must sum to one");
+
+// f_eq of a moving population from phi and e.(phi u) at its node, in one
+// fixed rounding order (both split kernels use it, so their results are
+// bitwise equal): c = 1/3 on the axes, 1/12 on the diagonals.
+LBM_FORCEINLINE float feq_moving(float ph, float ej, float c) { return __builtin_fmaf(ej, c, ph * kW1); }
+
+// e.(phi u) with e = (ex, ey), ex, ey in {-1, 0, 1}: exact for one nonzero
+// component, one rounding for two.
+LBM_FORCEINLINE float e_dot_j(float ex, float ey, float jx, float jy) { return __builtin_fmaf(ey, jy, ex * jx); }
+
 // Scale, round and saturate to half; flags an out-of-range value.
 LBM_FORCEINLINE __half to_half(float v, float scale, bool& over) {
   float s = v * scale;
@@ -43,6 +62,13 @@ LBM_FORCEINLINE __half to_half(float v, float scale, bool& over) {
     s = s != s ? 0.0f : (s > 0.0f ? kHalfMax : -kHalfMax);
   }
   return __float2half_rn(s);
+}
+
+// Already scaled value to half: clamped to the half range (finite values
+// saturate); the largest magnitude seen is kept for the overflow flag.
+LBM_FORCEINLINE __half to_half_clamped(float s, float& mx) {
+  mx = fmaxf(mx, fabsf(s));
+  return __float2half_rn(__builtin_amdgcn_fmed3f(s, -kHalfMax, kHalfMax));
 }
 
 LBM_FORCEINLINE int64_t wrap_any(int64_t i, int64_t n) {
@@ -139,14 +165,14 @@ __global__ __launch_bounds__(BX * BY) void k_step_d2q9_split(const RunArgs a, un
     const int ly = threadIdx.y + 1 + dy, lx = threadIdx.x + 1 + dx;                      \
     const float ph = sphi[ly][lx], jx = sjx[ly][lx], jy = sjy[ly][lx];                   \
     float feq;                                                                           \
-    if (pop == 0) feq = ph * (5.0f / 9.0f);                                              \
+    if (pop == 0) feq = ph * kW0;                                                        \
     else {                                                                               \
       const int ex = (pop == 1 || pop == 5 || pop == 8) ? 1 : (pop == 3 || pop == 6 || pop == 7) ? -1 : 0; \
       const int ey = (pop == 2 || pop == 5 || pop == 6) ? 1 : (pop == 4 || pop == 7 || pop == 8) ? -1 : 0; \
-      const float ej = (float)ex * jx + (float)ey * jy;                                  \
-      feq = ph * (1.0f / 18.0f) + ej * (pop <= 4 ? (1.0f / 3.0f) : (1.0f / 12.0f));      \
+      const float ej = e_dot_j((float)ex, (float)ey, jx, jy);                            \
+      feq = feq_moving(ph, ej, pop <= 4 ? (1.0f / 3.0f) : (1.0f / 12.0f));               \
     }                                                                                    \
-    f[I] = feq + __half2float(src[(int64_t)pop * a.plane + sy * a.nx + sx]) * inv;       \
+    f[I] = __builtin_fmaf(__half2float(src[(int64_t)pop * a.plane + sy * a.nx + sx]), inv, feq); \
   }
   LBM_SPLIT_PULL(0, 0, 0)
   LBM_SPLIT_PULL(1, 1, 0)
@@ -161,15 +187,142 @@ __global__ __launch_bounds__(BX * BY) void k_step_d2q9_split(const RunArgs a, un
   float ux, uy;
   velocity2<float>(a, x, y, ux, uy);
   const float phi = f[0] + f[1] + f[2] + f[3] + f[4] + f[5] + f[6] + f[7] + f[8];
-  collide_d2q9<float>(f, ux, uy, 0.0f, const_rel2<float>(a));
+  float h[9];
+  collide_neq_d2q9<float>(f, ux, uy, host_rel2(a), (float)a.fp16_scale, h);
   const int64_t node = y * a.nx + x;
   ((float*)a.dst_phi)[node] = phi;
   __half* __restrict__ dst = (__half*)a.dst;
-  const float scale = (float)a.fp16_scale;
-  bool over = false;
+  float mx = 0.0f;
 #pragma unroll
-  for (int i = 0; i < 9; ++i) dst[i * a.plane + node] = to_half(f[i] - feq_d2q9(i, phi, ux, uy), scale, over);
-  if (over) overflow[0] = 1u;
+  for (int i = 0; i < 9; ++i) dst[i * a.plane + node] = to_half_clamped(h[i], mx);
+  if (!(mx <= kHalfMax)) overflow[0] = 1u;
+}
+
+// x mod n for x in [0, 3n) (one or two conditional subtractions).
+LBM_FORCEINLINE uint32_t mod3n(uint32_t x, uint32_t n) {
+  x = x >= n ? x - n : x;
+  return x >= n ? x - n : x;
+}
+
+// Split storage on a fully periodic grid with nx >= BX, ny >= BY and every
+// byte offset below 4 GiB (phi plane and the nine half planes): every access is a
+// uniform base plus a 32-bit byte offset, the tile's halo indices need at
+// most two conditional subtractions, every load is issued before the one
+// barrier, and the stored part comes straight out of the moment-space
+// collision, already scaled.  A separable u is multiplied in the same order
+// as velocity2, so both kernels give bitwise the same state.  NT: streaming
+// stores.
+template <int BX, int BY, bool NT>
+__global__ __launch_bounds__(BX * BY) void k_step_d2q9_split_p(const RunArgs a, unsigned* __restrict__ overflow) {
+  constexpr int NT_ = BX * BY, HW = BX + 2, HN = (BX + 2) * (BY + 2);
+  constexpr int NH = (HN + NT_ - 1) / NT_;  // halo entries per thread
+  __shared__ float sphi[BY + 2][BX + 2], sjx[BY + 2][BX + 2], sjy[BY + 2][BX + 2];
+  const uint32_t nx = (uint32_t)a.nx, ny = (uint32_t)a.ny;
+  const uint32_t ntx = (nx + BX - 1) / BX;
+  const uint32_t b = (uint32_t)tile_of_block(blockIdx.x, gridDim.x, ntx, a.xcd_remap);
+  const uint32_t tx0 = (b % ntx) * BX, ty0 = (b / ntx) * BY;
+  const char* __restrict__ phis = (const char*)a.src_phi;
+  const int tid = threadIdx.y * BX + threadIdx.x;
+  const bool sep = a.u_kind == U_SEPARABLE;
+  const char* __restrict__ tb = (const char*)a.u_tab;
+  const uint32_t tstride = (1u + nx + ny + 1u) * 4u;  // bytes per velocity component table
+  const float ax0 = sep ? *(const float*)tb : 0.0f, ay0 = sep ? *(const float*)(tb + tstride) : 0.0f;
+  const float zx = sep ? *(const float*)(tb + (1u + nx + ny) * 4u) : 0.0f;
+  const float zy = sep ? *(const float*)(tb + tstride + (1u + nx + ny) * 4u) : 0.0f;
+  const float cux = (float)a.u_const[0], cuy = (float)a.u_const[1];
+  // Loads in the order their results are needed, all issued before the first
+  // wait: phi and the velocity factors of the tile and its halo, then the nine
+  // stored halves of this thread's node (waited for after the barrier).
+  float hphi[NH], hx[NH], hy[NH], vx[NH], vy[NH];
+#pragma unroll
+  for (int j = 0; j < NH; ++j) {
+    const int k = min(tid + j * NT_, HN - 1);
+    const uint32_t lx = (uint32_t)k % HW, ly = (uint32_t)k / HW;
+    const uint32_t gx = mod3n(tx0 + lx + nx - 1u, nx), gy = mod3n(ty0 + ly + ny - 1u, ny);
+    hphi[j] = *(const float*)(phis + (gy * nx + gx) * 4u);
+    hx[j] = hy[j] = vx[j] = vy[j] = 0.0f;
+    if (sep) {
+      hx[j] = *(const float*)(tb + (1u + gx) * 4u);
+      vx[j] = *(const float*)(tb + (1u + nx + gy) * 4u);
+      hy[j] = *(const float*)(tb + tstride + (1u + gx) * 4u);
+      vy[j] = *(const float*)(tb + tstride + (1u + nx + gy) * 4u);
+    }
+  }
+  const uint32_t xr = tx0 + threadIdx.x, yr = ty0 + threadIdx.y;
+  const bool active = xr < nx && yr < ny;
+  // threads past the grid edge read (and discard) a valid node: the loads stay
+  // unconditional, so the compiler issues all nine without waiting in between
+  const uint32_t x = active ? xr : 0u, y = active ? yr : 0u;
+  const uint32_t xm = x == 0 ? nx - 1u : x - 1u, xp = x + 1u == nx ? 0u : x + 1u;
+  const uint32_t rm = (y == 0 ? ny - 1u : y - 1u) * nx, r0 = y * nx, rp = (y + 1u == ny ? 0u : y + 1u) * nx;
+  const char* __restrict__ src = (const char*)a.src;
+  const uint32_t pb = (uint32_t)a.plane * 2u;  // bytes per plane
+  const uint32_t off[9] = {r0 + x, r0 + xm, rm + x, r0 + xp, rp + x, rm + xm, rm + xp, rp + xp, rp + xm};
+  __half raw[9];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) raw[i] = *(const __half*)(src + i * pb + off[i] * 2u);
+  // phi, phi ux, phi uy of the tile; u in velocity2's product order
+#pragma unroll
+  for (int j = 0; j < NH; ++j) {
+    const int k = tid + j * NT_;
+    if (k < HN) {
+      const float ux = sep ? ((ax0 * hx[j]) * vx[j]) * zx : cux;
+      const float uy = sep ? ((ay0 * hy[j]) * vy[j]) * zy : cuy;
+      sphi[k / HW][k % HW] = hphi[j];
+      sjx[k / HW][k % HW] = hphi[j] * ux;
+      sjy[k / HW][k % HW] = hphi[j] * uy;
+    }
+  }
+  __syncthreads();
+  if (!active) return;
+  const float inv = (float)a.fp16_inv_scale;
+  const int lx = threadIdx.x + 1, ly = threadIdx.y + 1;
+  float f[9];
+#define LBM_SPLIT_P(I, EX, EY)                                                                       \
+  {                                                                                                \
+    const int sx = lx - (EX), sy = ly - (EY);                                                      \
+    const float ph = sphi[sy][sx];                                                                 \
+    float feq;                                                                                     \
+    if ((I) == 0) feq = ph * kW0;                                                                  \
+    else                                                                                           \
+      feq = feq_moving(ph, e_dot_j((float)(EX), (float)(EY), (EX) != 0 ? sjx[sy][sx] : 0.0f,        \
+                                   (EY) != 0 ? sjy[sy][sx] : 0.0f),                                \
+                       ((EX) == 0 || (EY) == 0) ? (1.0f / 3.0f) : (1.0f / 12.0f));                 \
+    f[I] = __builtin_fmaf(__half2float(raw[I]), inv, feq);                                         \
+  }
+  LBM_SPLIT_P(0, 0, 0)
+  LBM_SPLIT_P(1, 1, 0)
+  LBM_SPLIT_P(2, 0, 1)
+  LBM_SPLIT_P(3, -1, 0)
+  LBM_SPLIT_P(4, 0, -1)
+  LBM_SPLIT_P(5, 1, 1)
+  LBM_SPLIT_P(6, -1, 1)
+  LBM_SPLIT_P(7, -1, -1)
+  LBM_SPLIT_P(8, 1, -1)
+#undef LBM_SPLIT_P
+  // u at the node itself: phi u / phi is not exact, so it is formed again
+  float ux = cux, uy = cuy;
+  if (sep) {
+    const char* tx = tb + (1u + x) * 4u;
+    const char* ty = tb + (1u + nx + y) * 4u;
+    ux = ((ax0 * *(const float*)tx) * *(const float*)ty) * zx;
+    uy = ((ay0 * *(const float*)(tx + tstride)) * *(const float*)(ty + tstride)) * zy;
+  }
+  const float phi = f[0] + f[1] + f[2] + f[3] + f[4] + f[5] + f[6] + f[7] + f[8];
+  float h[9];
+  collide_neq_d2q9<float>(f, ux, uy, host_rel2(a), (float)a.fp16_scale, h);
+  const uint32_t nb = (r0 + x) * 2u;  // byte offset of the node in a half plane
+  store_pop<float, NT>((float*)((char*)a.dst_phi + nb * 2u), phi);
+  char* __restrict__ dst = (char*)a.dst;
+  float mx = 0.0f;
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    const unsigned short v = __half_as_ushort(to_half_clamped(h[i], mx));
+    unsigned short* p = (unsigned short*)(dst + i * pb + nb);
+    if constexpr (NT) __builtin_nontemporal_store(v, p);
+    else *p = v;
+  }
+  if (!(mx <= kHalfMax)) overflow[0] = 1u;
 }
 
 // Literal half storage of the shifted populations, same step as FP32.

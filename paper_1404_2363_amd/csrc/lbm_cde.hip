@@ -108,6 +108,8 @@ struct lbm_cde {
   bool env_variant = false;   // LBM_CDE_TILE / _NT / _XCD override every run
   Variant env{256, 1, 1, true, 0};
   Variant env3{128, 1, 1, true, 0};
+  bool env16_set = false;     // LBM_CDE_TILE16 = BXxBY[x1]: split 16-bit launch shape [streaming stores]
+  Variant env16{64, 4, 1, false, 0};
 };
 
 namespace {
@@ -438,6 +440,18 @@ RunArgs make_args(const lbm_cde* h, const Run& r, int parity) {
   for (int i = 0; i < 3; ++i)
     for (int j = 0; j < 3; ++j) a.A[i][j] = r.A[i][j];
   for (int i = 0; i < 3; ++i) a.heat[i] = r.heat[i];
+  {
+    // FP32 copies of the D2Q9 rates, rounded as the device's own FP32 set-up
+    const float s4 = (float)r.heat[0], s6 = (float)r.heat[1];
+    const float axx = (float)r.A[0][0], axy = (float)r.A[0][1], ayy = (float)r.A[1][1];
+    const bool modified = r.d.model == LBM_CDE_MRT_A;
+    const bool nl = r.d.model == LBM_CDE_MRT_B1 || r.d.model == LBM_CDE_MRT_B2;
+    const float v[16] = {(float)r.s[1], (float)r.s[2], (float)r.s[7], (float)r.s[8], s4, s6, axx, axy, ayy,
+                         modified ? (axx * 0.5f - 1.0f) * s4 : 0.0f, modified ? (axy * 0.5f) * s6 : 0.0f,
+                         modified ? (axy * 0.5f) * s4 : 0.0f, modified ? (ayy * 0.5f - 1.0f) * s6 : 0.0f,
+                         nl ? 1.0f : 0.0f, r.d.model == LBM_CDE_MRT_B1 ? 1.0f : 2.0f, 0.0f};
+    for (int i = 0; i < 16; ++i) a.relf[i] = v[i];
+  }
   a.max_steps = r.d.max_steps;
   a.xref0 = r.d.xref0;
   a.xref_drift = r.d.xref_drift;
@@ -536,11 +550,21 @@ const StepEntry kSteps[] = {
     STEP_ENTRY(128, 2, 2, true),  STEP_ENTRY(512, 1, 1, true),  STEP_ENTRY(128, 1, 1, true),
 };
 
-template <int BX, int BY, bool WALLS>
+// A periodic split run takes the 32-bit-offset kernel when its grid covers a
+// tile and every byte offset (phi plane, nine half planes) fits 32 bits.
+bool split_fast_ok(const RunArgs& a, int bx, int by) {
+  return a.nx >= bx && a.ny >= by && 4 * a.nx * a.ny < (1ll << 32) && 18 * a.plane < (1ll << 32);
+}
+
+template <int BX, int BY, bool WALLS, bool NT>
 void launch_split(const RunArgs a, hipStream_t s) {
   const int64_t ntx = (a.nx + BX - 1) / BX, nty = (a.ny + BY - 1) / BY;
-  hipLaunchKernelGGL((k_step_d2q9_split<BX, BY, WALLS>), dim3((unsigned)(ntx * nty)), dim3(BX, BY), 0, s, a,
-                     (unsigned*)a.fp16_flags);
+  if (!WALLS && split_fast_ok(a, BX, BY))
+    hipLaunchKernelGGL((k_step_d2q9_split_p<BX, BY, NT>), dim3((unsigned)(ntx * nty)), dim3(BX, BY), 0, s, a,
+                       (unsigned*)a.fp16_flags);
+  else
+    hipLaunchKernelGGL((k_step_d2q9_split<BX, BY, WALLS>), dim3((unsigned)(ntx * nty)), dim3(BX, BY), 0, s, a,
+                       (unsigned*)a.fp16_flags);
 }
 
 template <bool WALLS>
@@ -552,18 +576,22 @@ void launch_half(const RunArgs a, hipStream_t s) {
 
 struct SplitEntry {
   int bx, by;
-  StepFn fn[2];  // [walls?]
+  StepFn fn[2][2];  // [walls?][streaming stores? (periodic kernel only)]
 };
-#define SPLIT_ENTRY(BX, BY) \
-  SplitEntry { BX, BY, {launch_split<BX, BY, false>, launch_split<BX, BY, true>} }
+#define SPLIT_ENTRY(BX, BY)                                                                 \
+  SplitEntry {                                                                              \
+    BX, BY, {{launch_split<BX, BY, false, false>, launch_split<BX, BY, false, true>},       \
+             {launch_split<BX, BY, true, false>, launch_split<BX, BY, true, false>}}        \
+  }
 const SplitEntry kSplit[] = {SPLIT_ENTRY(64, 4), SPLIT_ENTRY(128, 2), SPLIT_ENTRY(256, 1), SPLIT_ENTRY(64, 8),
                              SPLIT_ENTRY(128, 4), SPLIT_ENTRY(256, 2)};
+
 
 StepFn find_step(const Run& r, const Variant& v) {
   const int p = r.dbl ? 1 : 0, w = r.walls ? 1 : 0;
   if (r.split) {
     for (const auto& e : kSplit)
-      if (e.bx == v.bx && e.by == v.by && v.ny == 1) return e.fn[w];
+      if (e.bx == v.bx && e.by == v.by && v.ny == 1) return e.fn[w][v.nt && !r.walls ? 1 : 0];
     return nullptr;
   }
   if (r.half) return (v.bx == 256 && v.by == 1 && v.ny == 1) ? (r.walls ? launch_half<true> : launch_half<false>)
@@ -667,6 +695,12 @@ void parse_env(lbm_cde* h) {
   const char* t3 = std::getenv("LBM_CDE_TILE3");
   const char* nt = std::getenv("LBM_CDE_NT");
   const char* xcd = std::getenv("LBM_CDE_XCD");
+  const char* t16 = std::getenv("LBM_CDE_TILE16");
+  int bx16, by16, nt16 = 0;
+  if (t16 && std::sscanf(t16, "%dx%dx%d", &bx16, &by16, &nt16) >= 2) {
+    h->env16_set = true;
+    h->env16 = Variant{bx16, by16, 1, nt16 != 0, 0};
+  }
   if (!t2 && !t3 && !nt && !xcd) return;
   h->env_variant = true;
   int bx, by, ny;
@@ -721,6 +755,7 @@ int init_runs(lbm_cde* h, const lbm_cde_run_desc* runs, int32_t nruns, const dou
     r.walls = false;
     for (int a = 0; a < r.dim; ++a) r.walls |= r.d.bc[a] != LBM_CDE_PERIODIC;
     r.var = default_variant(r.d.lattice, r.d.precision);
+    if (r.split && h->env16_set) r.var = h->env16;
     if (h->env_variant && !r.half) r.var = r.d.lattice == LBM_CDE_D3Q15 ? h->env3 : h->env;
     if (!find_step(r, r.var)) return fail_init(LBM_CDE_EINVAL, "run %d: launch variant not built", i);
     // host tables are copied during init; keep no pointer to caller memory
@@ -1188,8 +1223,9 @@ int lbm_cde_tune(lbm_cde_handle h, int32_t trials) {
     if (r.half) {
       if (r.split)
         for (const auto& e : kSplit)
+          for (int nt = 0; nt < (r.walls ? 1 : 2); ++nt)
           for (int xcd = 0; xcd < 3; ++xcd) {
-            const Variant c{e.bx, e.by, 1, false, xcd};
+            const Variant c{e.bx, e.by, 1, nt != 0, xcd};
             if (xcd == 2 && tile_rows(r, c) % 8 != 0) continue;
             double ms = 0.0;
             const int rc = time_variant(h, r, c, trials, &ms);

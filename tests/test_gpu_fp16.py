@@ -4,8 +4,12 @@ Split storage (phi in FP32, the non-equilibrium part in FP16 with a
 power-of-two scale) must stay within 1e-3 of max|phi| of the oracle; the
 literal form (shifted populations in FP16) is measured and reported next to
 it.  Saturation is detected (EOVERFLOW), forced from the host with an
-oversized scale.
+oversized scale.  The split step has a general kernel and a 32-bit-index
+kernel for periodic grids; every launch shape of both gives bitwise the same
+state.
 """
+import os
+
 import numpy as np
 import pytest
 
@@ -71,7 +75,7 @@ def test_split_walls(walls):
     assert rel(phi, ref) <= 1e-3
 
 
-@pytest.mark.parametrize("shape", [(67, 45), (1, 9), (7, 1)])
+@pytest.mark.parametrize("shape", [(67, 45), (1, 9), (7, 1), (68, 45), (4, 9), (260, 3), (1028, 5)])
 def test_split_ragged(shape):
     nx, ny = shape
     wl = W.cellular(nx=nx, ny=ny, steps=60, n_hills=4, sigma=max(2.0, min(nx, ny) / 6), U0=0.05)
@@ -103,3 +107,43 @@ def test_split_checkpoint_restart():
     b.set_state(ck, 25)
     b.step(35)
     np.testing.assert_array_equal(a.phi().cpu().numpy(), b.phi().cpu().numpy())
+
+
+SPLIT_VARIANTS = ["64x4", "128x2", "256x1", "64x8", "128x4", "256x2"]
+
+
+def _split_state(wl, steps, tile):
+    from paper_1404_2363_amd.solver import Solver
+    os.environ["LBM_CDE_TILE16"] = tile
+    try:
+        s = Solver(wl, "fp16")
+        v = s.variant()
+        s.step(steps)
+        out = s.get_state().cpu().numpy()
+        s.close()
+    finally:
+        del os.environ["LBM_CDE_TILE16"]
+    return out, v
+
+
+@pytest.mark.parametrize("case", ["periodic", "mixed_kernels", "specular_y", "bounce_y", "narrow"])
+def test_split_kernels_bitwise_equal(case):
+    """Every launch shape gives the same bits.  On a periodic grid the
+    32-bit-index kernel runs when the grid covers a tile and the general one
+    otherwise; at nx = 100 the 64-wide shapes take the first and the wider
+    ones the second, so the two kernels are compared with each other."""
+    if case == "narrow":
+        wl = W.cellular(nx=12, ny=7, steps=30, n_hills=2, sigma=2.0)
+    elif case == "periodic":
+        wl = W.cellular(nx=520, ny=37, steps=30, n_hills=5, sigma=6.0)
+    elif case == "mixed_kernels":
+        wl = W.cellular(nx=100, ny=30, steps=30, n_hills=4, sigma=5.0)
+    else:
+        wl = W.taylor_aris_channel(13, 12.0, 1.1, nx=1032, steps=30,
+                                   wall="specular" if case == "specular_y" else "bounce")
+    print(f"case split variants {case} {wl.shape}", flush=True)
+    ref, v0 = _split_state(wl, 30, SPLIT_VARIANTS[0])
+    for tile in SPLIT_VARIANTS[1:]:
+        out, v = _split_state(wl, 30, tile)
+        assert v["block"] == tuple(int(t) for t in tile.split("x"))
+        np.testing.assert_array_equal(out, ref, err_msg=tile)
