@@ -31,10 +31,24 @@ BYTES_PER_LU = {("d2q9", "fp64"): 144, ("d2q9", "fp32"): 72, ("d2q9", "fp16"): 4
 COPY_PROBE_BYTES = 1 << 30     # bytes read (and written) by one calibration copy
 
 
+def kernel_tag(name, launch):
+    """Name of the step kernel a launch variant runs, as rocprofv3 prints it,
+    plus the block order (a kernel argument, not part of the name)."""
+    bx, by = launch["block"]
+    nt = "true" if launch["nt_stores"] else "false"
+    if name.startswith("d2q9") and name.endswith("fp16"):
+        kern = f"lbm::k_step_d2q9_split_p<{bx}, {by}, {nt}>"
+    elif name.startswith("d2q9"):
+        kern = f"lbm::k_step_d2q9<float, {bx}, {by}, {launch['rows_per_thread']}, false, {nt}>"
+    else:
+        kern = f"lbm::k_step_d3q15<float, {bx}, {by}, {launch['rows_per_thread']}, false, {nt}>"
+    return f"{kern}|order{launch['block_order']}"
+
+
 def profiled_traffic(name, launch):
-    """HBM bytes per launch from the committed PMC profile of this kernel, or
-    None when the kernel source or the launch variant has changed since the
-    counters were taken."""
+    """HBM bytes per launch from the committed PMC profile of this kernel and
+    launch variant, or None when the kernel source or the variant differs from
+    what the counters were taken on."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "traffic.json")
     try:
@@ -46,11 +60,8 @@ def profiled_traffic(name, launch):
         h.update(open(os.path.join(ROOT, "paper_1404_2363_amd", "csrc", f), "rb").read())
     if h.hexdigest()[:16] != rec["source_sha"]:
         return None
-    bx, by = launch["block"]
-    tag = f"<float, {bx}, {by}, {launch['rows_per_thread']}, false, {'true' if launch['nt_stores'] else 'false'}>"
-    if tag not in rec["kernel"]:
-        return None
-    return rec["traffic_bytes_per_launch"]
+    k = rec["kernels"].get(kernel_tag(name, launch))
+    return None if k is None else k["traffic_bytes_per_launch"]
 
 
 def log(msg):
@@ -206,6 +217,7 @@ def main():
             continue
         log(f"{name}: {k} steps")
         out[name] = gpu_variant(wl, prec, k, w, tune)
+        out[name]["traffic"] = profiled_traffic(name, out[name]["launch"]) if prec != "fp64" else None
         log(f"{name}: {out[name]['mlups']:.0f} MLUPS, {out[name]['achieved_gbs']:.0f} GB/s")
     if (not args.only and not args.quick) or args.only == "taylor_aris_batch":
         runs = W.taylor_aris_batch()
@@ -245,7 +257,7 @@ def main():
                    "nodes": wl2.nodes},
         "roofline": {"bound": "hbm", "achieved": main_v["achieved_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": main_v["hbm_frac"],
-                     "traffic": profiled_traffic("d2q9_4096_fp32", main_v["launch"]),
+                     "traffic": main_v.get("traffic", profiled_traffic("d2q9_4096_fp32", main_v["launch"])),
                      "kernel": "k_step_d2q9<float>", "bytes_per_launch": 72 * wl2.nodes},
         "variants": out,
         "cpu_baseline": cpu,

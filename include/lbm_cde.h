@@ -226,9 +226,9 @@ int lbm_cde_tune(lbm_cde_handle h, int32_t trials);
  * thread, streaming stores (0/1), block order
  * (0: hardware order, 1: each XCD takes a contiguous range of tiles, 2: tile
  * rows interleaved over the 8 XCDs with all x-tiles of a row on one XCD).
- * The environment variable LBM_CDE_TILE16 = "BXxBY" or "BXxBYx1" (streaming
- * stores), read by lbm_cde_init(), fixes the FP16_SPLIT launch variant (as
- * LBM_CDE_TILE does for FP32/FP64 D2Q9 runs). */
+ * The environment variable LBM_CDE_TILE16 = "BXxBY[xNT[xORDER]]" (NT 1:
+ * streaming stores; ORDER the block order), read by lbm_cde_init(), fixes the
+ * FP16_SPLIT launch variant (as LBM_CDE_TILE does for FP32/FP64 D2Q9 runs). */
 int lbm_cde_get_variant(lbm_cde_handle h, int32_t run, int32_t* out);
 
 /* ---- state access (checkpoints) ------------------------------------------ */

@@ -108,7 +108,7 @@ struct lbm_cde {
   bool env_variant = false;   // LBM_CDE_TILE / _NT / _XCD override every run
   Variant env{256, 1, 1, true, 0};
   Variant env3{128, 1, 1, true, 0};
-  bool env16_set = false;     // LBM_CDE_TILE16 = BXxBY[x1]: split 16-bit launch shape [streaming stores]
+  bool env16_set = false;     // LBM_CDE_TILE16 = BXxBY[xNT[xORDER]]: split 16-bit launch variant
   Variant env16{64, 4, 1, false, 0};
 };
 
@@ -696,10 +696,10 @@ void parse_env(lbm_cde* h) {
   const char* nt = std::getenv("LBM_CDE_NT");
   const char* xcd = std::getenv("LBM_CDE_XCD");
   const char* t16 = std::getenv("LBM_CDE_TILE16");
-  int bx16, by16, nt16 = 0;
-  if (t16 && std::sscanf(t16, "%dx%dx%d", &bx16, &by16, &nt16) >= 2) {
+  int bx16, by16, nt16 = 0, xcd16 = 0;
+  if (t16 && std::sscanf(t16, "%dx%dx%dx%d", &bx16, &by16, &nt16, &xcd16) >= 2) {
     h->env16_set = true;
-    h->env16 = Variant{bx16, by16, 1, nt16 != 0, 0};
+    h->env16 = Variant{bx16, by16, 1, nt16 != 0, xcd16};
   }
   if (!t2 && !t3 && !nt && !xcd) return;
   h->env_variant = true;
