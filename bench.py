@@ -116,6 +116,39 @@ def batch_variant(runs, precision, steps, warmup):
             "bytes_per_lu": bpl, "hbm_frac": gbs / HBM_PEAK_GBS, "wall_s": wall, "nonfinite": nonfinite}
 
 
+def unsteady_variant(precision, steps, warmup):
+    """Time-dependent u on the 4096^2 grid: before every step a new velocity
+    field (device FP64, already resident) replaces the run's field; the step
+    then reads it (+8 B per lattice update in FP32) and the replacement
+    converts it (16 B read + 8 B written per node)."""
+    import torch
+    from paper_1404_2363_amd import workloads as W
+    from paper_1404_2363_amd.solver import Solver
+    wl = W.drifting_cellular(nx=4096, ny=4096, steps=steps, n_hills=64, sigma=32.0, drift=0.5)
+    fields = [torch.as_tensor(wl.u_schedule(n), dtype=torch.float64, device="cuda") for n in range(4)]
+    s = Solver(wl, precision)
+    for n in range(warmup):
+        s.set_velocity(fields[n % 4])
+        s.step(1)
+    torch.cuda.synchronize()
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start.record()
+    for n in range(steps):
+        s.set_velocity(fields[n % 4])
+        s.step(1)
+    stop.record()
+    torch.cuda.synchronize()
+    t_step = start.elapsed_time(stop) / 1e3 / steps
+    nonfinite = s.nonfinite()
+    s.close()
+    elem = 4 if precision == "fp32" else 8
+    bpl = BYTES_PER_LU[("d2q9", precision)] + 2 * elem      # populations + the field read by the step
+    upd = 16 + 2 * elem                                      # FP64 field read + stored copy written
+    return {"precision": precision, "nodes": wl.nodes, "steps": steps, "ms_per_step": t_step * 1e3,
+            "mlups": wl.nodes / t_step / 1e6, "step_bytes_per_lu": bpl, "update_bytes_per_node": upd,
+            "achieved_gbs_incl_update": wl.nodes * (bpl + upd) / t_step / 1e9, "nonfinite": nonfinite}
+
+
 def adjoint_variant(precision="fp32"):
     """One gradient of the snapshot misfit for one initial condition of the
     512^2 inverse problem (2000 steps, snapshots every 200, checkpoints every
@@ -225,6 +258,11 @@ def main():
         log(f"taylor_aris_batch: {len(runs)} channels, {k} steps")
         out["taylor_aris_batch_fp32"] = batch_variant(runs, "fp32", k, max(args.warmup // 4, 1))
         log(f"taylor_aris_batch: {out['taylor_aris_batch_fp32']['mlups']:.0f} MLUPS")
+    if (not args.only and not args.quick) or args.only == "unsteady":
+        k = max(args.steps // 4, 1)
+        log(f"unsteady: 4096^2 FP32 with a new velocity field every step, {k} steps")
+        out["d2q9_4096_fp32_unsteady_u"] = unsteady_variant("fp32", k, max(args.warmup // 4, 1))
+        log(f"unsteady: {out['d2q9_4096_fp32_unsteady_u']['mlups']:.0f} MLUPS")
     if (not args.only and not args.quick) or args.only == "adjoint":
         log("adjoint: one 512^2 x 2000-step gradient")
         out["inverse_adjoint_fp32"] = adjoint_variant("fp32")

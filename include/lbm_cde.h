@@ -111,11 +111,13 @@ enum { LBM_CDE_PERIODIC = 0, LBM_CDE_BOUNCE_BACK = 1, LBM_CDE_SPECULAR = 2, LBM_
  * (37).  The B models are D2Q9 only, FP64/FP32 storage, no adjoint. */
 enum { LBM_CDE_MRT_A = 0, LBM_CDE_MRT_B1 = 1, LBM_CDE_MRT_B2 = 2, LBM_CDE_MRT_B3 = 3 };
 
-/* Velocity field u(x) (steady):
+/* Velocity field u(x):
  *   CONST      u_const[0..dim-1].
  *   SEPARABLE  u_c(x,y,z) = amp_c * X_c[x] * Y_c[y] * Z_c[z] per component c,
  *              from host tables (see u_tables).
- *   FIELD      per node, device FP64 array [dim][nz][ny][nx]. */
+ *   FIELD      per node, device FP64 array [dim][nz][ny][nx], copied (in the
+ *              storage precision) at init and replaced by
+ *              lbm_cde_set_velocity() whenever the flow changes in time. */
 enum { LBM_CDE_U_CONST = 0, LBM_CDE_U_SEPARABLE = 1, LBM_CDE_U_FIELD = 2 };
 
 /* Rates s4, s6 (, s8) of the heat-flux moments, which the modified S
@@ -209,8 +211,18 @@ int lbm_cde_run_sampled(lbm_cde_handle h, int64_t n, int64_t every, double* hist
 int lbm_cde_samples_written(lbm_cde_handle h, int64_t* rows);
 
 /* The relaxation matrix S of run `run` (constant D only), row-major Q x Q,
- * into host memory S_out (Q*Q doubles); Q = 9 or 15. */
+ * into host memory S_out (Q*Q doubles); Q = 9 or 15.  Eq. (31) / (A.5) for
+ * MRT_A, Eq. (24) for the MRT_B models. */
 int lbm_cde_relaxation_matrix(lbm_cde_handle h, int32_t run, double* S_out);
+
+/* Replace the velocity field of run `run` (initialised with u_kind FIELD) by
+ * the device FP64 array u [dim][nz][ny][nx] (Eq. 1 with u = u(x, t)).  Each
+ * step relaxes the populations it arrives at with the field current when the
+ * step is enqueued: the field set before the call that takes a run from step
+ * n-1 to step n is u(x, t_n).  Enqueued on the handle's stream (the caller
+ * keeps u valid until that work has run); captured graphs need no rebuild.
+ * EINVAL if the run has no velocity field or an argument is NULL. */
+int lbm_cde_set_velocity(lbm_cde_handle h, int32_t run, const double* u);
 
 /* Autotuner: for every run, time `trials` launches of each compiled launch
  * variant (tile shape, streaming stores, XCD block order) and keep the

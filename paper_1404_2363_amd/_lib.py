@@ -90,6 +90,7 @@ def load() -> ctypes.CDLL:
         "lbm_cde_run_sampled": [P, I64, I64, P, I64],
         "lbm_cde_samples_written": [P, ctypes.POINTER(I64)],
         "lbm_cde_relaxation_matrix": [P, I32, ctypes.POINTER(D)],
+        "lbm_cde_set_velocity": [P, I32, P],
         "lbm_cde_tune": [P, I32],
         "lbm_cde_get_variant": [P, I32, ctypes.POINTER(I32)],
         "lbm_cde_state_bytes": [P, I32, ctypes.POINTER(ctypes.c_size_t)],
@@ -169,6 +170,10 @@ def lbm_cde_relaxation_matrix(h: int, run: int, Q: int):
     out = (ctypes.c_double * (Q * Q))()
     _check(load().lbm_cde_relaxation_matrix(h, run, out), "lbm_cde_relaxation_matrix", h)
     return [out[i] for i in range(Q * Q)]
+
+
+def lbm_cde_set_velocity(h: int, run: int, u_ptr: int) -> None:
+    _check(load().lbm_cde_set_velocity(h, run, u_ptr), "lbm_cde_set_velocity", h)
 
 
 def lbm_cde_tune(h: int, trials: int) -> None:

@@ -1195,8 +1195,24 @@ int lbm_cde_relaxation_matrix(lbm_cde_handle h, int32_t run, double* S_out) {
   for (int a = 0; a < r->dim; ++a)
     for (int b = 0; b < r->dim; ++b) {
       S_out[flux[a] * Q + flux[b]] = r->A[a][b];
-      S_out[flux[a] * Q + heatrow[b]] = (a == b ? r->A[a][b] / 2.0 - 1.0 : r->A[a][b] / 2.0) * r->heat[b];
+      if (r->d.model == LBM_CDE_MRT_A)  // the coupling of Eq. (31); Eq. (24) has none
+        S_out[flux[a] * Q + heatrow[b]] = (a == b ? r->A[a][b] / 2.0 - 1.0 : r->A[a][b] / 2.0) * r->heat[b];
     }
+  return LBM_CDE_OK;
+}
+
+int lbm_cde_set_velocity(lbm_cde_handle h, int32_t run, const double* u) {
+  Run* r = get_run(h, run);
+  if (!r || !u) return fail(h, LBM_CDE_EINVAL, "set_velocity: bad handle, run or pointer");
+  if (r->d.u_kind != LBM_CDE_U_FIELD || !r->ufield)
+    return fail(h, LBM_CDE_EINVAL, "set_velocity: run %d was not initialised with a velocity field", run);
+  const int64_t n = r->dim * r->nodes;
+  const unsigned blocks = (unsigned)((n + 255) / 256);
+  if (r->dbl)
+    hipLaunchKernelGGL(k_convert<double>, dim3(blocks), dim3(256), 0, h->stream, u, (double*)r->ufield, n);
+  else
+    hipLaunchKernelGGL(k_convert<float>, dim3(blocks), dim3(256), 0, h->stream, u, (float*)r->ufield, n);
+  HIP_TRY(h, hipGetLastError());
   return LBM_CDE_OK;
 }
 

@@ -59,7 +59,12 @@ def make_desc(wl, precision: str = "fp64", device="cuda:0", heat="lambda_min", r
             [Dm[0, 0], Dm[1, 1], Dm[2, 2], Dm[0, 1], Dm[0, 2], Dm[1, 2]]
         for i, v in enumerate(comps):
             d.D[i] = float(v)
-    if wl.u_sep is not None:
+    if wl.u_field is not None:
+        d.u_kind = L.LBM_CDE_U_FIELD
+        Uf = torch.as_tensor(np.ascontiguousarray(wl.u_field), dtype=torch.float64, device=device)
+        keep.append(Uf)
+        d.u_field = Uf.data_ptr()
+    elif wl.u_sep is not None:
         d.u_kind = L.LBM_CDE_U_SEPARABLE
         tab = wl.u_sep.as_flat_tables(wl.shape)
         keep.append(tab)
@@ -110,6 +115,7 @@ class Solver:
                 p = torch.as_tensor(np.ascontiguousarray(wl.phi0()), dtype=torch.float64, device=self.device)
             phis.append(p)
         self.descs = descs
+        self._u_keep = {}
         self.ws_bytes = L.lbm_cde_workspace_bytes(descs)
         self.workspace = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
         if self.workspace.data_ptr() % 256:
@@ -162,6 +168,13 @@ class Solver:
 
     def set_state(self, state: torch.Tensor, steps: int, run: int = 0) -> None:
         L.lbm_cde_set_state(self.h, run, state.data_ptr(), int(steps))
+
+    def set_velocity(self, u, run: int = 0) -> None:
+        """Replace the velocity field of a run made with a per-node field
+        (array or tensor shaped (dim, *grid)); applies from the next step."""
+        t = torch.as_tensor(u, dtype=torch.float64, device=self.device).contiguous()
+        L.lbm_cde_set_velocity(self.h, run, t.data_ptr())
+        self._u_keep[run] = t      # the conversion runs on the stream; keep the source alive until then
 
     def tune(self, trials: int = 20) -> None:
         L.lbm_cde_tune(self.h, int(trials))

@@ -137,6 +137,8 @@ class Workload:
     u_const: Optional[np.ndarray] = None
     u_sep: Optional[SeparableU] = None
     meta: dict = dataclasses.field(default_factory=dict)
+    u_field: Optional[np.ndarray] = None   # (dim, *grid) per-node velocity at step 0
+    u_schedule: Optional[object] = None    # n -> (dim, *grid) velocity of step n (time-dependent u)
 
     @property
     def dim(self) -> int:
@@ -161,6 +163,8 @@ class Workload:
         """Velocity on a window (default: whole grid), shape (dim, *window)."""
         idx = self.full_index() if idx is None else idx
         wshape = tuple(len(i) for i in reversed(idx))
+        if self.u_field is not None:
+            return self.u_field[(slice(None),) + np.ix_(*reversed([np.asarray(i) for i in idx]))].copy()
         if self.u_sep is not None:
             return self.u_sep.window(idx)
         u0 = np.zeros(self.dim) if self.u_const is None else np.asarray(self.u_const, np.float64)
@@ -412,6 +416,30 @@ def paper_hill(kind: str = "isotropic", u=(0.0, 0.0), n: int = 512) -> Workload:
     return Workload(f"paper_hill_{kind}", "d2q9", (n, n), ("periodic", "periodic"), steps, spec,
                     D=D, u_const=u_lat, meta={"kind": kind, "sigma0": sig, "t_m": t_m, "centre": (n / 2.0, n / 2.0),
                                               "phi_ref": 0.0})
+
+
+def drifting_cellular_field(nx: int, ny: int, U0: float, shift: float) -> np.ndarray:
+    """u = U0 (sin k(x - s) cos ky, -cos k(x - s) sin ky), k = 2 pi / n, as a
+    (2, ny, nx) array: the cellular flow translated by s nodes in x."""
+    kx, ky = 2.0 * math.pi / nx, 2.0 * math.pi / ny
+    X, Y = np.meshgrid(np.arange(nx, dtype=np.float64), np.arange(ny, dtype=np.float64))
+    return np.stack([U0 * np.sin(kx * (X - shift)) * np.cos(ky * Y), -U0 * np.cos(kx * (X - shift)) * np.sin(ky * Y)])
+
+
+def drifting_cellular(nx: int = 512, ny: Optional[int] = None, steps: int = 400, n_hills: int = 16,
+                      sigma: float = 12.0, U0: float = CELLULAR_U0, drift: float = 0.25, D=CELLULAR_D,
+                      walls=("periodic", "periodic"), seed_id: int = 6) -> Workload:
+    """A time-dependent flow: the cellular flow whose cells drift along x by
+    `drift` nodes per step, u(x, t_n) = drifting_cellular_field(n drift),
+    given as a per-node field updated every step (the case of a velocity
+    that changes in space and time, Sec. 2).  Random Gaussian hills."""
+    ny = nx if ny is None else ny
+    rng = rng_for(seed_id)
+    spec = random_hills(rng, n_hills, (nx, ny), sigma)
+    wl = Workload("drifting_cellular", "d2q9", (nx, ny), tuple(walls), steps, spec, D=np.asarray(D, np.float64),
+                  u_field=drifting_cellular_field(nx, ny, U0, 0.0), meta={"U0": U0, "drift": drift})
+    wl.u_schedule = lambda n: drifting_cellular_field(nx, ny, U0, n * drift)
+    return wl
 
 
 class TopHatX:
