@@ -843,7 +843,11 @@ int init_runs(lbm_cde* h, const lbm_cde_run_desc* runs, int32_t nruns, const dou
     hipDeviceProp_t prop;
     if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
       cus = prop.multiProcessorCount;
-    h->batch_grid = (unsigned)std::min<int64_t>(tiles.back(), (int64_t)8 * cus);
+    // blocks of the persistent launch per CU (LBM_CDE_BATCH_BLOCKS; 0 = one block per tile)
+    int64_t per_cu = 64;
+    if (const char* e = std::getenv("LBM_CDE_BATCH_BLOCKS")) per_cu = std::atoll(e);
+    const int64_t cap = std::min<int64_t>(tiles.back(), (int64_t)1 << 30);
+    h->batch_grid = (unsigned)(per_cu > 0 ? std::min<int64_t>(cap, per_cu * cus) : cap);
     h->batched = true;
   }
   HIP_TRY(nullptr, hipStreamCreateWithFlags(&h->capture, hipStreamNonBlocking));
