@@ -158,7 +158,10 @@ LBM_FORCEINLINE Rel2<float> host_rel2(const RunArgs& a) {
 // Since f_eq = M^-1 m_eq, h = M^-1 (n - S n) with n = M f - m_eq: the
 // increments of collide_d2q9 are formed the same way and the add/sub tree of
 // M^T is applied to scale (n - S n)/norm^2 directly, without forming f' or f_eq.
-template <typename R>
+// MODIFIED_ONLY: the run is MRT-A (no u^2 equilibrium terms, m2_eq = 2 phi),
+// known at compile time; the results are the same bits as with the runtime
+// coefficients nl = 0, c2 = 2.
+template <typename R, bool MODIFIED_ONLY = false>
 LBM_FORCEINLINE void collide_neq_d2q9(const R (&f)[9], R ux, R uy, const Rel2<R>& r, R scale, R (&h)[9]) {
   const R sa = f[1] + f[2] + f[3] + f[4];
   const R sd = f[5] + f[6] + f[7] + f[8];
@@ -176,16 +179,24 @@ LBM_FORCEINLINE void collide_neq_d2q9(const R (&f)[9], R ux, R uy, const Rel2<R>
   const R m7 = f[1] - f[2] + f[3] - f[4];
   const R m8 = f[5] - f[6] + f[7] - f[8];
   const R jx = phi * ux, jy = phi * uy;
-  const R q = r.nl * phi;
-  const R u2 = ux * ux + uy * uy;
-  const R n1 = m1 + (R)2 * phi - (R)3 * q * u2;
-  const R n2 = m2 - r.c2 * phi + (R)3 * q * u2;
+  R n1, n2, n7, n8;
+  if constexpr (MODIFIED_ONLY) {
+    n1 = m1 + (R)2 * phi;
+    n2 = m2 - (R)2 * phi;
+    n7 = m7;
+    n8 = m8;
+  } else {
+    const R q = r.nl * phi;
+    const R u2 = ux * ux + uy * uy;
+    n1 = m1 + (R)2 * phi - (R)3 * q * u2;
+    n2 = m2 - r.c2 * phi + (R)3 * q * u2;
+    n7 = m7 - q * (ux * ux - uy * uy);
+    n8 = m8 - q * ux * uy;
+  }
   const R n3 = m3 - jx;
   const R n4 = m4 + jx;
   const R n5 = m5 - jy;
   const R n6 = m6 + jy;
-  const R n7 = m7 - q * (ux * ux - uy * uy);
-  const R n8 = m8 - q * ux * uy;
   // scale (n - S n) / norm^2
   const R k36 = scale * (R)(1.0 / 36.0), k12 = scale * (R)(1.0 / 12.0);
   const R k6 = scale * (R)(1.0 / 6.0), k4 = scale * (R)0.25;

@@ -188,7 +188,7 @@ __global__ __launch_bounds__(BX * BY) void k_step_d2q9_split(const RunArgs a, un
   velocity2<float>(a, x, y, ux, uy);
   const float phi = f[0] + f[1] + f[2] + f[3] + f[4] + f[5] + f[6] + f[7] + f[8];
   float h[9];
-  collide_neq_d2q9<float>(f, ux, uy, host_rel2(a), (float)a.fp16_scale, h);
+  collide_neq_d2q9<float, true>(f, ux, uy, host_rel2(a), (float)a.fp16_scale, h);
   const int64_t node = y * a.nx + x;
   ((float*)a.dst_phi)[node] = phi;
   __half* __restrict__ dst = (__half*)a.dst;
@@ -214,8 +214,8 @@ LBM_FORCEINLINE uint32_t mod3n(uint32_t x, uint32_t n) {
 // stores.
 template <int BX, int BY, bool NT>
 __global__ __launch_bounds__(BX * BY) void k_step_d2q9_split_p(const RunArgs a, unsigned* __restrict__ overflow) {
-  constexpr int NT_ = BX * BY, HW = BX + 2, HN = (BX + 2) * (BY + 2);
-  constexpr int NH = (HN + NT_ - 1) / NT_;  // halo entries per thread
+  constexpr int NT_ = BX * BY, RN = 2 * (BX + 2) + 2 * BY;  // ring (halo) entries of the tile
+  constexpr int NR = (RN + NT_ - 1) / NT_;                      // ring entries per thread
   __shared__ float sphi[BY + 2][BX + 2], sjx[BY + 2][BX + 2], sjy[BY + 2][BX + 2];
   const uint32_t nx = (uint32_t)a.nx, ny = (uint32_t)a.ny;
   const uint32_t ntx = (nx + BX - 1) / BX;
@@ -231,14 +231,42 @@ __global__ __launch_bounds__(BX * BY) void k_step_d2q9_split_p(const RunArgs a, 
   const float zy = sep ? *(const float*)(tb + tstride + (1u + nx + ny) * 4u) : 0.0f;
   const float cux = (float)a.u_const[0], cuy = (float)a.u_const[1];
   // Loads in the order their results are needed, all issued before the first
-  // wait: phi and the velocity factors of the tile and its halo, then the nine
-  // stored halves of this thread's node (waited for after the barrier).
-  float hphi[NH], hx[NH], hy[NH], vx[NH], vy[NH];
+  // wait: this thread's node (phi, velocity factors), one ring entry of the
+  // tile's halo, then the nine stored halves (waited for after the barrier).
+  // A thread past the grid edge stages the node its tile position wraps to
+  // (a neighbour may pull from it) and reads, and discards, valid halves.
+  const uint32_t xr = tx0 + threadIdx.x, yr = ty0 + threadIdx.y;
+  const bool active = xr < nx && yr < ny;
+  const uint32_t x = xr < nx ? xr : xr - nx, y = yr < ny ? yr : yr - ny;
+  const float ph_own = *(const float*)(phis + (y * nx + x) * 4u);
+  float ox = 0.0f, oy = 0.0f, px = 0.0f, py = 0.0f;
+  if (sep) {
+    ox = *(const float*)(tb + (1u + x) * 4u);
+    oy = *(const float*)(tb + (1u + nx + y) * 4u);
+    px = *(const float*)(tb + tstride + (1u + x) * 4u);
+    py = *(const float*)(tb + tstride + (1u + nx + y) * 4u);
+  }
+  float hphi[NR], hx[NR], hy[NR], vx[NR], vy[NR];
+  int hl[NR];
 #pragma unroll
-  for (int j = 0; j < NH; ++j) {
-    const int k = min(tid + j * NT_, HN - 1);
-    const uint32_t lx = (uint32_t)k % HW, ly = (uint32_t)k / HW;
-    const uint32_t gx = mod3n(tx0 + lx + nx - 1u, nx), gy = mod3n(ty0 + ly + ny - 1u, ny);
+  for (int j = 0; j < NR; ++j) {
+    const int r = min(tid + j * NT_, RN - 1);
+    int lx, ly;
+    if (r < BX + 2) {
+      lx = r;
+      ly = 0;
+    } else if (r < 2 * (BX + 2)) {
+      lx = r - (BX + 2);
+      ly = BY + 1;
+    } else if (r < 2 * (BX + 2) + BY) {
+      lx = 0;
+      ly = 1 + r - 2 * (BX + 2);
+    } else {
+      lx = BX + 1;
+      ly = 1 + r - 2 * (BX + 2) - BY;
+    }
+    hl[j] = ly * (BX + 2) + lx;
+    const uint32_t gx = mod3n(tx0 + (uint32_t)lx + nx - 1u, nx), gy = mod3n(ty0 + (uint32_t)ly + ny - 1u, ny);
     hphi[j] = *(const float*)(phis + (gy * nx + gx) * 4u);
     hx[j] = hy[j] = vx[j] = vy[j] = 0.0f;
     if (sep) {
@@ -248,11 +276,6 @@ __global__ __launch_bounds__(BX * BY) void k_step_d2q9_split_p(const RunArgs a, 
       vy[j] = *(const float*)(tb + tstride + (1u + nx + gy) * 4u);
     }
   }
-  const uint32_t xr = tx0 + threadIdx.x, yr = ty0 + threadIdx.y;
-  const bool active = xr < nx && yr < ny;
-  // threads past the grid edge read (and discard) a valid node: the loads stay
-  // unconditional, so the compiler issues all nine without waiting in between
-  const uint32_t x = active ? xr : 0u, y = active ? yr : 0u;
   const uint32_t xm = x == 0 ? nx - 1u : x - 1u, xp = x + 1u == nx ? 0u : x + 1u;
   const uint32_t rm = (y == 0 ? ny - 1u : y - 1u) * nx, r0 = y * nx, rp = (y + 1u == ny ? 0u : y + 1u) * nx;
   const char* __restrict__ src = (const char*)a.src;
@@ -262,15 +285,19 @@ __global__ __launch_bounds__(BX * BY) void k_step_d2q9_split_p(const RunArgs a, 
 #pragma unroll
   for (int i = 0; i < 9; ++i) raw[i] = *(const __half*)(src + i * pb + off[i] * 2u);
   // phi, phi ux, phi uy of the tile; u in velocity2's product order
+  const float ux = sep ? ((ax0 * ox) * oy) * zx : cux;
+  const float uy = sep ? ((ay0 * px) * py) * zy : cuy;
+  sphi[threadIdx.y + 1][threadIdx.x + 1] = ph_own;
+  sjx[threadIdx.y + 1][threadIdx.x + 1] = ph_own * ux;
+  sjy[threadIdx.y + 1][threadIdx.x + 1] = ph_own * uy;
 #pragma unroll
-  for (int j = 0; j < NH; ++j) {
-    const int k = tid + j * NT_;
-    if (k < HN) {
-      const float ux = sep ? ((ax0 * hx[j]) * vx[j]) * zx : cux;
-      const float uy = sep ? ((ay0 * hy[j]) * vy[j]) * zy : cuy;
-      sphi[k / HW][k % HW] = hphi[j];
-      sjx[k / HW][k % HW] = hphi[j] * ux;
-      sjy[k / HW][k % HW] = hphi[j] * uy;
+  for (int j = 0; j < NR; ++j) {
+    if (tid + j * NT_ < RN) {
+      const float hux = sep ? ((ax0 * hx[j]) * vx[j]) * zx : cux;
+      const float huy = sep ? ((ay0 * hy[j]) * vy[j]) * zy : cuy;
+      (&sphi[0][0])[hl[j]] = hphi[j];
+      (&sjx[0][0])[hl[j]] = hphi[j] * hux;
+      (&sjy[0][0])[hl[j]] = hphi[j] * huy;
     }
   }
   __syncthreads();
@@ -300,17 +327,9 @@ __global__ __launch_bounds__(BX * BY) void k_step_d2q9_split_p(const RunArgs a, 
   LBM_SPLIT_P(7, -1, -1)
   LBM_SPLIT_P(8, 1, -1)
 #undef LBM_SPLIT_P
-  // u at the node itself: phi u / phi is not exact, so it is formed again
-  float ux = cux, uy = cuy;
-  if (sep) {
-    const char* tx = tb + (1u + x) * 4u;
-    const char* ty = tb + (1u + nx + y) * 4u;
-    ux = ((ax0 * *(const float*)tx) * *(const float*)ty) * zx;
-    uy = ((ay0 * *(const float*)(tx + tstride)) * *(const float*)(ty + tstride)) * zy;
-  }
   const float phi = f[0] + f[1] + f[2] + f[3] + f[4] + f[5] + f[6] + f[7] + f[8];
   float h[9];
-  collide_neq_d2q9<float>(f, ux, uy, host_rel2(a), (float)a.fp16_scale, h);
+  collide_neq_d2q9<float, true>(f, ux, uy, host_rel2(a), (float)a.fp16_scale, h);
   const uint32_t nb = (r0 + x) * 2u;  // byte offset of the node in a half plane
   store_pop<float, NT>((float*)((char*)a.dst_phi + nb * 2u), phi);
   char* __restrict__ dst = (char*)a.dst;
