@@ -28,6 +28,98 @@ namespace lbm {
 
 constexpr float kHalfMax = 65504.0f;
 
+// Rates of a constant-D run from the host-rounded FP32 copy.
+LBM_FORCEINLINE Rel2<float> host_rel2(const RunArgs& a) {
+  Rel2<float> r;
+  r.s1 = a.relf[0];
+  r.s2 = a.relf[1];
+  r.s7 = a.relf[2];
+  r.s8 = a.relf[3];
+  r.s4 = a.relf[4];
+  r.s6 = a.relf[5];
+  r.axx = a.relf[6];
+  r.axy = a.relf[7];
+  r.ayy = a.relf[8];
+  r.c34 = a.relf[9];
+  r.c36 = a.relf[10];
+  r.c54 = a.relf[11];
+  r.c56 = a.relf[12];
+  r.nl = a.relf[13];
+  r.c2 = a.relf[14];
+  return r;
+}
+
+// The non-equilibrium part of the post-collision populations times a scale,
+// h = scale (f' - f_eq(phi, u)), of one node with unshifted populations f.
+// Since f_eq = M^-1 m_eq, h = M^-1 (n - S n) with n = M f - m_eq: the
+// increments of collide_d2q9 are formed the same way and the add/sub tree of
+// M^T is applied to scale (n - S n)/norm^2 directly, without forming f' or f_eq.
+// MODIFIED_ONLY: the run is MRT-A (no u^2 equilibrium terms, m2_eq = 2 phi),
+// known at compile time; the results are the same bits as with the runtime
+// coefficients nl = 0, c2 = 2.
+template <typename R, bool MODIFIED_ONLY = false>
+LBM_FORCEINLINE void collide_neq_d2q9(const R (&f)[9], R ux, R uy, const Rel2<R>& r, R scale, R (&h)[9]) {
+  const R sa = f[1] + f[2] + f[3] + f[4];
+  const R sd = f[5] + f[6] + f[7] + f[8];
+  const R phi = f[0] + sa + sd;
+  const R m1 = (R)2 * sd - sa - (R)4 * f[0];
+  const R m2 = (R)4 * f[0] - (R)2 * sa + sd;
+  const R dx13 = f[1] - f[3];
+  const R dx58 = f[5] - f[6] - f[7] + f[8];
+  const R dy24 = f[2] - f[4];
+  const R dy56 = f[5] + f[6] - f[7] - f[8];
+  const R m3 = dx13 + dx58;
+  const R m4 = dx58 - (R)2 * dx13;
+  const R m5 = dy24 + dy56;
+  const R m6 = dy56 - (R)2 * dy24;
+  const R m7 = f[1] - f[2] + f[3] - f[4];
+  const R m8 = f[5] - f[6] + f[7] - f[8];
+  const R jx = phi * ux, jy = phi * uy;
+  R n1, n2, n7, n8;
+  if constexpr (MODIFIED_ONLY) {
+    n1 = m1 + (R)2 * phi;
+    n2 = m2 - (R)2 * phi;
+    n7 = m7;
+    n8 = m8;
+  } else {
+    const R q = r.nl * phi;
+    const R u2 = ux * ux + uy * uy;
+    n1 = m1 + (R)2 * phi - (R)3 * q * u2;
+    n2 = m2 - r.c2 * phi + (R)3 * q * u2;
+    n7 = m7 - q * (ux * ux - uy * uy);
+    n8 = m8 - q * ux * uy;
+  }
+  const R n3 = m3 - jx;
+  const R n4 = m4 + jx;
+  const R n5 = m5 - jy;
+  const R n6 = m6 + jy;
+  // scale (n - S n) / norm^2
+  const R k36 = scale * (R)(1.0 / 36.0), k12 = scale * (R)(1.0 / 12.0);
+  const R k6 = scale * (R)(1.0 / 6.0), k4 = scale * (R)0.25;
+  const R b1 = (n1 - r.s1 * n1) * k36;
+  const R b2 = (n2 - r.s2 * n2) * k36;
+  const R b3 = (n3 - (r.axx * n3 + r.c34 * n4 + r.axy * n5 + r.c36 * n6)) * k6;
+  const R b4 = (n4 - r.s4 * n4) * k12;
+  const R b5 = (n5 - (r.axy * n3 + r.c54 * n4 + r.ayy * n5 + r.c56 * n6)) * k6;
+  const R b6 = (n6 - r.s6 * n6) * k12;
+  const R b7 = (n7 - r.s7 * n7) * k4;
+  const R b8 = (n8 - r.s8 * n8) * k4;
+  const R ax = -b1 - (R)2 * b2;
+  const R dg = (R)2 * b1 + b2;
+  const R q3 = b3 - (R)2 * b4, q5 = b5 - (R)2 * b6;
+  const R p3 = b3 + b4, p5 = b5 + b6;
+  h[0] = (R)4 * (b2 - b1);
+  h[1] = ax + q3 + b7;
+  h[2] = ax + q5 - b7;
+  h[3] = ax - q3 + b7;
+  h[4] = ax - q5 - b7;
+  h[5] = dg + p3 + p5 + b8;
+  h[6] = dg - p3 + p5 - b8;
+  h[7] = dg - p3 - p5 + b8;
+  h[8] = dg + p3 - p5 - b8;
+}
+
+
 LBM_FORCEINLINE float feq_d2q9(int i, float phi, float ux, float uy) {
   if (i == 0) return phi * (5.0f / 9.0f);
   const int ex = (i == 1 || i == 5 || i == 8) ? 1 : (i == 3 || i == 6 || i == 7) ? -1 : 0;
