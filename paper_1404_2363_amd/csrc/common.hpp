@@ -43,6 +43,7 @@ struct RunArgs {
   // s6 axx axy ayy c34 c36 c54 c56 nl c2 (the FP16 split kernels read these)
   float relf[16];
   int32_t xcd_remap;        // block order (see tile_of_block)
+  int32_t rows32;           // D2Q9 batch: x periodic, constant D, every byte offset < 4 GiB
   int32_t active;           // 0: run has used its step budget
   int64_t max_steps;        // step budget (< 0: unlimited), used by batched launches
   double xref0, xref_drift; // sampled x-moments: x_ref(t) = xref0 + xref_drift * t

@@ -300,6 +300,86 @@ __global__ __launch_bounds__(BX * BY) void k_step_d2q9(const RunArgs a) {
   tile_d2q9<R, BX, BY, NY, WALLS, NT>(a, b % ntx, b / ntx);
 }
 
+// Where population (EX, EY) of row y comes from when x is periodic: the
+// stored population, the source row and the x shift, the same for every node
+// of the row (the wall rule of pull_index_d2q9 restricted to y walls).
+template <int EX, int EY>
+LBM_FORCEINLINE void row_source_d2q9(const RunArgs& a, int32_t y, int32_t ny, int& pop, int32_t& sy, int& dx) {
+  pop = pop_of_d2q9(EX, EY);
+  dx = -EX;
+  sy = y - EY;
+  if (EY != 0 && (sy < 0 || sy >= ny)) {
+    if (a.bc[1] == LBM_CDE_PERIODIC) {
+      sy = sy < 0 ? sy + ny : sy - ny;
+    } else if (a.bc[1] == LBM_CDE_BOUNCE_BACK) {
+      pop = pop_of_d2q9(-EX, -EY);
+      sy = y;
+      dx = 0;
+    } else {
+      pop = pop_of_d2q9(EX, -EY);
+      sy = a.bc[1] == LBM_CDE_NODE_MIRROR ? y + EY : y;
+    }
+  }
+}
+
+// One row tile of a run with periodic x and constant D, addressed with 32-bit
+// byte offsets from uniform bases: the same loads, velocities and collision
+// as tile_d2q9 with walls (bitwise the same result), with the wall rule
+// evaluated once per row.
+template <typename R, int BX, bool NT>
+LBM_FORCEINLINE void tile_rows_d2q9(const RunArgs& a, int64_t tile_x, int64_t tile_y) {
+  const uint32_t nx = (uint32_t)a.nx;
+  const int32_t ny = (int32_t)a.ny;
+  const uint32_t x = (uint32_t)tile_x * BX + threadIdx.x;
+  if (x >= nx) return;
+  const int32_t y = (int32_t)tile_y;
+  const uint32_t xm = x == 0 ? nx - 1u : x - 1u, xp = x + 1u == nx ? 0u : x + 1u;
+  const char* __restrict__ src = (const char*)a.src;
+  char* __restrict__ dst = (char*)a.dst;
+  const uint32_t pb = (uint32_t)a.plane * (uint32_t)sizeof(R);
+  R f[9];
+#define LBM_ROW_PULL(I, EX, EY)                                                                 \
+  {                                                                                           \
+    int pop, dx;                                                                              \
+    int32_t sy;                                                                               \
+    row_source_d2q9<EX, EY>(a, y, ny, pop, sy, dx);                                           \
+    const uint32_t sx = dx < 0 ? xm : (dx > 0 ? xp : x);                                      \
+    f[I] = *(const R*)(src + (uint32_t)pop * pb + ((uint32_t)sy * nx + sx) * (uint32_t)sizeof(R)); \
+  }
+  LBM_ROW_PULL(0, 0, 0)
+  LBM_ROW_PULL(1, 1, 0)
+  LBM_ROW_PULL(2, 0, 1)
+  LBM_ROW_PULL(3, -1, 0)
+  LBM_ROW_PULL(4, 0, -1)
+  LBM_ROW_PULL(5, 1, 1)
+  LBM_ROW_PULL(6, -1, 1)
+  LBM_ROW_PULL(7, -1, -1)
+  LBM_ROW_PULL(8, 1, -1)
+#undef LBM_ROW_PULL
+  R ux, uy;
+  if (a.u_kind == U_CONST) {
+    ux = (R)a.u_const[0];
+    uy = (R)a.u_const[1];
+  } else if (a.u_kind == U_SEPARABLE) {
+    const char* t = (const char*)a.u_tab;
+    const uint32_t stride = (1u + nx + (uint32_t)ny + (uint32_t)a.nz) * (uint32_t)sizeof(R);
+    const uint32_t ox = (1u + x) * (uint32_t)sizeof(R), oy = (1u + nx + (uint32_t)y) * (uint32_t)sizeof(R);
+    const uint32_t oz = (1u + nx + (uint32_t)ny) * (uint32_t)sizeof(R);
+    ux = ((*(const R*)t * *(const R*)(t + ox)) * *(const R*)(t + oy)) * *(const R*)(t + oz);
+    uy = ((*(const R*)(t + stride) * *(const R*)(t + stride + ox)) * *(const R*)(t + stride + oy)) *
+         *(const R*)(t + stride + oz);
+  } else {
+    const char* u = (const char*)a.u_field;
+    const uint32_t o = ((uint32_t)y * nx + x) * (uint32_t)sizeof(R);
+    ux = *(const R*)(u + o);
+    uy = *(const R*)(u + nx * (uint32_t)ny * (uint32_t)sizeof(R) + o);
+  }
+  collide_d2q9<R>(f, ux, uy, (R)a.phi_ref, const_rel2<R>(a));
+  const uint32_t nb = ((uint32_t)y * nx + x) * (uint32_t)sizeof(R);
+#pragma unroll
+  for (int i = 0; i < 9; ++i) store_pop<R, NT>((R*)(dst + i * pb + nb), f[i]);
+}
+
 // One step of every active run of a batch, in one persistent launch: the
 // grid walks a flat list of BX-wide row tiles spanning all runs.  The
 // global step t is read from device memory (so a captured graph stays valid)
@@ -326,7 +406,8 @@ __global__ __launch_bounds__(BX) void k_batch_d2q9(const RunArgs* __restrict__ r
     }
     const int64_t local = t - tile_start[lo];
     const int64_t ntx = (a.nx + BX - 1) / BX;
-    tile_d2q9<R, BX, 1, 1, true, NT>(a, local % ntx, local / ntx);
+    if (a.rows32) tile_rows_d2q9<R, BX, NT>(a, local % ntx, local / ntx);
+    else tile_d2q9<R, BX, 1, 1, true, NT>(a, local % ntx, local / ntx);
   }
 }
 

@@ -456,6 +456,8 @@ RunArgs make_args(const lbm_cde* h, const Run& r, int parity) {
   a.xref0 = r.d.xref0;
   a.xref_drift = r.d.xref_drift;
   a.xcd_remap = r.var.xcd;
+  a.rows32 = r.d.lattice == LBM_CDE_D2Q9 && !r.half && r.d.bc[0] == LBM_CDE_PERIODIC && !r.node_par &&
+             (double)r.plane * r.Q * r.elem < 4294967296.0 && r.d.nx < (1ll << 31) && r.d.ny < (1ll << 31);
   if (a.xcd_remap == 2 && tile_rows(r, r.var) % 8 != 0) a.xcd_remap = 0;
   a.active = 1;
   return a;

@@ -119,3 +119,28 @@ def test_taylor_aris_ensemble_dispersion():
               flush=True)
         assert abs(r["rel_err"]) <= 1e-2, r
     assert info["nonfinite"] == 0
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_batched_row_tiles_equal_single_runs(precision):
+    """The batch's row tiles (wall rule once per row, 32-bit offsets) give
+    bitwise the state of the same runs stepped alone by the general kernels,
+    for every y boundary kind and a per-node velocity field."""
+    from paper_1404_2363_amd.solver import Solver
+    wls = [W.taylor_aris_channel(h, Pe, tau, nx=nx, wall=wall, steps=50)
+           for (h, Pe, tau, nx), wall in zip([(12, 20.0, 0.8, 100), (9, 8.0, 1.3, 77), (16, 12.0, 1.1, 90)],
+                                             ["specular", "bounce", "specular"])]
+    wls.append(W.plate_channel(1.5, 8.0, W_lat=10, length=7, steps=50))
+    per = [{"heat": [1.0, 1.0]}] * len(wls)
+    fld = W.drifting_cellular(nx=64, ny=30, steps=50, n_hills=3, sigma=4.0, drift=0.0)
+    wls.append(fld)
+    per = per + [{"heat": [1.0, 1.0]}]
+    s = Solver(wls, precision, per_run=per)
+    s.step(50)
+    batched = [s.phi(i).cpu().numpy() for i in range(len(wls))]
+    s.close()
+    for i, wl in enumerate(wls):
+        one = Solver(wl, precision, per_run=[per[i]])
+        one.step(50)
+        np.testing.assert_array_equal(batched[i], one.phi().cpu().numpy(), err_msg=wl.name)
+        one.close()
