@@ -177,6 +177,51 @@ def adjoint_variant(precision="fp32"):
             "forward + recompute + reverse (3 passes)"}
 
 
+def adjoint_segment_variant(n=2048, K=16, precision="fp32"):
+    """One checkpoint segment of the adjoint on an n^2 grid with a per-node D
+    field: K forward steps recomputed from the checkpoint, then K reverse
+    steps.  Bytes per node: forward step 72 (populations) + 20 (per-node flux
+    block and heat rates, FP32); reverse step 36 (lambda) + 36 (forward
+    state) + 20 (parameters) + 48 (FP64 gradient read and written) + 36 (mu)."""
+    import torch
+    from paper_1404_2363_amd import _lib as L
+    from paper_1404_2363_amd import workloads as W
+    from paper_1404_2363_amd.solver import Solver
+    inv = W.inverse_dfield(n=n, n_ic=1, steps=K)
+    ic = inv["ics"][0]
+    D = torch.tensor(inv["D_trial"], dtype=torch.float64, device="cuda")
+    import dataclasses
+    wl = dataclasses.replace(ic, D_field=D)
+    s = Solver(wl, precision, heat=[1.0, 1.0])
+    nb = s.state_bytes()
+    ck = s.get_state()
+    mu = torch.zeros(nb, dtype=torch.uint8, device="cuda")
+    mu_tmp = torch.empty_like(mu)
+    seg = torch.empty(nb * K, dtype=torch.uint8, device="cuda")
+    grad = torch.zeros((3, n, n), dtype=torch.float64, device="cuda")
+    g = torch.ones((n, n), dtype=torch.float64, device="cuda") * 1e-3
+    inj = [None] * (K - 1) + [g.data_ptr()]
+    L.lbm_cde_adjoint_segment(s.h, 0, ck.data_ptr(), K, seg.data_ptr(), inj, mu.data_ptr(), mu_tmp.data_ptr(),
+                              grad.data_ptr())                      # warm-up
+    torch.cuda.synchronize()
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 3
+    start.record()
+    for _ in range(reps):
+        L.lbm_cde_adjoint_segment(s.h, 0, ck.data_ptr(), K, seg.data_ptr(), inj, mu.data_ptr(),
+                                  mu_tmp.data_ptr(), grad.data_ptr())
+    stop.record()
+    torch.cuda.synchronize()
+    t = start.elapsed_time(stop) / 1e3 / reps
+    finite = bool(torch.isfinite(grad).all())
+    s.close()
+    nodes = n * n
+    byts = nodes * (K * (92 + 176) + 8)
+    return {"precision": precision, "nodes": nodes, "segment_steps": K, "seconds_per_segment": t,
+            "forward_plus_reverse_mlups": nodes * K / t / 1e6, "bytes_per_node_step": {"forward": 92, "reverse": 176},
+            "achieved_gbs": byts / t / 1e9, "hbm_frac": byts / t / 1e9 / HBM_PEAK_GBS, "finite": finite}
+
+
 def copy_probe():
     """A plain device copy of known size, for calibrating HBM byte counters."""
     import torch
@@ -264,6 +309,9 @@ def main():
         out["d2q9_4096_fp32_unsteady_u"] = unsteady_variant("fp32", k, max(args.warmup // 4, 1))
         log(f"unsteady: {out['d2q9_4096_fp32_unsteady_u']['mlups']:.0f} MLUPS")
     if (not args.only and not args.quick) or args.only == "adjoint":
+        log("adjoint: one 2048^2 checkpoint segment of 16 steps (forward recompute + reverse)")
+        out["adjoint_segment_2048_fp32"] = adjoint_segment_variant()
+        log(f"adjoint segment: {out['adjoint_segment_2048_fp32']['achieved_gbs']:.0f} GB/s")
         log("adjoint: one 512^2 x 2000-step gradient")
         out["inverse_adjoint_fp32"] = adjoint_variant("fp32")
         log(f"adjoint: {out['inverse_adjoint_fp32']['seconds_per_gradient']:.3f} s per gradient")
