@@ -79,10 +79,13 @@ template <typename R, bool WALLS>
 __global__ __launch_bounds__(256) void k_adjoint_d2q9(const RunArgs a, const R* __restrict__ mu_in,
                                                       const double* __restrict__ inj, R* __restrict__ mu_out,
                                                       double* __restrict__ grad, double inv_kappa) {
+  // one block per 256-wide row tile (the tile index splits with scalar
+  // arithmetic; no per-thread 64-bit division)
   const int64_t N = a.nx * a.ny;
-  const int64_t node = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (node >= N) return;
-  const int64_t x = node % a.nx, y = node / a.nx;
+  const int64_t ntx = (a.nx + 255) / 256;
+  const int64_t x = (int64_t)(blockIdx.x % ntx) * 256 + threadIdx.x, y = blockIdx.x / ntx;
+  if (x >= a.nx) return;
+  const int64_t node = y * a.nx + x;
   const R* src = (const R*)a.src;
 
   // adjoint populations lambda_{t+1}(y)

@@ -1014,7 +1014,7 @@ int check_adjoint_run(lbm_cde* h, Run* r) {
 template <typename R>
 void launch_adjoint(const Run& r, const RunArgs& a, const void* mu_in, const double* inj, void* mu_out,
                     double* grad, double inv_kappa, hipStream_t s) {
-  const unsigned blocks = (unsigned)((r.nodes + 255) / 256);
+  const unsigned blocks = (unsigned)((r.d.nx + 255) / 256 * r.d.ny);  // 256-wide row tiles
   if (r.walls)
     hipLaunchKernelGGL((k_adjoint_d2q9<R, true>), dim3(blocks), dim3(256), 0, s, a, (const R*)mu_in, inj,
                        (R*)mu_out, grad, inv_kappa);
