@@ -20,7 +20,7 @@ from paper_1404_2363_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
 
-TOL = {"fp64": 1e-12, "fp32": 1e-5}
+TOL = {"fp64": 1e-12, "fp32": 1e-5, "fp16": 1e-3}
 
 
 def _solver(*a, **k):
@@ -207,7 +207,7 @@ def cellular_full():
     return W.cellular()
 
 
-@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "fp16"])
 def test_full_size_sampled_nodes(cellular_full, precision):
     wl = cellular_full
     steps = 40
