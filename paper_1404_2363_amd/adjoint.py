@@ -12,7 +12,7 @@ D only through the flux block A = (3 D + I/2)^-1.
 from __future__ import annotations
 
 import dataclasses
-from typing import Optional, Sequence
+from typing import Sequence
 
 import torch
 

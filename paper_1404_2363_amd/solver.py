@@ -5,7 +5,6 @@ stream; every step, readout and reduction runs in ``liblbm_cde.so``.
 """
 from __future__ import annotations
 
-import math
 from typing import Optional, Sequence
 
 import numpy as np

@@ -5,11 +5,9 @@
 * Descriptor validation (pure host logic) rejects invalid runs with the
   documented status codes; workspace sizes follow the documented layout.
 """
-import ctypes
 import os
 import re
 
-import numpy as np
 import pytest
 
 from paper_1404_2363_amd import _lib as L

@@ -9,8 +9,6 @@ single launches, the full 4096^2 cellular grid checked node by node on
 sampled nodes (the oracle computes each from its dependence cone), FP64
 reductions, and the documented error paths.
 """
-import math
-import os
 
 import numpy as np
 import pytest
