@@ -342,7 +342,10 @@ __global__ __launch_bounds__(BX * BY) void k_step_d2q9_split_p(const RunArgs a, 
   int hl[NR];
 #pragma unroll
   for (int j = 0; j < NR; ++j) {
-    const int r = min(tid + j * NT_, RN - 1);
+    // the ring is not a multiple of the block: waves past its end skip the
+    // staging (uniformly, so the remaining loads keep their order)
+    if (tid + j * NT_ >= RN) continue;
+    const int r = tid + j * NT_;
     int lx, ly;
     if (r < BX + 2) {
       lx = r;
