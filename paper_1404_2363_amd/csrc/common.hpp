@@ -42,6 +42,12 @@ struct RunArgs {
   // host exactly as the kernels' own FP32 set-up rounds them: s1 s2 s7 s8 s4
   // s6 axx axy ayy c34 c36 c54 c56 nl c2 (the FP16 split kernels read these)
   float relf[16];
+  // FP16 split storage, rounded on the host to FP32 as the kernels would:
+  // scale/36, scale/12, scale/6, scale/4 (the collision's output weights)
+  // and 1/scale
+  float split_k[4];
+  float split_inv;
+  void* split_dst[9];       // base of each destination half plane (periodic split step)
   int32_t xcd_remap;        // block order (see tile_of_block)
   int32_t rows32;           // D2Q9 batch: x periodic, constant D, every byte offset < 4 GiB
   int32_t active;           // 0: run has used its step budget

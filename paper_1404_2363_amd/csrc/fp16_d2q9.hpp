@@ -58,7 +58,7 @@ LBM_FORCEINLINE Rel2<float> host_rel2(const RunArgs& a) {
 // known at compile time; the results are the same bits as with the runtime
 // coefficients nl = 0, c2 = 2.
 template <typename R, bool MODIFIED_ONLY = false>
-LBM_FORCEINLINE void collide_neq_d2q9(const R (&f)[9], R ux, R uy, const Rel2<R>& r, R scale, R (&h)[9]) {
+LBM_FORCEINLINE void collide_neq_d2q9(const R (&f)[9], R ux, R uy, const Rel2<R>& r, const R (&k)[4], R (&h)[9]) {
   const R sa = f[1] + f[2] + f[3] + f[4];
   const R sd = f[5] + f[6] + f[7] + f[8];
   const R phi = f[0] + sa + sd;
@@ -93,9 +93,8 @@ LBM_FORCEINLINE void collide_neq_d2q9(const R (&f)[9], R ux, R uy, const Rel2<R>
   const R n4 = m4 + jx;
   const R n5 = m5 - jy;
   const R n6 = m6 + jy;
-  // scale (n - S n) / norm^2
-  const R k36 = scale * (R)(1.0 / 36.0), k12 = scale * (R)(1.0 / 12.0);
-  const R k6 = scale * (R)(1.0 / 6.0), k4 = scale * (R)0.25;
+  // scale (n - S n) / norm^2; k = scale/36, scale/12, scale/6, scale/4
+  const R k36 = k[0], k12 = k[1], k6 = k[2], k4 = k[3];
   const R b1 = (n1 - r.s1 * n1) * k36;
   const R b2 = (n2 - r.s2 * n2) * k36;
   const R b3 = (n3 - (r.axx * n3 + r.c34 * n4 + r.axy * n5 + r.c36 * n6)) * k6;
@@ -143,8 +142,12 @@ static_assert(kW0 + 8.0f * kW1 == 1.0f, "split rest weights must sum to one");
 LBM_FORCEINLINE float feq_moving(float ph, float ej, float c) { return __builtin_fmaf(ej, c, ph * kW1); }
 
 // e.(phi u) with e = (ex, ey), ex, ey in {-1, 0, 1}: exact for one nonzero
-// component, one rounding for two.
-LBM_FORCEINLINE float e_dot_j(float ex, float ey, float jx, float jy) { return __builtin_fmaf(ey, jy, ex * jx); }
+// component (no addition of a zero product), one rounding for two.
+LBM_FORCEINLINE float e_dot_j(int ex, int ey, float jx, float jy) {
+  if (ex == 0) return (float)ey * jy;
+  if (ey == 0) return (float)ex * jx;
+  return __builtin_fmaf((float)ey, jy, (float)ex * jx);
+}
 
 // Scale, round and saturate to half; flags an out-of-range value.
 LBM_FORCEINLINE __half to_half(float v, float scale, bool& over) {
@@ -238,7 +241,7 @@ __global__ __launch_bounds__(BX * BY) void k_step_d2q9_split(const RunArgs a, un
   const int64_t x = tx0 + threadIdx.x, y = ty0 + threadIdx.y;
   if (x >= a.nx || y >= a.ny) return;
   const __half* __restrict__ src = (const __half*)a.src;
-  const float inv = (float)a.fp16_inv_scale;
+  const float inv = a.split_inv;
   float f[9];
   // f_i = f_eq_j(phi(s), u(s)) + h_j(s) / scale with f_eq_j = w phi + c e_j.(phi u)
 #define LBM_SPLIT_PULL(I, EX, EY)                                                        \
@@ -261,7 +264,7 @@ __global__ __launch_bounds__(BX * BY) void k_step_d2q9_split(const RunArgs a, un
     else {                                                                               \
       const int ex = (pop == 1 || pop == 5 || pop == 8) ? 1 : (pop == 3 || pop == 6 || pop == 7) ? -1 : 0; \
       const int ey = (pop == 2 || pop == 5 || pop == 6) ? 1 : (pop == 4 || pop == 7 || pop == 8) ? -1 : 0; \
-      const float ej = e_dot_j((float)ex, (float)ey, jx, jy);                            \
+      const float ej = e_dot_j(ex, ey, jx, jy);                                          \
       feq = feq_moving(ph, ej, pop <= 4 ? (1.0f / 3.0f) : (1.0f / 12.0f));               \
     }                                                                                    \
     f[I] = __builtin_fmaf(__half2float(src[(int64_t)pop * a.plane + sy * a.nx + sx]), inv, feq); \
@@ -280,7 +283,7 @@ __global__ __launch_bounds__(BX * BY) void k_step_d2q9_split(const RunArgs a, un
   velocity2<float>(a, x, y, ux, uy);
   const float phi = f[0] + f[1] + f[2] + f[3] + f[4] + f[5] + f[6] + f[7] + f[8];
   float h[9];
-  collide_neq_d2q9<float, true>(f, ux, uy, host_rel2(a), (float)a.fp16_scale, h);
+  collide_neq_d2q9<float, true>(f, ux, uy, host_rel2(a), a.split_k, h);
   const int64_t node = y * a.nx + x;
   ((float*)a.dst_phi)[node] = phi;
   __half* __restrict__ dst = (__half*)a.dst;
@@ -397,7 +400,7 @@ __global__ __launch_bounds__(BX * BY) void k_step_d2q9_split_p(const RunArgs a, 
   }
   __syncthreads();
   if (!active) return;
-  const float inv = (float)a.fp16_inv_scale;
+  const float inv = a.split_inv;
   const int lx = threadIdx.x + 1, ly = threadIdx.y + 1;
   float f[9];
 #define LBM_SPLIT_P(I, EX, EY)                                                                       \
@@ -407,7 +410,7 @@ __global__ __launch_bounds__(BX * BY) void k_step_d2q9_split_p(const RunArgs a, 
     float feq;                                                                                     \
     if ((I) == 0) feq = ph * kW0;                                                                  \
     else                                                                                           \
-      feq = feq_moving(ph, e_dot_j((float)(EX), (float)(EY), (EX) != 0 ? sjx[sy][sx] : 0.0f,        \
+      feq = feq_moving(ph, e_dot_j((EX), (EY), (EX) != 0 ? sjx[sy][sx] : 0.0f,                      \
                                    (EY) != 0 ? sjy[sy][sx] : 0.0f),                                \
                        ((EX) == 0 || (EY) == 0) ? (1.0f / 3.0f) : (1.0f / 12.0f));                 \
     f[I] = __builtin_fmaf(__half2float(raw[I]), inv, feq);                                         \
@@ -424,15 +427,18 @@ __global__ __launch_bounds__(BX * BY) void k_step_d2q9_split_p(const RunArgs a, 
 #undef LBM_SPLIT_P
   const float phi = f[0] + f[1] + f[2] + f[3] + f[4] + f[5] + f[6] + f[7] + f[8];
   float h[9];
-  collide_neq_d2q9<float, true>(f, ux, uy, host_rel2(a), (float)a.fp16_scale, h);
-  const uint32_t nb = (r0 + x) * 2u;  // byte offset of the node in a half plane
+  collide_neq_d2q9<float, true>(f, ux, uy, host_rel2(a), a.split_k, h);
+  uint32_t nb = (r0 + x) * 2u;  // byte offset of the node in a half plane
+  // keep nb an opaque 32-bit value so that every store below takes the
+  // uniform-base + 32-bit-offset form instead of a 64-bit address per store
+  asm volatile("" : "+v"(nb));
   store_pop<float, NT>((float*)((char*)a.dst_phi + nb * 2u), phi);
-  char* __restrict__ dst = (char*)a.dst;
   float mx = 0.0f;
 #pragma unroll
   for (int i = 0; i < 9; ++i) {
     const unsigned short v = __half_as_ushort(to_half_clamped(h[i], mx));
-    unsigned short* p = (unsigned short*)(dst + i * pb + nb);
+    // a uniform plane base from the arguments plus the node's 32-bit offset
+    unsigned short* p = (unsigned short*)((char*)a.split_dst[i] + nb);
     if constexpr (NT) __builtin_nontemporal_store(v, p);
     else *p = v;
   }

@@ -423,6 +423,16 @@ RunArgs make_args(const lbm_cde* h, const Run& r, int parity) {
   a.dst_phi = r.phi[parity ^ 1];
   a.fp16_scale = r.half ? r.fp16_scale : 1.0;
   a.fp16_inv_scale = r.half ? 1.0 / r.fp16_scale : 1.0;
+  {
+    const float sc = (float)a.fp16_scale;
+    a.split_k[0] = sc * (float)(1.0 / 36.0);
+    a.split_k[1] = sc * (float)(1.0 / 12.0);
+    a.split_k[2] = sc * (float)(1.0 / 6.0);
+    a.split_k[3] = sc * 0.25f;
+    a.split_inv = (float)a.fp16_inv_scale;
+    if (r.half && a.dst)
+      for (int i = 0; i < 9; ++i) a.split_dst[i] = (char*)a.dst + (size_t)i * (size_t)r.plane * 2u;
+  }
   a.fp16_flags = r.flags ? (void*)&r.flags[1] : nullptr;
   a.nx = r.d.nx;
   a.ny = r.d.ny;
