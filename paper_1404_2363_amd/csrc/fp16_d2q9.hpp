@@ -138,8 +138,18 @@ static_assert(kW0 + 8.0f * kW1 == 1.0f, "split rest weights must sum to one");
 
 // f_eq of a moving population from phi and e.(phi u) at its node, in one
 // fixed rounding order (both split kernels use it, so their results are
-// bitwise equal): c = 1/3 on the axes, 1/12 on the diagonals.
-LBM_FORCEINLINE float feq_moving(float ph, float ej, float c) { return __builtin_fmaf(ej, c, ph * kW1); }
+// bitwise equal): c = 1/3 on the axes, 1/12 on the diagonals.  The two
+// populations of a node with opposite velocities carry e.(phi u) of opposite
+// sign; both come from t = w phi + c |e.(phi u)|, one as t and the other as
+// 2 w phi - t (exact), so every such pair sums to exactly 2 w phi.  Rounding
+// w phi + c e.(phi u) and w phi - c e.(phi u) separately is biased where one
+// of them crosses a power of two (the rounding grid changes there, and both
+// terms scale with phi): the total then drifted by about +3e-10 per step.
+LBM_FORCEINLINE float feq_moving(float ph, float ej, float c) {
+  const float p = ph * kW1;
+  const float t = __builtin_fmaf(fabsf(ej), c, p);
+  return ej >= 0.0f ? t : __builtin_fmaf(2.0f, p, -t);
+}
 
 // e.(phi u) with e = (ex, ey), ex, ey in {-1, 0, 1}: exact for one nonzero
 // component (no addition of a zero product), one rounding for two.
