@@ -38,14 +38,10 @@ struct RunArgs {
   double s[15];             // s[k] by moment index (flux-row entries unused)
   double A[3][3];           // flux block s_ab
   double heat[3];           // s4, s6, s8
-  // the D2Q9 FP32 relaxation coefficients of a constant-D run, rounded on the
-  // host exactly as the kernels' own FP32 set-up rounds them: s1 s2 s7 s8 s4
-  // s6 axx axy ayy c34 c36 c54 c56 nl c2 (the FP16 split kernels read these)
-  float relf[16];
-  // FP16 split storage, rounded on the host to FP32 as the kernels would:
-  // scale/36, scale/12, scale/6, scale/4 (the collision's output weights)
-  // and 1/scale
-  float split_k[4];
+  // FP16 split storage (MRT-A, constant D), rounded once on the host: the
+  // rows of (I - S) times the storage scale over |M_k|^2 (see
+  // collide_neq_d2q9) and 1/scale
+  float split_g[14];
   float split_inv;
   void* split_dst[9];       // base of each destination half plane (periodic split step)
   int32_t xcd_remap;        // block order (see tile_of_block)

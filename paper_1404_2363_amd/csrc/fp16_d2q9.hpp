@@ -28,86 +28,43 @@ namespace lbm {
 
 constexpr float kHalfMax = 65504.0f;
 
-// Rates of a constant-D run from the host-rounded FP32 copy.
-LBM_FORCEINLINE Rel2<float> host_rel2(const RunArgs& a) {
-  Rel2<float> r;
-  r.s1 = a.relf[0];
-  r.s2 = a.relf[1];
-  r.s7 = a.relf[2];
-  r.s8 = a.relf[3];
-  r.s4 = a.relf[4];
-  r.s6 = a.relf[5];
-  r.axx = a.relf[6];
-  r.axy = a.relf[7];
-  r.ayy = a.relf[8];
-  r.c34 = a.relf[9];
-  r.c36 = a.relf[10];
-  r.c54 = a.relf[11];
-  r.c56 = a.relf[12];
-  r.nl = a.relf[13];
-  r.c2 = a.relf[14];
-  return r;
-}
-
-// The non-equilibrium part of the post-collision populations times a scale,
-// h = scale (f' - f_eq(phi, u)), of one node with unshifted populations f.
-// Since f_eq = M^-1 m_eq, h = M^-1 (n - S n) with n = M f - m_eq: the
-// increments of collide_d2q9 are formed the same way and the add/sub tree of
-// M^T is applied to scale (n - S n)/norm^2 directly, without forming f' or f_eq.
-// MODIFIED_ONLY: the run is MRT-A (no u^2 equilibrium terms, m2_eq = 2 phi),
-// known at compile time; the results are the same bits as with the runtime
-// coefficients nl = 0, c2 = 2.
-template <typename R, bool MODIFIED_ONLY = false>
-LBM_FORCEINLINE void collide_neq_d2q9(const R (&f)[9], R ux, R uy, const Rel2<R>& r, const R (&k)[4], R (&h)[9]) {
-  const R sa = f[1] + f[2] + f[3] + f[4];
-  const R sd = f[5] + f[6] + f[7] + f[8];
-  const R phi = f[0] + sa + sd;
-  const R m1 = (R)2 * sd - sa - (R)4 * f[0];
-  const R m2 = (R)4 * f[0] - (R)2 * sa + sd;
-  const R dx13 = f[1] - f[3];
-  const R dx58 = f[5] - f[6] - f[7] + f[8];
-  const R dy24 = f[2] - f[4];
-  const R dy56 = f[5] + f[6] - f[7] - f[8];
-  const R m3 = dx13 + dx58;
-  const R m4 = dx58 - (R)2 * dx13;
-  const R m5 = dy24 + dy56;
-  const R m6 = dy56 - (R)2 * dy24;
-  const R m7 = f[1] - f[2] + f[3] - f[4];
-  const R m8 = f[5] - f[6] + f[7] - f[8];
-  const R jx = phi * ux, jy = phi * uy;
-  R n1, n2, n7, n8;
-  if constexpr (MODIFIED_ONLY) {
-    n1 = m1 + (R)2 * phi;
-    n2 = m2 - (R)2 * phi;
-    n7 = m7;
-    n8 = m8;
-  } else {
-    const R q = r.nl * phi;
-    const R u2 = ux * ux + uy * uy;
-    n1 = m1 + (R)2 * phi - (R)3 * q * u2;
-    n2 = m2 - r.c2 * phi + (R)3 * q * u2;
-    n7 = m7 - q * (ux * ux - uy * uy);
-    n8 = m8 - q * ux * uy;
-  }
-  const R n3 = m3 - jx;
-  const R n4 = m4 + jx;
-  const R n5 = m5 - jy;
-  const R n6 = m6 + jy;
-  // scale (n - S n) / norm^2; k = scale/36, scale/12, scale/6, scale/4
-  const R k36 = k[0], k12 = k[1], k6 = k[2], k4 = k[3];
-  const R b1 = (n1 - r.s1 * n1) * k36;
-  const R b2 = (n2 - r.s2 * n2) * k36;
-  const R b3 = (n3 - (r.axx * n3 + r.c34 * n4 + r.axy * n5 + r.c36 * n6)) * k6;
-  const R b4 = (n4 - r.s4 * n4) * k12;
-  const R b5 = (n5 - (r.axy * n3 + r.c54 * n4 + r.ayy * n5 + r.c56 * n6)) * k6;
-  const R b6 = (n6 - r.s6 * n6) * k12;
-  const R b7 = (n7 - r.s7 * n7) * k4;
-  const R b8 = (n8 - r.s8 * n8) * k4;
-  const R ax = -b1 - (R)2 * b2;
-  const R dg = (R)2 * b1 + b2;
-  const R q3 = b3 - (R)2 * b4, q5 = b5 - (R)2 * b6;
-  const R p3 = b3 + b4, p5 = b5 + b6;
-  h[0] = (R)4 * (b2 - b1);
+// The non-equilibrium part of the post-collision populations times the
+// storage scale, h = scale (f' - f_eq(phi, u)), of one node of an MRT-A run
+// with unshifted populations f, and phi = sum f.  Since f_eq = M^-1 m_eq
+// (m_eq of Eq. 37), h = scale M^-1 (I - S) n with n = M f - m_eq, and
+// M^-1 = M^T diag(1/|M_k|^2).  g holds the rows of (I - S) (Eq. 31) already
+// multiplied by scale/|M_k|^2 and rounded once on the host: (1 - s1) k36,
+// (1 - s2) k36, (1 - s4) k12, (1 - s6) k12, (1 - s7) k4, (1 - s8) k4, then
+// row 3 and row 5 of (I - S) over n3..n6 times k6 (kN = scale / N).
+LBM_FORCEINLINE void collide_neq_d2q9(const float (&f)[9], float ux, float uy, const float (&g)[14], float (&h)[9],
+                                      float& phi) {
+  const float sa = f[1] + f[2] + f[3] + f[4];
+  const float sd = f[5] + f[6] + f[7] + f[8];
+  phi = f[0] + sa + sd;
+  const float m1 = 2.0f * sd - sa - 4.0f * f[0];
+  const float m2 = 4.0f * f[0] - 2.0f * sa + sd;
+  const float dx13 = f[1] - f[3];
+  const float dx58 = f[5] - f[6] - f[7] + f[8];
+  const float dy24 = f[2] - f[4];
+  const float dy56 = f[5] + f[6] - f[7] - f[8];
+  const float m3 = dx13 + dx58;
+  const float m4 = dx58 - 2.0f * dx13;
+  const float m5 = dy24 + dy56;
+  const float m6 = dy56 - 2.0f * dy24;
+  const float m7 = f[1] - f[2] + f[3] - f[4];
+  const float m8 = f[5] - f[6] + f[7] - f[8];
+  const float jx = phi * ux, jy = phi * uy;
+  const float n1 = m1 + 2.0f * phi, n2 = m2 - 2.0f * phi;
+  const float n3 = m3 - jx, n4 = m4 + jx, n5 = m5 - jy, n6 = m6 + jy;
+  const float b1 = g[0] * n1, b2 = g[1] * n2, b4 = g[2] * n4, b6 = g[3] * n6;
+  const float b7 = g[4] * m7, b8 = g[5] * m8;
+  const float b3 = __builtin_fmaf(g[9], n6, __builtin_fmaf(g[8], n5, __builtin_fmaf(g[7], n4, g[6] * n3)));
+  const float b5 = __builtin_fmaf(g[13], n6, __builtin_fmaf(g[12], n5, __builtin_fmaf(g[11], n4, g[10] * n3)));
+  const float ax = -b1 - 2.0f * b2;
+  const float dg = 2.0f * b1 + b2;
+  const float q3 = b3 - 2.0f * b4, q5 = b5 - 2.0f * b6;
+  const float p3 = b3 + b4, p5 = b5 + b6;
+  h[0] = 4.0f * (b2 - b1);
   h[1] = ax + q3 + b7;
   h[2] = ax + q5 - b7;
   h[3] = ax - q3 + b7;
@@ -145,11 +102,12 @@ static_assert(kW0 + 8.0f * kW1 == 1.0f, "split rest weights must sum to one");
 // w phi + c e.(phi u) and w phi - c e.(phi u) separately is biased where one
 // of them crosses a power of two (the rounding grid changes there, and both
 // terms scale with phi): the total then drifted by about +3e-10 per step.
-LBM_FORCEINLINE float feq_moving(float ph, float ej, float c) {
-  const float p = ph * kW1;
+// p = w phi = phi * kW1.
+LBM_FORCEINLINE float feq_moving_w(float p, float ej, float c) {
   const float t = __builtin_fmaf(fabsf(ej), c, p);
   return ej >= 0.0f ? t : __builtin_fmaf(2.0f, p, -t);
 }
+LBM_FORCEINLINE float feq_moving(float ph, float ej, float c) { return feq_moving_w(ph * kW1, ej, c); }
 
 // e.(phi u) with e = (ex, ey), ex, ey in {-1, 0, 1}: exact for one nonzero
 // component (no addition of a zero product), one rounding for two.
@@ -291,9 +249,8 @@ __global__ __launch_bounds__(BX * BY) void k_step_d2q9_split(const RunArgs a, un
 #undef LBM_SPLIT_PULL
   float ux, uy;
   velocity2<float>(a, x, y, ux, uy);
-  const float phi = f[0] + f[1] + f[2] + f[3] + f[4] + f[5] + f[6] + f[7] + f[8];
-  float h[9];
-  collide_neq_d2q9<float, true>(f, ux, uy, host_rel2(a), a.split_k, h);
+  float h[9], phi;
+  collide_neq_d2q9(f, ux, uy, a.split_g, h, phi);
   const int64_t node = y * a.nx + x;
   ((float*)a.dst_phi)[node] = phi;
   __half* __restrict__ dst = (__half*)a.dst;
@@ -321,7 +278,8 @@ template <int BX, int BY, bool NT>
 __global__ __launch_bounds__(BX * BY) void k_step_d2q9_split_p(const RunArgs a, unsigned* __restrict__ overflow) {
   constexpr int NT_ = BX * BY, RN = 2 * (BX + 2) + 2 * BY;  // ring (halo) entries of the tile
   constexpr int NR = (RN + NT_ - 1) / NT_;                      // ring entries per thread
-  __shared__ float sphi[BY + 2][BX + 2], sjx[BY + 2][BX + 2], sjy[BY + 2][BX + 2];
+  // w phi, phi ux, phi uy of the tile and its halo
+  __shared__ float swp[BY + 2][BX + 2], sjx[BY + 2][BX + 2], sjy[BY + 2][BX + 2];
   const uint32_t nx = (uint32_t)a.nx, ny = (uint32_t)a.ny;
   const uint32_t ntx = (nx + BX - 1) / BX;
   const uint32_t b = (uint32_t)tile_of_block(blockIdx.x, gridDim.x, ntx, a.xcd_remap);
@@ -392,10 +350,10 @@ __global__ __launch_bounds__(BX * BY) void k_step_d2q9_split_p(const RunArgs a, 
   __half raw[9];
 #pragma unroll
   for (int i = 0; i < 9; ++i) raw[i] = *(const __half*)(src + i * pb + off[i] * 2u);
-  // phi, phi ux, phi uy of the tile; u in velocity2's product order
+  // w phi, phi ux, phi uy of the tile; u in velocity2's product order
   const float ux = sep ? ((ax0 * ox) * oy) * zx : cux;
   const float uy = sep ? ((ay0 * px) * py) * zy : cuy;
-  sphi[threadIdx.y + 1][threadIdx.x + 1] = ph_own;
+  swp[threadIdx.y + 1][threadIdx.x + 1] = ph_own * kW1;
   sjx[threadIdx.y + 1][threadIdx.x + 1] = ph_own * ux;
   sjy[threadIdx.y + 1][threadIdx.x + 1] = ph_own * uy;
 #pragma unroll
@@ -403,7 +361,7 @@ __global__ __launch_bounds__(BX * BY) void k_step_d2q9_split_p(const RunArgs a, 
     if (tid + j * NT_ < RN) {
       const float hux = sep ? ((ax0 * hx[j]) * vx[j]) * zx : cux;
       const float huy = sep ? ((ay0 * hy[j]) * vy[j]) * zy : cuy;
-      (&sphi[0][0])[hl[j]] = hphi[j];
+      (&swp[0][0])[hl[j]] = hphi[j] * kW1;
       (&sjx[0][0])[hl[j]] = hphi[j] * hux;
       (&sjy[0][0])[hl[j]] = hphi[j] * huy;
     }
@@ -416,13 +374,12 @@ __global__ __launch_bounds__(BX * BY) void k_step_d2q9_split_p(const RunArgs a, 
 #define LBM_SPLIT_P(I, EX, EY)                                                                       \
   {                                                                                                \
     const int sx = lx - (EX), sy = ly - (EY);                                                      \
-    const float ph = sphi[sy][sx];                                                                 \
     float feq;                                                                                     \
-    if ((I) == 0) feq = ph * kW0;                                                                  \
+    if ((I) == 0) feq = ph_own * kW0;                                                              \
     else                                                                                           \
-      feq = feq_moving(ph, e_dot_j((EX), (EY), (EX) != 0 ? sjx[sy][sx] : 0.0f,                      \
-                                   (EY) != 0 ? sjy[sy][sx] : 0.0f),                                \
-                       ((EX) == 0 || (EY) == 0) ? (1.0f / 3.0f) : (1.0f / 12.0f));                 \
+      feq = feq_moving_w(swp[sy][sx], e_dot_j((EX), (EY), (EX) != 0 ? sjx[sy][sx] : 0.0f,           \
+                                              (EY) != 0 ? sjy[sy][sx] : 0.0f),                     \
+                         ((EX) == 0 || (EY) == 0) ? (1.0f / 3.0f) : (1.0f / 12.0f));               \
     f[I] = __builtin_fmaf(__half2float(raw[I]), inv, feq);                                         \
   }
   LBM_SPLIT_P(0, 0, 0)
@@ -435,9 +392,8 @@ __global__ __launch_bounds__(BX * BY) void k_step_d2q9_split_p(const RunArgs a, 
   LBM_SPLIT_P(7, -1, -1)
   LBM_SPLIT_P(8, 1, -1)
 #undef LBM_SPLIT_P
-  const float phi = f[0] + f[1] + f[2] + f[3] + f[4] + f[5] + f[6] + f[7] + f[8];
-  float h[9];
-  collide_neq_d2q9<float, true>(f, ux, uy, host_rel2(a), a.split_k, h);
+  float h[9], phi;
+  collide_neq_d2q9(f, ux, uy, a.split_g, h, phi);
   uint32_t nb = (r0 + x) * 2u;  // byte offset of the node in a half plane
   // keep nb an opaque 32-bit value so that every store below takes the
   // uniform-base + 32-bit-offset form instead of a 64-bit address per store

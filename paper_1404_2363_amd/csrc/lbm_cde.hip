@@ -423,16 +423,9 @@ RunArgs make_args(const lbm_cde* h, const Run& r, int parity) {
   a.dst_phi = r.phi[parity ^ 1];
   a.fp16_scale = r.half ? r.fp16_scale : 1.0;
   a.fp16_inv_scale = r.half ? 1.0 / r.fp16_scale : 1.0;
-  {
-    const float sc = (float)a.fp16_scale;
-    a.split_k[0] = sc * (float)(1.0 / 36.0);
-    a.split_k[1] = sc * (float)(1.0 / 12.0);
-    a.split_k[2] = sc * (float)(1.0 / 6.0);
-    a.split_k[3] = sc * 0.25f;
-    a.split_inv = (float)a.fp16_inv_scale;
-    if (r.half && a.dst)
-      for (int i = 0; i < 9; ++i) a.split_dst[i] = (char*)a.dst + (size_t)i * (size_t)r.plane * 2u;
-  }
+  a.split_inv = (float)a.fp16_inv_scale;
+  if (r.half && a.dst)
+    for (int i = 0; i < 9; ++i) a.split_dst[i] = (char*)a.dst + (size_t)i * (size_t)r.plane * 2u;
   a.fp16_flags = r.flags ? (void*)&r.flags[1] : nullptr;
   a.nx = r.d.nx;
   a.ny = r.d.ny;
@@ -450,17 +443,18 @@ RunArgs make_args(const lbm_cde* h, const Run& r, int parity) {
   for (int i = 0; i < 3; ++i)
     for (int j = 0; j < 3; ++j) a.A[i][j] = r.A[i][j];
   for (int i = 0; i < 3; ++i) a.heat[i] = r.heat[i];
-  {
-    // FP32 copies of the D2Q9 rates, rounded as the device's own FP32 set-up
-    const float s4 = (float)r.heat[0], s6 = (float)r.heat[1];
-    const float axx = (float)r.A[0][0], axy = (float)r.A[0][1], ayy = (float)r.A[1][1];
-    const bool modified = r.d.model == LBM_CDE_MRT_A;
-    const bool nl = r.d.model == LBM_CDE_MRT_B1 || r.d.model == LBM_CDE_MRT_B2;
-    const float v[16] = {(float)r.s[1], (float)r.s[2], (float)r.s[7], (float)r.s[8], s4, s6, axx, axy, ayy,
-                         modified ? (axx * 0.5f - 1.0f) * s4 : 0.0f, modified ? (axy * 0.5f) * s6 : 0.0f,
-                         modified ? (axy * 0.5f) * s4 : 0.0f, modified ? (ayy * 0.5f - 1.0f) * s6 : 0.0f,
-                         nl ? 1.0f : 0.0f, r.d.model == LBM_CDE_MRT_B1 ? 1.0f : 2.0f, 0.0f};
-    for (int i = 0; i < 16; ++i) a.relf[i] = v[i];
+  if (r.split) {
+    // rows of (I - S) of MRT-A (Eq. 31) times scale / |M_k|^2, in FP64, rounded once
+    const double sc = a.fp16_scale, k36 = sc / 36.0, k12 = sc / 12.0, k6 = sc / 6.0, k4 = sc / 4.0;
+    const double s4 = r.heat[0], s6 = r.heat[1];
+    const double axx = r.A[0][0], axy = r.A[0][1], ayy = r.A[1][1];
+    const double c34 = (axx * 0.5 - 1.0) * s4, c36 = (axy * 0.5) * s6;
+    const double c54 = (axy * 0.5) * s4, c56 = (ayy * 0.5 - 1.0) * s6;
+    const double g[14] = {(1.0 - r.s[1]) * k36, (1.0 - r.s[2]) * k36, (1.0 - s4) * k12, (1.0 - s6) * k12,
+                          (1.0 - r.s[7]) * k4,  (1.0 - r.s[8]) * k4,  (1.0 - axx) * k6, -c34 * k6,
+                          -axy * k6,            -c36 * k6,            -axy * k6,        -c54 * k6,
+                          (1.0 - ayy) * k6,     -c56 * k6};
+    for (int i = 0; i < 14; ++i) a.split_g[i] = (float)g[i];
   }
   a.max_steps = r.d.max_steps;
   a.xref0 = r.d.xref0;
