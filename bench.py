@@ -268,7 +268,7 @@ def main():
     ap.add_argument("--quick", action="store_true", help="headline variant only")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (run with --gpus 1)", file=sys.stderr)
+        print("bench.py measures one GPU: the library has no multi-GPU path (run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
     import torch
     from paper_1404_2363_amd import _lib

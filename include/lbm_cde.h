@@ -58,7 +58,7 @@ enum {
   LBM_CDE_EHIP = -4,        /* HIP runtime error; the runtime's message is kept      */
   LBM_CDE_ENONFINITE = -5,  /* a reduction met NaN or Inf in the state               */
   LBM_CDE_ENOSPC = -6,      /* workspace smaller than lbm_cde_workspace_bytes()       */
-  LBM_CDE_EUNSUPPORTED = -7, /* a valid combination this build does not provide       */
+  LBM_CDE_EUNSUPPORTED = -7, /* a valid combination the library does not provide      */
   LBM_CDE_EOVERFLOW = -8     /* 16-bit storage saturated at least once (sticky)         */
 };
 
