@@ -383,22 +383,37 @@ LBM_FORCEINLINE void tile_rows_d2q9(const RunArgs& a, int64_t tile_x, int64_t ti
 // One step of every active run of a batch, in one persistent launch: the
 // grid walks a flat list of BX-wide row tiles spanning all runs.  The
 // global step t is read from device memory (so a captured graph stays valid)
-// and fixes the buffer parity; a run whose budget max_steps <= t is skipped.
+// and fixes the buffer parity.  The tile list holds the runs in order[] of
+// decreasing step budget (unlimited first), so the runs still active at t
+// (budget max_steps > t) own a prefix of it: blocks past that prefix exit at
+// once instead of searching and skipping the tiles of finished runs.
 template <typename R, int BX, bool NT>
 __global__ __launch_bounds__(BX) void k_batch_d2q9(const RunArgs* __restrict__ runs,
-                                                   const int64_t* __restrict__ tile_start, int nruns,
+                                                   const int64_t* __restrict__ tile_start,
+                                                   const int32_t* __restrict__ order, int nruns,
                                                    const int64_t* __restrict__ clock) {
   const int64_t t_global = clock[0];
-  const int64_t total = tile_start[nruns];
+  // number of active runs: the first position in order[] whose run is done
+  int na;
+  {
+    int lo = 0, hi = nruns;
+    while (lo < hi) {
+      const int mid = (lo + hi) / 2;
+      const int64_t ms = runs[order[mid]].max_steps;
+      if (ms >= 0 && t_global >= ms) hi = mid;
+      else lo = mid + 1;
+    }
+    na = lo;
+  }
+  const int64_t total = tile_start[na];
   for (int64_t t = blockIdx.x; t < total; t += gridDim.x) {
-    int lo = 0, hi = nruns - 1;
+    int lo = 0, hi = na - 1;
     while (lo < hi) {
       const int mid = (lo + hi + 1) / 2;
       if (tile_start[mid] <= t) lo = mid;
       else hi = mid - 1;
     }
-    const RunArgs& ar = runs[lo];
-    if (ar.max_steps >= 0 && t_global >= ar.max_steps) continue;
+    const RunArgs& ar = runs[order[lo]];
     RunArgs a = ar;
     if (t_global & 1) {
       a.src = ar.dst;

@@ -97,6 +97,7 @@ struct lbm_cde {
   bool batched = false;
   RunArgs* dev_runs = nullptr;       // per-run arguments (parity 0) in the workspace
   int64_t* dev_tiles = nullptr;      // tile_start[nruns + 1] of the flat tile list
+  int32_t* dev_order = nullptr;      // run of each tile-list position (decreasing step budget)
   int64_t* dev_clock = nullptr;      // [0] global steps, [1] history rows written
   double* batch_partial = nullptr;   // reduction partials [nruns][kBatchRedBlocks][3]
   int64_t global_steps = 0;
@@ -479,7 +480,8 @@ bool batch_eligible(const lbm_cde_run_desc* runs, int32_t nruns) {
 }
 
 size_t batch_bytes(int32_t nruns) {
-  return align_up(sizeof(RunArgs) * nruns) + align_up(sizeof(int64_t) * (nruns + 1)) + align_up(2 * sizeof(int64_t)) +
+  return align_up(sizeof(RunArgs) * nruns) + align_up(sizeof(int64_t) * (nruns + 1)) +
+         align_up(sizeof(int32_t) * nruns) + align_up(2 * sizeof(int64_t)) +
          align_up(sizeof(double) * 3 * kBatchRedBlocks * nruns);
 }
 
@@ -830,19 +832,32 @@ int init_runs(lbm_cde* h, const lbm_cde_run_desc* runs, int32_t nruns, const dou
     p += align_up(sizeof(RunArgs) * nruns);
     h->dev_tiles = (int64_t*)p;
     p += align_up(sizeof(int64_t) * (nruns + 1));
+    h->dev_order = (int32_t*)p;
+    p += align_up(sizeof(int32_t) * nruns);
     h->dev_clock = (int64_t*)p;
     p += align_up(2 * sizeof(int64_t));
     h->batch_partial = (double*)p;
     std::vector<RunArgs> args;
+    for (auto& r : h->runs) args.push_back(make_args(h, r, 0));
+    // tile list in order of decreasing step budget (unlimited first), so that
+    // the active runs always own a prefix of it
+    std::vector<int32_t> order(nruns);
+    for (int32_t i = 0; i < nruns; ++i) order[i] = i;
+    auto budget = [&](int32_t i) {
+      const int64_t m = h->runs[i].d.max_steps;
+      return m < 0 ? INT64_MAX : m;
+    };
+    std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) { return budget(x) > budget(y); });
     std::vector<int64_t> tiles(1, 0);
-    for (auto& r : h->runs) {
-      args.push_back(make_args(h, r, 0));
+    for (int32_t k = 0; k < nruns; ++k) {
+      const Run& r = h->runs[order[k]];
       tiles.push_back(tiles.back() + (r.d.nx + kBatchTile - 1) / kBatchTile * r.d.ny);
     }
     hipStream_t s = h->stream;
     HIP_TRY(nullptr, hipMemcpyAsync(h->dev_runs, args.data(), sizeof(RunArgs) * nruns, hipMemcpyHostToDevice, s));
     HIP_TRY(nullptr, hipMemcpyAsync(h->dev_tiles, tiles.data(), sizeof(int64_t) * (nruns + 1),
                                     hipMemcpyHostToDevice, s));
+    HIP_TRY(nullptr, hipMemcpyAsync(h->dev_order, order.data(), sizeof(int32_t) * nruns, hipMemcpyHostToDevice, s));
     HIP_TRY(nullptr, hipMemsetAsync(h->dev_clock, 0, 2 * sizeof(int64_t), s));
     HIP_TRY(nullptr, hipStreamSynchronize(s));
     int dev = 0, cus = 256;
@@ -865,10 +880,10 @@ void launch_batch_step(lbm_cde* h, hipStream_t s) {
   const int nr = (int)h->runs.size();
   if (h->runs[0].dbl)
     hipLaunchKernelGGL((k_batch_d2q9<double, kBatchTile, true>), dim3(h->batch_grid), dim3(kBatchTile), 0, s,
-                       h->dev_runs, h->dev_tiles, nr, h->dev_clock);
+                       h->dev_runs, h->dev_tiles, h->dev_order, nr, h->dev_clock);
   else
     hipLaunchKernelGGL((k_batch_d2q9<float, kBatchTile, true>), dim3(h->batch_grid), dim3(kBatchTile), 0, s,
-                       h->dev_runs, h->dev_tiles, nr, h->dev_clock);
+                       h->dev_runs, h->dev_tiles, h->dev_order, nr, h->dev_clock);
   hipLaunchKernelGGL(k_tick, dim3(1), dim3(64), 0, s, h->dev_clock, 0);
 }
 
