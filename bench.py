@@ -235,7 +235,7 @@ def copy_probe():
     torch.cuda.empty_cache()
 
 
-def cpu_baseline(wl, steps=2):
+def cpu_baseline(wl, steps=6):
     """The FP64 oracle as it stands, with one BLAS thread, on the same grid."""
     from oracle import lbm as O
     try:
