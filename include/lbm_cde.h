@@ -200,6 +200,20 @@ int lbm_cde_moments(lbm_cde_handle h, int32_t run, double* phi_out);
  * EOVERFLOW (with out filled) when 16-bit storage of the run has saturated. */
 int lbm_cde_reduce(lbm_cde_handle h, int32_t run, int32_t kind, double x_ref, double* out);
 
+/* For callers that cannot allocate memory or wait for the GPU (code under
+ * HIP graph capture, tight serving loops): the reduction of lbm_cde_reduce,
+ * enqueued on the handle's stream without waiting and without allocating.
+ * out is a device buffer of 4 doubles that receives S0, S1, S2 (S1 = S2 = 0
+ * unless kind is XMOMENTS; S0 = sum phi) and the number of non-finite stored
+ * values, for every kind; nothing is reported through the return status
+ * about the state (no ENONFINITE, no EOVERFLOW).  The partial sums live in a
+ * static device array of the library, one per GPU, held until the process
+ * ends (1 MiB: room for runs of up to 536,870,912 nodes; larger runs return
+ * EINVAL).  Every call on one GPU uses the same array: calls whose work can
+ * overlap on that GPU (other streams, other host threads) race and must be
+ * ordered by the caller.  Errors: EINVAL. */
+int lbm_cde_reduce_noalloc(lbm_cde_handle h, int32_t run, int32_t kind, double x_ref, double* out);
+
 /* Advance n steps and, after every `every` steps, append the XMOMENTS
  * (S0, S1, S2) of each run, taken about x_ref(t) of that run, to the device
  * history buffer hist (FP64, [capacity][nruns][3]).  Sampling continues the

@@ -87,6 +87,7 @@ def load() -> ctypes.CDLL:
         "lbm_cde_steps_done": [P, I32, ctypes.POINTER(I64)],
         "lbm_cde_moments": [P, I32, P],
         "lbm_cde_reduce": [P, I32, I32, D, ctypes.POINTER(D)],
+        "lbm_cde_reduce_noalloc": [P, I32, I32, D, P],
         "lbm_cde_run_sampled": [P, I64, I64, P, I64],
         "lbm_cde_samples_written": [P, ctypes.POINTER(I64)],
         "lbm_cde_relaxation_matrix": [P, I32, ctypes.POINTER(D)],
@@ -154,6 +155,11 @@ def lbm_cde_reduce(h: int, run: int, kind: int, x_ref: float = 0.0, allow_nonfin
     if not (allow_nonfinite and rc == LBM_CDE_ENONFINITE):
         _check(rc, "lbm_cde_reduce", h)
     return [out[0], out[1], out[2]], rc
+
+
+def lbm_cde_reduce_noalloc(h: int, run: int, kind: int, x_ref: float, out_ptr: int) -> None:
+    _check(load().lbm_cde_reduce_noalloc(h, run, kind, float(x_ref), ctypes.c_void_p(out_ptr)),
+           "lbm_cde_reduce_noalloc", h)
 
 
 def lbm_cde_run_sampled(h: int, n: int, every: int, hist_ptr: int, capacity: int) -> None:

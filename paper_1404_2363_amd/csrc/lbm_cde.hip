@@ -15,6 +15,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -27,6 +28,14 @@
 #include "fp16_d2q9.hpp"
 
 using namespace lbm;
+
+// Reduction partials of lbm_cde_reduce_noalloc (4 doubles per partial), for
+// callers that cannot allocate.  One copy per GPU, held until the process
+// ends; host code reaches it only through the address that
+// hipGetSymbolAddress returns on that GPU (see scratch_address).
+constexpr int64_t kScratchPartials = 32768;     // 1 MiB
+constexpr int64_t kNodesPerPartial = 16384;     // nodes reduced into one partial
+static __device__ __align__(256) double scratch[4 * kScratchPartials];
 
 namespace {
 
@@ -111,6 +120,7 @@ struct lbm_cde {
   Variant env3{128, 1, 1, true, 0};
   bool env16_set = false;     // LBM_CDE_TILE16 = BXxBY[xNT[xORDER]]: split 16-bit launch variant
   Variant env16{64, 4, 1, false, 0};
+  double* scratch_dev = nullptr;  // device address of `scratch` on the handle's GPU
 };
 
 namespace {
@@ -698,6 +708,26 @@ int reduce_into(lbm_cde* h, Run& r, int kind, double x_ref, double* out_dev) {
   return LBM_CDE_OK;
 }
 
+// Device address of `scratch` on the current GPU, looked up once per device.
+int scratch_address(double** out) {
+  static std::mutex mu;
+  static double* addr[64] = {};
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return fail_init(LBM_CDE_EHIP, "hipGetDevice: %s", hipGetErrorString(e));
+  if (dev < 0 || dev >= 64) return fail_init(LBM_CDE_EUNSUPPORTED, "device %d: at most 64 GPUs are supported", dev);
+  std::lock_guard<std::mutex> lock(mu);
+  if (!addr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail_init(LBM_CDE_EHIP, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+    addr[dev] = (double*)p;
+  }
+  *out = addr[dev];
+  return LBM_CDE_OK;
+}
+
 void parse_env(lbm_cde* h) {
   const char* t2 = std::getenv("LBM_CDE_TILE");
   const char* t3 = std::getenv("LBM_CDE_TILE3");
@@ -1072,7 +1102,8 @@ int lbm_cde_init(const lbm_cde_run_desc* runs, int32_t nruns, const double* cons
   lbm_cde* h = new lbm_cde();
   h->stream = (hipStream_t)hip_stream;
   parse_env(h);
-  const int rc = init_runs(h, runs, nruns, phi0, (char*)workspace, ws_bytes);
+  int rc = scratch_address(&h->scratch_dev);
+  if (!rc) rc = init_runs(h, runs, nruns, phi0, (char*)workspace, ws_bytes);
   if (rc) {
     if (h->capture) (void)hipStreamDestroy(h->capture);
     delete h;
@@ -1158,6 +1189,34 @@ int lbm_cde_reduce(lbm_cde_handle h, int32_t run, int32_t kind, double x_ref, do
     if (res[3] != 0.0) return fail(h, LBM_CDE_ENONFINITE, "reduce: %g non-finite values in the state", res[3]);
   }
   if (over) return fail(h, LBM_CDE_EOVERFLOW, "reduce: 16-bit storage of run %d saturated", run);
+  return LBM_CDE_OK;
+}
+
+int lbm_cde_reduce_noalloc(lbm_cde_handle h, int32_t run, int32_t kind, double x_ref, double* out) {
+  Run* r = get_run(h, run);
+  if (!r || !out) return fail(h, LBM_CDE_EINVAL, "reduce_noalloc: bad handle, run or pointer");
+  if (kind < LBM_CDE_RED_MASS || kind > LBM_CDE_RED_NONFINITE)
+    return fail(h, LBM_CDE_EINVAL, "reduce_noalloc: unknown kind %d", kind);
+  if (kind == LBM_CDE_RED_XMOMENTS && !std::isfinite(x_ref))
+    return fail(h, LBM_CDE_EINVAL, "reduce_noalloc: x_ref is not finite");
+  const int64_t nb = std::max<int64_t>(1, (r->nodes + kNodesPerPartial - 1) / kNodesPerPartial);
+  if (nb > kScratchPartials)
+    return fail(h, LBM_CDE_EINVAL,
+                "reduce_noalloc: run %d has %lld nodes; the static scratch holds the partials of at most %lld nodes",
+                run, (long long)r->nodes, (long long)(kScratchPartials * kNodesPerPartial));
+  const RunArgs a = make_args(h, *r, (int)(r->steps & 1));
+  double* partial = h->scratch_dev;  // every partial in [0, nb) is written before it is read
+  if (r->dbl)
+    hipLaunchKernelGGL(k_reduce_partial<double>, dim3((unsigned)nb), dim3(RED_THREADS), 0, h->stream, a, r->Q, kind,
+                       x_ref, partial);
+  else if (r->half)
+    hipLaunchKernelGGL(k_reduce_partial<__half>, dim3((unsigned)nb), dim3(RED_THREADS), 0, h->stream, a, r->Q, kind,
+                       x_ref, partial);
+  else
+    hipLaunchKernelGGL(k_reduce_partial<float>, dim3((unsigned)nb), dim3(RED_THREADS), 0, h->stream, a, r->Q, kind,
+                       x_ref, partial);
+  hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(RED_THREADS), 0, h->stream, (const double*)partial, (int)nb, out);
+  HIP_TRY(h, hipGetLastError());
   return LBM_CDE_OK;
 }
 
