@@ -47,7 +47,7 @@
 extern "C" {
 #endif
 
-#define LBM_CDE_ABI_VERSION 1
+#define LBM_CDE_ABI_VERSION 2
 
 /* ---- status codes -------------------------------------------------------- */
 enum {
@@ -238,24 +238,48 @@ int lbm_cde_relaxation_matrix(lbm_cde_handle h, int32_t run, double* S_out);
  * EINVAL if the run has no velocity field or an argument is NULL. */
 int lbm_cde_set_velocity(lbm_cde_handle h, int32_t run, const double* u);
 
-/* Autotuner: for every run, time `trials` launches of each compiled launch
- * variant (tile shape, streaming stores, XCD block order) and keep the
- * fastest.  Each timed launch reads the current state and overwrites only
- * the other population buffer, so the simulation state is unchanged.
- * Results are bitwise independent of the variant.  If the environment
- * variable LBM_CDE_TUNE_CACHE names a file, results are looked up there
- * (keyed by GPU architecture, lattice, precision, grid and boundaries) and
- * new ones appended.  Waits for the stream.  EINVAL for trials < 1. */
+/* Launch variants.  A variant is six integers: block x, block y, rows per
+ * thread, streaming stores (0/1), block order (0: hardware order, 1: each
+ * XCD takes a contiguous range of tiles, 2: tile rows interleaved over the 8
+ * XCDs with all x-tiles of a row on one XCD) and, for a batched handle
+ * (several D2Q9 runs in one FP64 or FP32 precision, stepped by one persistent
+ * launch over a flat list of block-x-wide row tiles), the number of blocks
+ * of that launch (0: one block per tile; otherwise each block walks every
+ * grid-th tile).  A batched handle has one variant for all its runs; the
+ * run index only has to be valid.  Results are bitwise the same for every
+ * variant. */
+
+/* Autotuner: time `trials` launches of every compiled variant (those listed
+ * by lbm_cde_variant_at) and keep the fastest, per run, or once for a
+ * batched handle.  Each timed launch reads the current state and overwrites
+ * only the other population buffer, so the simulation state is unchanged.
+ * If the environment variable LBM_CDE_TUNE_CACHE names a file, results are
+ * looked up there (keyed by GPU architecture, lattice, precision, grid and
+ * boundaries, and for a batch by every run's grid, boundaries and budget)
+ * and new ones appended.  Waits for the stream.  EINVAL for trials < 1. */
 int lbm_cde_tune(lbm_cde_handle h, int32_t trials);
 
-/* The launch variant of run `run`: out[0..4] = block x, block y, rows per
- * thread, streaming stores (0/1), block order
- * (0: hardware order, 1: each XCD takes a contiguous range of tiles, 2: tile
- * rows interleaved over the 8 XCDs with all x-tiles of a row on one XCD).
- * The environment variable LBM_CDE_TILE16 = "BXxBY[xNT[xORDER]]" (NT 1:
- * streaming stores; ORDER the block order), read by lbm_cde_init(), fixes the
- * FP16_SPLIT launch variant (as LBM_CDE_TILE does for FP32/FP64 D2Q9 runs). */
+/* The launch variant of run `run` into out[0..5] (layout above; out[5] is
+ * the launch's actual number of blocks on a batched handle, else 0).  The
+ * environment variables LBM_CDE_TILE = "BXxBYxNY", LBM_CDE_TILE3,
+ * LBM_CDE_NT, LBM_CDE_XCD, LBM_CDE_TILE16 = "BXxBY[xNT[xORDER]]" and
+ * LBM_CDE_BATCH = "BX[xNT[xGRID]]", read by lbm_cde_init(), fix the initial
+ * variant of D2Q9 FP64/FP32, D3Q15, FP16_SPLIT runs and batches. */
 int lbm_cde_get_variant(lbm_cde_handle h, int32_t run, int32_t* out);
+
+/* Number of compiled launch variants of run `run` (the tuner's candidates). */
+int lbm_cde_variant_count(lbm_cde_handle h, int32_t run, int32_t* count);
+
+/* Candidate `index` (0 <= index < count) of run `run` into out[0..5].
+ * EINVAL for an index out of range. */
+int lbm_cde_variant_at(lbm_cde_handle h, int32_t run, int32_t index, int32_t* out);
+
+/* Make v[0..5] the launch variant of run `run` (of the whole batch on a
+ * batched handle).  Captured graphs are rebuilt on the next step.  EINVAL
+ * if the variant is not compiled for the run (a block count must be 0 for a
+ * run stepped alone, >= 0 for a batch; the row-interleaved order needs a
+ * multiple of 8 tile rows).  Waits for the stream on a batched handle. */
+int lbm_cde_set_variant(lbm_cde_handle h, int32_t run, const int32_t* v);
 
 /* ---- state access (checkpoints) ------------------------------------------ */
 

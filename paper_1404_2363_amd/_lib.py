@@ -94,6 +94,9 @@ def load() -> ctypes.CDLL:
         "lbm_cde_set_velocity": [P, I32, P],
         "lbm_cde_tune": [P, I32],
         "lbm_cde_get_variant": [P, I32, ctypes.POINTER(I32)],
+        "lbm_cde_variant_count": [P, I32, ctypes.POINTER(I32)],
+        "lbm_cde_variant_at": [P, I32, I32, ctypes.POINTER(I32)],
+        "lbm_cde_set_variant": [P, I32, ctypes.POINTER(I32)],
         "lbm_cde_state_bytes": [P, I32, ctypes.POINTER(ctypes.c_size_t)],
         "lbm_cde_get_state": [P, I32, P],
         "lbm_cde_set_state": [P, I32, P, I64],
@@ -186,11 +189,37 @@ def lbm_cde_tune(h: int, trials: int) -> None:
     _check(load().lbm_cde_tune(h, trials), "lbm_cde_tune", h)
 
 
-def lbm_cde_get_variant(h: int, run: int):
-    out = (ctypes.c_int32 * 5)()
-    _check(load().lbm_cde_get_variant(h, run, out), "lbm_cde_get_variant", h)
+def _variant_dict(out) -> dict:
     return {"block": (out[0], out[1]), "rows_per_thread": out[2], "nt_stores": bool(out[3]),
-            "block_order": int(out[4])}
+            "block_order": int(out[4]), "grid": int(out[5])}
+
+
+def variant_tuple(v: dict) -> tuple:
+    """The six integers of a variant dict (as returned by lbm_cde_get_variant)."""
+    return (v["block"][0], v["block"][1], v["rows_per_thread"], int(v["nt_stores"]), v["block_order"], v["grid"])
+
+
+def lbm_cde_get_variant(h: int, run: int):
+    out = (ctypes.c_int32 * 6)()
+    _check(load().lbm_cde_get_variant(h, run, out), "lbm_cde_get_variant", h)
+    return _variant_dict(out)
+
+
+def lbm_cde_variant_count(h: int, run: int) -> int:
+    out = ctypes.c_int32(0)
+    _check(load().lbm_cde_variant_count(h, run, ctypes.byref(out)), "lbm_cde_variant_count", h)
+    return int(out.value)
+
+
+def lbm_cde_variant_at(h: int, run: int, index: int):
+    out = (ctypes.c_int32 * 6)()
+    _check(load().lbm_cde_variant_at(h, run, index, out), "lbm_cde_variant_at", h)
+    return _variant_dict(out)
+
+
+def lbm_cde_set_variant(h: int, run: int, v: dict) -> None:
+    arr = (ctypes.c_int32 * 6)(*variant_tuple(v))
+    _check(load().lbm_cde_set_variant(h, run, arr), "lbm_cde_set_variant", h)
 
 
 def lbm_cde_state_bytes(h: int, run: int) -> int:

@@ -43,7 +43,6 @@ thread_local std::string g_init_error;
 
 constexpr size_t kAlign = 256;
 constexpr int kGraphSteps = 32;   // steps per captured graph (an even number)
-constexpr int kBatchTile = 256;   // row-tile width of the batched kernel
 constexpr int kBatchRedBlocks = 64;  // reduction blocks per run in batched sampling
 
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
@@ -57,11 +56,16 @@ size_t plane_skew() {
   return skew;
 }
 
-// A launch variant of the step kernel: tile shape, store kind, block order.
+// A launch variant of the step kernel: tile shape, store kind, block order,
+// and for the batched persistent launch its number of blocks.
 struct Variant {
   int bx, by, ny;
-  bool nt;    // non-temporal (streaming) stores
-  int xcd;    // block order: 0 hardware, 1 XCD-contiguous ranges, 2 rows interleaved over XCDs
+  bool nt;       // non-temporal (streaming) stores
+  int xcd;       // block order: 0 hardware, 1 XCD-contiguous ranges, 2 rows interleaved over XCDs
+  int grid = 0;  // batched launch: blocks walking the tile list (0: one block per tile)
+  bool operator==(const Variant& o) const {
+    return bx == o.bx && by == o.by && ny == o.ny && nt == o.nt && xcd == o.xcd && grid == o.grid;
+  }
 };
 
 struct Run {
@@ -108,8 +112,11 @@ struct lbm_cde {
   int64_t* dev_tiles = nullptr;      // tile_start[nruns + 1] of the flat tile list
   int32_t* dev_order = nullptr;      // run of each tile-list position (decreasing step budget)
   int64_t* dev_clock = nullptr;      // [0] global steps, [1] history rows written
+  std::vector<int32_t> batch_order;  // host copy of dev_order
   double* batch_partial = nullptr;   // reduction partials [nruns][kBatchRedBlocks][3]
   int64_t global_steps = 0;
+  Variant batch_var{256, 1, 1, true, 0, 0};  // row-tile width, stores and grid of the batched launch
+  int64_t batch_tiles = 0;           // tiles of the flat list at batch_var.bx
   unsigned batch_grid = 0;
   hipGraphExec_t batch_graph = nullptr;
   hipGraphExec_t sample_graph = nullptr;
@@ -775,6 +782,73 @@ int choose_fp16_scale(Run& r, lbm_cde* h, const double* phi0, hipStream_t s) {
   return LBM_CDE_OK;
 }
 
+// Batched launch variants (row-tile width, streaming stores) compiled into the library.
+using BatchFn = void (*)(const lbm_cde*, hipStream_t);
+struct BatchEntry {
+  int bx;
+  bool nt;
+  BatchFn fn[2];  // [double?]
+};
+template <typename R, int BX, bool NT>
+void launch_batch(const lbm_cde* h, hipStream_t s) {
+  hipLaunchKernelGGL((k_batch_d2q9<R, BX, NT>), dim3(h->batch_grid), dim3(BX), 0, s, h->dev_runs, h->dev_tiles,
+                     h->dev_order, (int)h->runs.size(), h->dev_clock);
+}
+#define BATCH_ENTRY(BX, NT) \
+  BatchEntry { BX, NT, {launch_batch<float, BX, NT>, launch_batch<double, BX, NT>} }
+const BatchEntry kBatch[] = {BATCH_ENTRY(128, true), BATCH_ENTRY(256, true), BATCH_ENTRY(512, true),
+                             BATCH_ENTRY(128, false), BATCH_ENTRY(256, false), BATCH_ENTRY(512, false)};
+
+const BatchEntry* find_batch(const Variant& v) {
+  if (v.by != 1 || v.ny != 1 || v.xcd != 0 || v.grid < 0) return nullptr;
+  for (const auto& e : kBatch)
+    if (e.bx == v.bx && e.nt == v.nt) return &e;
+  return nullptr;
+}
+
+int compute_units() {
+  int dev = 0, cus = 256;
+  hipDeviceProp_t prop;
+  if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+    cus = prop.multiProcessorCount;
+  return cus;
+}
+
+// Candidates of the batched launch: every compiled row-tile width and store
+// kind, with one block per tile or a persistent grid of 8..64 blocks per CU.
+std::vector<Variant> batch_candidates() {
+  std::vector<Variant> out;
+  const int cus = compute_units();
+  for (const auto& e : kBatch)
+    for (int per_cu : {0, 8, 16, 32, 64}) out.push_back(Variant{e.bx, 1, 1, e.nt, 0, per_cu * cus});
+  return out;
+}
+
+// Make v the batched launch variant: the flat tile list (runs in order of
+// decreasing step budget, ceil(nx / bx) tiles per row) is rewritten in the
+// workspace and the captured graphs are dropped.  tiles_out, if given,
+// receives the host copy.
+int apply_batch_variant(lbm_cde* h, const Variant& v, std::vector<int64_t>* tiles_out) {
+  if (!find_batch(v)) return fail(h, LBM_CDE_EINVAL, "batch variant %dx%dx%d nt=%d order=%d grid=%d not built", v.bx,
+                                  v.by, v.ny, (int)v.nt, v.xcd, v.grid);
+  const int32_t nruns = (int32_t)h->runs.size();
+  std::vector<int64_t> tiles(1, 0);
+  for (int32_t k = 0; k < nruns; ++k) {
+    const Run& r = h->runs[h->batch_order[k]];
+    tiles.push_back(tiles.back() + (r.d.nx + v.bx - 1) / v.bx * r.d.ny);
+  }
+  if (tiles.back() >= ((int64_t)1 << 31)) return fail(h, LBM_CDE_EINVAL, "batch: too many tiles");
+  HIP_TRY(h, hipMemcpyAsync(h->dev_tiles, tiles.data(), sizeof(int64_t) * (nruns + 1), hipMemcpyHostToDevice,
+                            h->stream));
+  HIP_TRY(h, hipStreamSynchronize(h->stream));
+  drop_graphs(h);
+  h->batch_var = v;
+  h->batch_tiles = tiles.back();
+  h->batch_grid = (unsigned)(v.grid > 0 ? std::min<int64_t>(v.grid, tiles.back()) : tiles.back());
+  if (tiles_out) *tiles_out = tiles;
+  return LBM_CDE_OK;
+}
+
 // Per-run set-up of lbm_cde_init (errors go to the thread's init error text).
 int init_runs(lbm_cde* h, const lbm_cde_run_desc* runs, int32_t nruns, const double* const* phi0, char* workspace,
               size_t ws_bytes) {
@@ -878,28 +952,18 @@ int init_runs(lbm_cde* h, const lbm_cde_run_desc* runs, int32_t nruns, const dou
       return m < 0 ? INT64_MAX : m;
     };
     std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) { return budget(x) > budget(y); });
-    std::vector<int64_t> tiles(1, 0);
-    for (int32_t k = 0; k < nruns; ++k) {
-      const Run& r = h->runs[order[k]];
-      tiles.push_back(tiles.back() + (r.d.nx + kBatchTile - 1) / kBatchTile * r.d.ny);
-    }
+    h->batch_order = order;
     hipStream_t s = h->stream;
     HIP_TRY(nullptr, hipMemcpyAsync(h->dev_runs, args.data(), sizeof(RunArgs) * nruns, hipMemcpyHostToDevice, s));
-    HIP_TRY(nullptr, hipMemcpyAsync(h->dev_tiles, tiles.data(), sizeof(int64_t) * (nruns + 1),
-                                    hipMemcpyHostToDevice, s));
     HIP_TRY(nullptr, hipMemcpyAsync(h->dev_order, order.data(), sizeof(int32_t) * nruns, hipMemcpyHostToDevice, s));
     HIP_TRY(nullptr, hipMemsetAsync(h->dev_clock, 0, 2 * sizeof(int64_t), s));
     HIP_TRY(nullptr, hipStreamSynchronize(s));
-    int dev = 0, cus = 256;
-    hipDeviceProp_t prop;
-    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
-      cus = prop.multiProcessorCount;
-    // blocks of the persistent launch per CU (LBM_CDE_BATCH_BLOCKS; 0 = one block per tile)
-    int64_t per_cu = 64;
-    if (const char* e = std::getenv("LBM_CDE_BATCH_BLOCKS")) per_cu = std::atoll(e);
-    const int64_t cap = std::min<int64_t>(tiles.back(), (int64_t)1 << 30);
-    h->batch_grid = (unsigned)(per_cu > 0 ? std::min<int64_t>(cap, per_cu * cus) : cap);
     h->batched = true;
+    Variant bv = h->batch_var;
+    int bx = bv.bx, nt = 1, grid = 0;
+    if (const char* e = std::getenv("LBM_CDE_BATCH"))  // "BX[xNT[xGRID]]" fixes the batched launch variant
+      if (std::sscanf(e, "%dx%dx%d", &bx, &nt, &grid) >= 1) bv = Variant{bx, 1, 1, nt != 0, 0, grid};
+    if (apply_batch_variant(h, bv, nullptr)) return fail_init(LBM_CDE_EINVAL, "init: %s", h->err.c_str());
   }
   HIP_TRY(nullptr, hipStreamCreateWithFlags(&h->capture, hipStreamNonBlocking));
   return LBM_CDE_OK;
@@ -907,13 +971,7 @@ int init_runs(lbm_cde* h, const lbm_cde_run_desc* runs, int32_t nruns, const dou
 
 // One batched step: the persistent kernel, then the clock tick.
 void launch_batch_step(lbm_cde* h, hipStream_t s) {
-  const int nr = (int)h->runs.size();
-  if (h->runs[0].dbl)
-    hipLaunchKernelGGL((k_batch_d2q9<double, kBatchTile, true>), dim3(h->batch_grid), dim3(kBatchTile), 0, s,
-                       h->dev_runs, h->dev_tiles, h->dev_order, nr, h->dev_clock);
-  else
-    hipLaunchKernelGGL((k_batch_d2q9<float, kBatchTile, true>), dim3(h->batch_grid), dim3(kBatchTile), 0, s,
-                       h->dev_runs, h->dev_tiles, h->dev_order, nr, h->dev_clock);
+  find_batch(h->batch_var)->fn[h->runs[0].dbl ? 1 : 0](h, s);
   hipLaunchKernelGGL(k_tick, dim3(1), dim3(64), 0, s, h->dev_clock, 0);
 }
 
@@ -994,12 +1052,12 @@ bool cache_lookup(const std::string& key, Variant& v) {
   FILE* f = std::fopen(path, "r");
   if (!f) return false;
   char k[256];
-  int bx, by, ny, nt, xcd;
+  int bx, by, ny, nt, xcd, grid;
   double ms;
   bool found = false;
-  while (std::fscanf(f, "%255s %d %d %d %d %d %lf", k, &bx, &by, &ny, &nt, &xcd, &ms) == 7)
+  while (std::fscanf(f, "%255s %d %d %d %d %d %d %lf", k, &bx, &by, &ny, &nt, &xcd, &grid, &ms) == 8)
     if (key == k) {
-      v = Variant{bx, by, ny, nt != 0, xcd};
+      v = Variant{bx, by, ny, nt != 0, xcd, grid};
       found = true;  // the last entry wins
     }
   std::fclose(f);
@@ -1010,7 +1068,7 @@ void cache_store(const std::string& key, const Variant& v, double ms) {
   const char* path = std::getenv("LBM_CDE_TUNE_CACHE");
   if (!path) return;
   if (FILE* f = std::fopen(path, "a")) {
-    std::fprintf(f, "%s %d %d %d %d %d %.6f\n", key.c_str(), v.bx, v.by, v.ny, (int)v.nt, v.xcd, ms);
+    std::fprintf(f, "%s %d %d %d %d %d %d %.6f\n", key.c_str(), v.bx, v.by, v.ny, (int)v.nt, v.xcd, v.grid, ms);
     std::fclose(f);
   }
 }
@@ -1039,6 +1097,85 @@ int time_variant(lbm_cde* h, Run& r, const Variant& v, int trials, double* ms) {
   HIP_TRY(h, hipGetLastError());
   *ms = elapsed / trials;
   return LBM_CDE_OK;
+}
+
+// Time `trials` launches of the batched step kernel without advancing the
+// clock: each reads the current buffers and writes the other ones, so the
+// state of every run is unchanged.
+int time_batch(lbm_cde* h, int trials, double* ms) {
+  const BatchFn fn = find_batch(h->batch_var)->fn[h->runs[0].dbl ? 1 : 0];
+  hipEvent_t e0, e1;
+  HIP_TRY(h, hipEventCreate(&e0));
+  HIP_TRY(h, hipEventCreate(&e1));
+  fn(h, h->stream);  // warm-up
+  HIP_TRY(h, hipEventRecord(e0, h->stream));
+  for (int t = 0; t < trials; ++t) fn(h, h->stream);
+  HIP_TRY(h, hipEventRecord(e1, h->stream));
+  HIP_TRY(h, hipEventSynchronize(e1));
+  float elapsed = 0.f;
+  HIP_TRY(h, hipEventElapsedTime(&elapsed, e0, e1));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  HIP_TRY(h, hipGetLastError());
+  *ms = elapsed / trials;
+  return LBM_CDE_OK;
+}
+
+// Launch variants of a run stepped alone: every compiled tile shape and store
+// kind in every block order (the row-interleaved one only with a multiple of
+// 8 tile rows).
+std::vector<Variant> run_candidates(const Run& r) {
+  std::vector<Variant> out;
+  auto add = [&](const Variant& c) {
+    if (c.xcd == 2 && tile_rows(r, c) % 8 != 0) return;
+    out.push_back(c);
+  };
+  for (int xcd = 0; xcd < 3; ++xcd) {
+    if (r.split) {
+      for (const auto& e : kSplit)
+        for (int nt = 0; nt < (r.walls ? 1 : 2); ++nt) add(Variant{e.bx, e.by, 1, nt != 0, xcd});
+    } else if (r.half) {
+      add(Variant{256, 1, 1, false, xcd});
+    } else if (r.d.lattice == LBM_CDE_D3Q15) {
+      for (const auto& e : kSteps3) add(Variant{e.bx, e.by, e.ny, e.nt, xcd});
+    } else {
+      for (const auto& e : kSteps) add(Variant{e.bx, e.by, e.ny, e.nt, xcd});
+    }
+  }
+  return out;
+}
+
+// Tuning-cache key of a batch: architecture, precision and every run's grid,
+// boundaries and step budget (FNV-1a).
+std::string batch_tune_key(const lbm_cde* h) {
+  uint64_t fnv = 1469598103934665603ull;
+  auto mix = [&](int64_t v) {
+    for (int b = 0; b < 8; ++b) {
+      fnv ^= (uint64_t)((v >> (8 * b)) & 0xff);
+      fnv *= 1099511628211ull;
+    }
+  };
+  for (const auto& r : h->runs) {
+    mix(r.d.nx);
+    mix(r.d.ny);
+    mix(r.d.bc[0] * 16 + r.d.bc[1]);
+    mix(r.d.max_steps);
+  }
+  const std::string first = tune_key(h->runs[0]);
+  char buf[256];
+  std::snprintf(buf, sizeof buf, "%s:batch%zu:%016llx", first.substr(0, first.find(':')).c_str(), h->runs.size(),
+                (unsigned long long)fnv);
+  return std::string(buf) + (h->runs[0].dbl ? ":fp64" : ":fp32");
+}
+
+// Variant as the six integers of the C ABI.
+void variant_out(const Variant& v, int grid, int32_t* out) {
+  out[0] = v.bx;
+  out[1] = v.by;
+  out[2] = v.ny;
+  out[3] = v.nt ? 1 : 0;
+  out[4] = v.xcd;
+  out[5] = grid;
 }
 
 }  // namespace
@@ -1311,6 +1448,25 @@ int lbm_cde_destroy(lbm_cde_handle h) {
 int lbm_cde_tune(lbm_cde_handle h, int32_t trials) {
   if (!h) return fail_init(LBM_CDE_EINVAL, "tune: null handle");
   if (trials < 1) return fail(h, LBM_CDE_EINVAL, "tune: trials must be >= 1");
+  if (h->batched) {
+    const std::string key = batch_tune_key(h);
+    Variant v;
+    if (cache_lookup(key, v) && find_batch(v)) return apply_batch_variant(h, v, nullptr);
+    double best = 1e300;
+    Variant best_v = h->batch_var;
+    for (const Variant& c : batch_candidates()) {
+      double ms = 0.0;
+      int rc = apply_batch_variant(h, c, nullptr);
+      if (!rc) rc = time_batch(h, trials, &ms);
+      if (rc) return rc;
+      if (ms < best) {
+        best = ms;
+        best_v = c;
+      }
+    }
+    cache_store(key, best_v, best);
+    return apply_batch_variant(h, best_v, nullptr);
+  }
   for (auto& r : h->runs) {
     const std::string key = tune_key(r);
     Variant v;
@@ -1320,41 +1476,15 @@ int lbm_cde_tune(lbm_cde_handle h, int32_t trials) {
     }
     double best = 1e300;
     Variant best_v = r.var;
-    if (r.half) {
-      if (r.split)
-        for (const auto& e : kSplit)
-          for (int nt = 0; nt < (r.walls ? 1 : 2); ++nt)
-          for (int xcd = 0; xcd < 3; ++xcd) {
-            const Variant c{e.bx, e.by, 1, nt != 0, xcd};
-            if (xcd == 2 && tile_rows(r, c) % 8 != 0) continue;
-            double ms = 0.0;
-            const int rc = time_variant(h, r, c, trials, &ms);
-            if (rc) return rc;
-            if (ms < best) {
-              best = ms;
-              best_v = c;
-            }
-          }
-      r.var = best_v;
-      if (r.split) cache_store(key, best_v, best);
-      continue;
-    }
-    const int n = r.d.lattice == LBM_CDE_D3Q15 ? (int)(sizeof kSteps3 / sizeof kSteps3[0])
-                                               : (int)(sizeof kSteps / sizeof kSteps[0]);
-    for (int i = 0; i < n; ++i)
-      for (int xcd = 0; xcd < 3; ++xcd) {
-        Variant c;
-        if (r.d.lattice == LBM_CDE_D3Q15) c = Variant{kSteps3[i].bx, kSteps3[i].by, kSteps3[i].ny, kSteps3[i].nt, xcd};
-        else c = Variant{kSteps[i].bx, kSteps[i].by, kSteps[i].ny, kSteps[i].nt, xcd};
-        if (xcd == 2 && tile_rows(r, c) % 8 != 0) continue;
-        double ms = 0.0;
-        const int rc = time_variant(h, r, c, trials, &ms);
-        if (rc) return rc;
-        if (ms < best) {
-          best = ms;
-          best_v = c;
-        }
+    for (const Variant& c : run_candidates(r)) {
+      double ms = 0.0;
+      const int rc = time_variant(h, r, c, trials, &ms);
+      if (rc) return rc;
+      if (ms < best) {
+        best = ms;
+        best_v = c;
       }
+    }
     r.var = best_v;
     cache_store(key, best_v, best);
   }
@@ -1365,11 +1495,45 @@ int lbm_cde_tune(lbm_cde_handle h, int32_t trials) {
 int lbm_cde_get_variant(lbm_cde_handle h, int32_t run, int32_t* out) {
   Run* r = get_run(h, run);
   if (!r || !out) return fail(h, LBM_CDE_EINVAL, "get_variant: bad handle, run or pointer");
-  out[0] = r->var.bx;
-  out[1] = r->var.by;
-  out[2] = r->var.ny;
-  out[3] = r->var.nt ? 1 : 0;
-  out[4] = r->var.xcd == 2 && tile_rows(*r, r->var) % 8 != 0 ? 0 : r->var.xcd;
+  if (h->batched) {
+    variant_out(h->batch_var, h->batch_grid, out);
+    return LBM_CDE_OK;
+  }
+  Variant v = r->var;
+  if (v.xcd == 2 && tile_rows(*r, v) % 8 != 0) v.xcd = 0;  // the launch falls back to the hardware order
+  variant_out(v, 0, out);
+  return LBM_CDE_OK;
+}
+
+int lbm_cde_variant_count(lbm_cde_handle h, int32_t run, int32_t* count) {
+  Run* r = get_run(h, run);
+  if (!r || !count) return fail(h, LBM_CDE_EINVAL, "variant_count: bad handle, run or pointer");
+  *count = (int32_t)(h->batched ? batch_candidates().size() : run_candidates(*r).size());
+  return LBM_CDE_OK;
+}
+
+int lbm_cde_variant_at(lbm_cde_handle h, int32_t run, int32_t index, int32_t* out) {
+  Run* r = get_run(h, run);
+  if (!r || !out) return fail(h, LBM_CDE_EINVAL, "variant_at: bad handle, run or pointer");
+  const std::vector<Variant> c = h->batched ? batch_candidates() : run_candidates(*r);
+  if (index < 0 || index >= (int32_t)c.size())
+    return fail(h, LBM_CDE_EINVAL, "variant_at: index %d outside [0, %zu)", index, c.size());
+  variant_out(c[index], c[index].grid, out);
+  return LBM_CDE_OK;
+}
+
+int lbm_cde_set_variant(lbm_cde_handle h, int32_t run, const int32_t* v) {
+  Run* r = get_run(h, run);
+  if (!r || !v) return fail(h, LBM_CDE_EINVAL, "set_variant: bad handle, run or pointer");
+  const Variant c{v[0], v[1], v[2], v[3] != 0, v[4], v[5]};
+  if (h->batched) return apply_batch_variant(h, c, nullptr);
+  if (c.grid != 0 || c.xcd < 0 || c.xcd > 2 || !find_step(*r, c))
+    return fail(h, LBM_CDE_EINVAL, "set_variant: variant %dx%dx%d nt=%d order=%d grid=%d is not built for run %d",
+                c.bx, c.by, c.ny, (int)c.nt, c.xcd, c.grid, run);
+  if (c.xcd == 2 && tile_rows(*r, c) % 8 != 0)
+    return fail(h, LBM_CDE_EINVAL, "set_variant: the row-interleaved order needs a multiple of 8 tile rows");
+  r->var = c;
+  drop_graphs(h);
   return LBM_CDE_OK;
 }
 

@@ -181,6 +181,13 @@ class Solver:
     def variant(self, run: int = 0) -> dict:
         return L.lbm_cde_get_variant(self.h, run)
 
+    def variants(self, run: int = 0) -> list:
+        """Every compiled launch variant of a run (the tuner's candidates)."""
+        return [L.lbm_cde_variant_at(self.h, run, i) for i in range(L.lbm_cde_variant_count(self.h, run))]
+
+    def set_variant(self, v: dict, run: int = 0) -> None:
+        L.lbm_cde_set_variant(self.h, run, v)
+
     def close(self) -> None:
         if getattr(self, "h", None):
             L.lbm_cde_destroy(self.h)

@@ -16,8 +16,8 @@ pytestmark = pytest.mark.gpu
 
 TOL = {"fp64": 1e-12, "fp32": 1e-5}
 
-CHANNELS = [  # (h, Pe, tau, nx, max_steps)
-    (12, 20.0, 0.8, 100, -1),
+CHANNELS = [  # (h, Pe, tau, nx, max_steps); the first has more nodes than one pass of the x-moment blocks
+    (12, 20.0, 0.8, 1400, -1),
     (20, 8.0, 1.4, 64, 47),
     (7, 40.0, 0.6, 130, -1),
     (16, 12.0, 1.1, 90, 70),
@@ -144,3 +144,36 @@ def test_batched_row_tiles_equal_single_runs(precision):
         one.step(50)
         np.testing.assert_array_equal(batched[i], one.phi().cpu().numpy(), err_msg=wl.name)
         one.close()
+
+
+def test_full_size_ensemble_sampled_nodes():
+    """The 64-channel Taylor-Aris ensemble (Nx = 4096, 17.9 M nodes) in the
+    launch variant the tuner picks for it, stepped 40 times by the batched
+    persistent kernel; sampled nodes of eight channels are compared with the
+    oracle run on a window of the channel: every row of the gap and 2 x 41
+    columns around the node, which after 40 steps depend on nothing else."""
+    from paper_1404_2363_amd.solver import Solver
+    runs = W.taylor_aris_batch()
+    per_run = [{"heat": [1 / r.meta["tau"]] * 2, "xref0": r.meta["x0"], "xref_drift": r.meta["U_node_mean"]}
+               for r in runs]
+    s = Solver(runs, "fp32", per_run=per_run)
+    s.tune(3)
+    steps = 40
+    print(f"case taylor_aris_batch 64 channels x {steps} fp32, tuned variant {s.variant()}", flush=True)
+    s.step(steps)
+    rng = np.random.default_rng(5)
+    picks = sorted(set([0, 63] + list(rng.choice(64, 6, replace=False))))
+    for i in picks:
+        wl = runs[i]
+        phi = s.phi(i).cpu().numpy()
+        nx, h = wl.shape
+        mass0 = O.mass(wl.phi0())
+        assert abs(O.mass(phi) - mass0) <= 1e-5 * mass0
+        scale = np.abs(wl.phi0()).max()
+        for cx in (0, int(wl.meta["x0"]), int(rng.integers(0, nx))):
+            idx = [np.mod(np.arange(cx - steps - 1, cx + steps + 2), nx), np.arange(h)]
+            ref, _ = O.run_workload(wl, steps=steps, idx=idx, heat_rule=per_run[i]["heat"])
+            c = steps + 1
+            err = np.abs(phi[:, cx] - ref[:, c]).max()
+            assert err <= TOL["fp32"] * scale, (i, cx, err)
+    s.close()
