@@ -10,6 +10,11 @@ the 64-channel Taylor-Aris ensemble advanced by the batched persistent
 kernel, one adjoint gradient of the 512^2 inverse problem, the roofline of
 the dominant kernel and the FP64 CPU oracle timed on the host cores.
 
+Timing: after W warm-up steps each variant is timed in 5 blocks of at
+least K steps (a multiple of the library's 32-step captured graph, and at
+least 0.1 s), with HIP events on the stream the library launches on; the
+median per-step time is reported with the minimum and maximum.
+
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--only NAME]
                        [--quick] [--no-cpu] [--no-tune] [--copy-probe]
 NAME: d2q9_4096_fp32 | d2q9_4096_fp64 | d2q9_4096_fp16 | d3q15_256_fp32 |
@@ -68,85 +73,136 @@ def log(msg):
     print(f"bench: {msg}", file=sys.stderr, flush=True)
 
 
-def time_steps(solver, steps, warmup):
+GRAPH_STEPS = 32               # steps per captured graph in the library
+REPS = 5                       # timed blocks per variant (the median is reported)
+MIN_BLOCK_S = 0.1              # each timed block lasts at least this long
+
+
+def time_blocks(advance, steps, warmup):
+    """Seconds per step of ``advance(n)`` (enqueues n steps on torch's
+    current stream, the stream the library launches on): after ``warmup``
+    steps, REPS blocks are timed with HIP events, each a multiple of the
+    library's graph length (so long advances run as graph replays), at least
+    ``steps`` steps and at least MIN_BLOCK_S long.  Returns the median, the
+    minimum and maximum per-step time, the block length and the wall time."""
     import torch
-    solver.step(warmup)
+    advance(max(warmup, 1))
     torch.cuda.synchronize()
-    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ev[0].record()
+    advance(GRAPH_STEPS)           # a probe block sizes the timed ones
+    ev[1].record()
+    torch.cuda.synchronize()
+    per = max(ev[0].elapsed_time(ev[1]) / 1e3 / GRAPH_STEPS, 1e-7)
+    n = max(steps, int(MIN_BLOCK_S / per) + 1)
+    n = -(-n // GRAPH_STEPS) * GRAPH_STEPS
+    out = []
     t0 = time.perf_counter()
-    start.record()                 # the library launches on torch's current stream
-    solver.step(steps)
-    stop.record()
-    torch.cuda.synchronize()
-    return start.elapsed_time(stop) / 1e3, time.perf_counter() - t0
+    for _ in range(REPS):
+        start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        start.record()
+        advance(n)
+        stop.record()
+        torch.cuda.synchronize()
+        out.append(start.elapsed_time(stop) / 1e3 / n)
+    wall = time.perf_counter() - t0
+    out.sort()
+    return {"median": out[len(out) // 2], "min": out[0], "max": out[-1], "steps_per_block": n, "blocks": REPS,
+            "wall_s": wall}
+
+
+def check_against_default(s, default, steps=GRAPH_STEPS):
+    """The tuned variant of a run stepped alone against its default variant
+    (which the parity tests compare with the oracle at this grid size): from
+    the same state, ``steps`` steps in each must give bitwise the same phi."""
+    import torch
+    tuned = s.variant()
+    t0 = s.steps_done()
+    ck = s.get_state()
+    s.step(steps)
+    a = s.phi()
+    s.set_state(ck, t0)
+    s.set_variant(default)
+    s.step(steps)
+    b = s.phi()
+    same = bool(torch.equal(a, b))
+    s.set_state(ck, t0)
+    s.set_variant(tuned)
+    return same
 
 
 def gpu_variant(wl, precision, steps, warmup, tune=True):
     from paper_1404_2363_amd.solver import Solver
     s = Solver(wl, precision)
+    default = s.variant()
     if tune:
         s.tune(10)
-    ev, wall = time_steps(s, steps, warmup)
+    tm = time_blocks(s.step, steps, warmup)
     nonfinite = s.nonfinite()
     var = s.variant()
+    same = check_against_default(s, default) if var != default else True
     s.close()
-    t_step = ev / steps
+    t_step = tm["median"]
     bpl = BYTES_PER_LU[(wl.lattice, precision)]
     gbs = wl.nodes * bpl / t_step / 1e9
-    return {"precision": precision, "nodes": wl.nodes, "steps": steps, "ms_per_step": t_step * 1e3,
-            "mlups": wl.nodes / t_step / 1e6, "achieved_gbs": gbs, "bytes_per_lu": bpl,
-            "hbm_frac": gbs / HBM_PEAK_GBS, "wall_s": wall, "nonfinite": nonfinite, "launch": var}
+    return {"precision": precision, "nodes": wl.nodes, "ms_per_step": t_step * 1e3,
+            "ms_per_step_min_max": [tm["min"] * 1e3, tm["max"] * 1e3], "timed_blocks": tm["blocks"],
+            "steps_per_block": tm["steps_per_block"], "mlups": wl.nodes / t_step / 1e6, "achieved_gbs": gbs,
+            "bytes_per_lu": bpl, "hbm_frac": gbs / HBM_PEAK_GBS, "wall_s": tm["wall_s"], "nonfinite": nonfinite,
+            "launch": var, "bitwise_equal_to_default_variant": same}
 
 
-def batch_variant(runs, precision, steps, warmup):
+def batch_variant(runs, precision, steps, warmup, tune=True):
     """The Taylor-Aris ensemble: all channels in one persistent launch per step."""
     from paper_1404_2363_amd.solver import Solver
     per_run = [{"heat": [1 / r.meta["tau"]] * 2, "xref0": r.meta["x0"], "xref_drift": r.meta["U_node_mean"]}
                for r in runs]
     s = Solver(runs, precision, per_run=per_run)
-    ev, wall = time_steps(s, steps, warmup)
+    if tune:
+        s.tune(10)
+    tm = time_blocks(s.step, steps, warmup)
     nonfinite = sum(s.nonfinite(i) for i in range(len(runs)))
+    var = s.variant()
     s.close()
     nodes = sum(r.nodes for r in runs)
-    t_step = ev / steps
+    t_step = tm["median"]
     bpl = BYTES_PER_LU[("d2q9", precision)]
     gbs = nodes * bpl / t_step / 1e9
-    return {"precision": precision, "runs": len(runs), "nodes": nodes, "steps": steps,
-            "ms_per_step": t_step * 1e3, "mlups": nodes / t_step / 1e6, "achieved_gbs": gbs,
-            "bytes_per_lu": bpl, "hbm_frac": gbs / HBM_PEAK_GBS, "wall_s": wall, "nonfinite": nonfinite}
+    return {"precision": precision, "runs": len(runs), "nodes": nodes, "ms_per_step": t_step * 1e3,
+            "ms_per_step_min_max": [tm["min"] * 1e3, tm["max"] * 1e3], "timed_blocks": tm["blocks"],
+            "steps_per_block": tm["steps_per_block"], "mlups": nodes / t_step / 1e6, "achieved_gbs": gbs,
+            "bytes_per_lu": bpl, "hbm_frac": gbs / HBM_PEAK_GBS, "wall_s": tm["wall_s"], "nonfinite": nonfinite,
+            "launch": var}
 
 
 def unsteady_variant(precision, steps, warmup):
     """Time-dependent u on the 4096^2 grid: before every step a new velocity
-    field (device FP64, already resident) replaces the run's field; the step
-    then reads it (+8 B per lattice update in FP32) and the replacement
-    converts it (16 B read + 8 B written per node)."""
+    field (device FP64, already resident) replaces the run's field and the
+    step reads it."""
     import torch
     from paper_1404_2363_amd import workloads as W
     from paper_1404_2363_amd.solver import Solver
     wl = W.drifting_cellular(nx=4096, ny=4096, steps=steps, n_hills=64, sigma=32.0, drift=0.5)
     fields = [torch.as_tensor(wl.u_schedule(n), dtype=torch.float64, device="cuda") for n in range(4)]
     s = Solver(wl, precision)
-    for n in range(warmup):
-        s.set_velocity(fields[n % 4])
-        s.step(1)
-    torch.cuda.synchronize()
-    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    start.record()
-    for n in range(steps):
-        s.set_velocity(fields[n % 4])
-        s.step(1)
-    stop.record()
-    torch.cuda.synchronize()
-    t_step = start.elapsed_time(stop) / 1e3 / steps
+    count = [0]
+
+    def advance(n):
+        for _ in range(n):
+            s.set_velocity(fields[count[0] % 4])
+            s.step(1)
+            count[0] += 1
+
+    tm = time_blocks(advance, steps, warmup)
     nonfinite = s.nonfinite()
     s.close()
-    elem = 4 if precision == "fp32" else 8
-    bpl = BYTES_PER_LU[("d2q9", precision)] + 2 * elem      # populations + the field read by the step
-    upd = 16 + 2 * elem                                      # FP64 field read + stored copy written
-    return {"precision": precision, "nodes": wl.nodes, "steps": steps, "ms_per_step": t_step * 1e3,
-            "mlups": wl.nodes / t_step / 1e6, "step_bytes_per_lu": bpl, "update_bytes_per_node": upd,
-            "achieved_gbs_incl_update": wl.nodes * (bpl + upd) / t_step / 1e9, "nonfinite": nonfinite}
+    t_step = tm["median"]
+    bpl = BYTES_PER_LU[("d2q9", precision)] + 16               # populations + the FP64 field read by the step
+    return {"precision": precision, "nodes": wl.nodes, "ms_per_step": t_step * 1e3,
+            "ms_per_step_min_max": [tm["min"] * 1e3, tm["max"] * 1e3], "steps_per_block": tm["steps_per_block"],
+            "mlups": wl.nodes / t_step / 1e6, "bytes_per_lu": bpl,
+            "achieved_gbs": wl.nodes * bpl / t_step / 1e9, "hbm_frac": wl.nodes * bpl / t_step / 1e9 / HBM_PEAK_GBS,
+            "nonfinite": nonfinite}
 
 
 def adjoint_variant(precision="fp32"):
@@ -204,15 +260,17 @@ def adjoint_segment_variant(n=2048, K=16, precision="fp32"):
     L.lbm_cde_adjoint_segment(s.h, 0, ck.data_ptr(), K, seg.data_ptr(), inj, mu.data_ptr(), mu_tmp.data_ptr(),
                               grad.data_ptr())                      # warm-up
     torch.cuda.synchronize()
-    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    reps = 3
-    start.record()
-    for _ in range(reps):
-        L.lbm_cde_adjoint_segment(s.h, 0, ck.data_ptr(), K, seg.data_ptr(), inj, mu.data_ptr(),
-                                  mu_tmp.data_ptr(), grad.data_ptr())
-    stop.record()
-    torch.cuda.synchronize()
-    t = start.elapsed_time(stop) / 1e3 / reps
+    per_block, times = 10, []
+    for _ in range(REPS):
+        start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        start.record()
+        for _ in range(per_block):
+            L.lbm_cde_adjoint_segment(s.h, 0, ck.data_ptr(), K, seg.data_ptr(), inj, mu.data_ptr(),
+                                      mu_tmp.data_ptr(), grad.data_ptr())
+        stop.record()
+        torch.cuda.synchronize()
+        times.append(start.elapsed_time(stop) / 1e3 / per_block)
+    t = sorted(times)[REPS // 2]
     finite = bool(torch.isfinite(grad).all())
     s.close()
     nodes = n * n
@@ -235,31 +293,54 @@ def copy_probe():
     torch.cuda.empty_cache()
 
 
-def cpu_baseline(wl, steps=6):
-    """The FP64 oracle as it stands, with one BLAS thread, on the same grid."""
-    from oracle import lbm as O
+def host_description():
+    """Logical CPUs this process may use and the CPU model."""
     try:
-        from threadpoolctl import threadpool_limits
-        ctx = threadpool_limits(1)
-    except Exception:
-        ctx = None
+        ncpu = len(os.sched_getaffinity(0))
+    except AttributeError:
+        ncpu = os.cpu_count() or 1
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return ncpu, model
+
+
+def cpu_baseline(wl, steps=4):
+    """The FP64 oracle as it stands on the same grid, timed twice: with one
+    BLAS thread and with one BLAS thread per available CPU (the oracle's
+    dense 9 x 9 transforms run in BLAS; its streaming is single-threaded
+    numpy, so extra threads help only the transforms)."""
+    from oracle import lbm as O
+    from threadpoolctl import threadpool_limits
+    ncpu, model = host_description()
     prob = O.problem_for(wl)
-    f = prob.equilibrium(wl.phi0())
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        f = prob.step(f)
-    dt = time.perf_counter() - t0
-    if ctx is not None:
-        ctx.restore_original_limits()
-    return {"value": wl.nodes * steps / dt / 1e6, "unit": "MLUPS", "cores": 1, "kind": "oracle",
-            "sample": f"{steps} FP64 oracle steps (numpy, one BLAS thread) of the full "
-                      f"{wl.shape[0]}x{wl.shape[1]} D2Q9 grid, {dt:.1f} s"}
+    f0 = prob.equilibrium(wl.phi0())
+    res = {}
+    for threads in (1, ncpu):
+        with threadpool_limits(threads):
+            f = f0
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                f = prob.step(f)
+            res[threads] = time.perf_counter() - t0
+        log(f"cpu baseline: {steps} oracle steps with {threads} BLAS thread(s): {res[threads]:.1f} s")
+    best = min(res, key=lambda k: res[k])
+    return {"value": wl.nodes * steps / res[best] / 1e6, "unit": "MLUPS", "cores": best, "kind": "oracle",
+            "sample": f"{steps} FP64 oracle steps (numpy) of the full {wl.shape[0]}x{wl.shape[1]} D2Q9 grid, "
+                      f"{res[best]:.1f} s with {best} BLAS thread(s)",
+            "host": {"cpus_available": ncpu, "cpu_model": model},
+            "by_threads": {str(k): {"mlups": wl.nodes * steps / v / 1e6, "seconds": v} for k, v in res.items()}}
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=400)
+    ap.add_argument("--steps", type=int, default=64)
     ap.add_argument("--warmup", type=int, default=40)
     ap.add_argument("--only", default="")
     ap.add_argument("--no-cpu", action="store_true")
@@ -284,10 +365,10 @@ def main():
     wl3 = None
     if (not args.only and not args.quick) or args.only.startswith("d3q15"):
         wl3 = W.sine3d()
-    plan += [("d2q9_4096_fp64", wl2, "fp64", max(args.steps // 2, 1), max(args.warmup // 2, 1)),
+    plan += [("d2q9_4096_fp64", wl2, "fp64", args.steps, args.warmup),
              ("d2q9_4096_fp16", wl2, "fp16", args.steps, args.warmup),
-             ("d3q15_256_fp32", wl3, "fp32", max(args.steps // 4, 1), max(args.warmup // 4, 1)),
-             ("d3q15_256_fp64", wl3, "fp64", max(args.steps // 8, 1), max(args.warmup // 8, 1))]
+             ("d3q15_256_fp32", wl3, "fp32", args.steps, args.warmup),
+             ("d3q15_256_fp64", wl3, "fp64", args.steps, args.warmup)]
     for name, wl, prec, k, w in plan:
         if args.only and name != args.only:
             continue
@@ -299,14 +380,14 @@ def main():
         log(f"{name}: {out[name]['mlups']:.0f} MLUPS, {out[name]['achieved_gbs']:.0f} GB/s")
     if (not args.only and not args.quick) or args.only == "taylor_aris_batch":
         runs = W.taylor_aris_batch()
-        k = max(args.steps // 4, 1)
+        k = args.steps
         log(f"taylor_aris_batch: {len(runs)} channels, {k} steps")
-        out["taylor_aris_batch_fp32"] = batch_variant(runs, "fp32", k, max(args.warmup // 4, 1))
+        out["taylor_aris_batch_fp32"] = batch_variant(runs, "fp32", k, args.warmup, tune)
         log(f"taylor_aris_batch: {out['taylor_aris_batch_fp32']['mlups']:.0f} MLUPS")
     if (not args.only and not args.quick) or args.only == "unsteady":
-        k = max(args.steps // 4, 1)
+        k = args.steps
         log(f"unsteady: 4096^2 FP32 with a new velocity field every step, {k} steps")
-        out["d2q9_4096_fp32_unsteady_u"] = unsteady_variant("fp32", k, max(args.warmup // 4, 1))
+        out["d2q9_4096_fp32_unsteady_u"] = unsteady_variant("fp32", k, args.warmup)
         log(f"unsteady: {out['d2q9_4096_fp32_unsteady_u']['mlups']:.0f} MLUPS")
     if (not args.only and not args.quick) or args.only == "adjoint":
         log("adjoint: one 2048^2 checkpoint segment of 16 steps (forward recompute + reverse)")
@@ -333,6 +414,11 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": main_v["ms_per_step"],
+        "timing": {"statistic": "median", "blocks": main_v["timed_blocks"],
+                   "steps_per_block": main_v["steps_per_block"],
+                   "ms_per_step_min_max": main_v["ms_per_step_min_max"],
+                   "note": "blocks are multiples of the 32-step captured graph, at least --steps steps and "
+                           "at least 0.1 s long, timed with HIP events on the library's stream"},
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -344,7 +430,8 @@ def main():
         "roofline": {"bound": "hbm", "achieved": main_v["achieved_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": main_v["hbm_frac"],
                      "traffic": main_v.get("traffic", profiled_traffic("d2q9_4096_fp32", main_v["launch"])),
-                     "kernel": "k_step_d2q9<float>", "bytes_per_launch": 72 * wl2.nodes},
+                     "kernel": "k_step_d2q9<float>", "launch": main_v["launch"],
+                     "bytes_per_launch": 72 * wl2.nodes},
         "variants": out,
         "cpu_baseline": cpu,
     }

@@ -54,7 +54,8 @@ enum {
   LBM_CDE_OK = 0,
   LBM_CDE_EINVAL = -1,      /* bad argument: null pointer, size, enum, step count   */
   LBM_CDE_ENOTSPD = -2,     /* D (or a node of D_field) is not symmetric positive definite */
-  LBM_CDE_EUNSTABLE = -3,   /* a rate outside (0, 2) or |u| >= c_s = 1/sqrt(3)        */
+  LBM_CDE_EUNSTABLE = -3,   /* a rate outside (0, 2), |u| >= c_s = 1/sqrt(3), or a
+                               linearised step that amplifies a Fourier mode           */
   LBM_CDE_EHIP = -4,        /* HIP runtime error; the runtime's message is kept      */
   LBM_CDE_ENONFINITE = -5,  /* a reduction met NaN or Inf in the state               */
   LBM_CDE_ENOSPC = -6,      /* workspace smaller than lbm_cde_workspace_bytes()       */
@@ -115,9 +116,11 @@ enum { LBM_CDE_MRT_A = 0, LBM_CDE_MRT_B1 = 1, LBM_CDE_MRT_B2 = 2, LBM_CDE_MRT_B3
  *   CONST      u_const[0..dim-1].
  *   SEPARABLE  u_c(x,y,z) = amp_c * X_c[x] * Y_c[y] * Z_c[z] per component c,
  *              from host tables (see u_tables).
- *   FIELD      per node, device FP64 array [dim][nz][ny][nx], copied (in the
- *              storage precision) at init and replaced by
- *              lbm_cde_set_velocity() whenever the flow changes in time. */
+ *   FIELD      per node, device FP64 array [dim][nz][ny][nx], copied (FP64)
+ *              into the workspace at init (EUNSTABLE if |u| >= 1/sqrt(3)
+ *              anywhere); lbm_cde_set_velocity() points the steps at a
+ *              caller array whenever the flow changes in time.  The steps
+ *              read the FP64 field (16 B per node in 2D, 24 B in 3D). */
 enum { LBM_CDE_U_CONST = 0, LBM_CDE_U_SEPARABLE = 1, LBM_CDE_U_FIELD = 2 };
 
 /* Rates s4, s6 (, s8) of the heat-flux moments, which the modified S
@@ -164,13 +167,29 @@ typedef struct lbm_cde_run_desc {
   int64_t max_steps;        /* per-run step budget (< 0: unlimited); a run that has
                                used it is left unchanged by further steps               */
   int32_t model;            /* LBM_CDE_MRT_A (0, default) | _MRT_B1 | _MRT_B2 | _MRT_B3    */
+  int32_t skip_stability_check; /* 0 (default): a run with constant D and constant u whose
+                               linearised step has a spectral radius above 1 is rejected
+                               with EUNSTABLE (see lbm_cde_spectral_radius); 1: accept it
+                               (e.g. to repeat a published set-up whose slow growth of
+                               short waves stays below round-off over the run)          */
 } lbm_cde_run_desc;
 
 typedef struct lbm_cde* lbm_cde_handle;
 
-/* Bytes of device workspace needed for nruns runs.  Returns EINVAL for an
- * invalid description (same checks as lbm_cde_init without the GPU). */
+/* Bytes of device workspace needed for nruns runs.  Returns the errors of
+ * lbm_cde_init's checks of the descriptions that need no GPU (EINVAL,
+ * ENOTSPD, EUNSTABLE, EUNSUPPORTED). */
 int lbm_cde_workspace_bytes(const lbm_cde_run_desc* runs, int32_t nruns, size_t* bytes);
+
+/* Von Neumann stability of the run described by d, which must have a
+ * constant D and a constant u (EUNSUPPORTED otherwise): *rho receives an
+ * upper bound (tight to about 1e-6) of the spectral radius of the linearised
+ * step G(k) = diag(exp(-i k.e_j)) C over a 48^2 (D2Q9) or 10^3 (D3Q15) grid
+ * of wave vectors k, C = I - M^-1 S (M - m_eq 1^T) the collision of
+ * Eq. (10)-(14) with the run's S and equilibrium.  Fourier modes grow where
+ * rho > 1; lbm_cde_init rejects runs with rho > 1 + 1e-5 unless
+ * skip_stability_check is set.  Host only; no GPU is used. */
+int lbm_cde_spectral_radius(const lbm_cde_run_desc* d, double* rho);
 
 /* Set up nruns independent runs in the caller's workspace (device memory of
  * ws_bytes bytes, 256-byte aligned) and initialise every population to the
@@ -229,13 +248,17 @@ int lbm_cde_samples_written(lbm_cde_handle h, int64_t* rows);
  * MRT_A, Eq. (24) for the MRT_B models. */
 int lbm_cde_relaxation_matrix(lbm_cde_handle h, int32_t run, double* S_out);
 
-/* Replace the velocity field of run `run` (initialised with u_kind FIELD) by
- * the device FP64 array u [dim][nz][ny][nx] (Eq. 1 with u = u(x, t)).  Each
- * step relaxes the populations it arrives at with the field current when the
- * step is enqueued: the field set before the call that takes a run from step
- * n-1 to step n is u(x, t_n).  Enqueued on the handle's stream (the caller
- * keeps u valid until that work has run); captured graphs need no rebuild.
- * EINVAL if the run has no velocity field or an argument is NULL. */
+/* Make the device FP64 array u [dim][nz][ny][nx] the velocity field of run
+ * `run` (initialised with u_kind FIELD; Eq. 1 with u = u(x, t)).  The steps
+ * read u itself, no copy is made: the caller keeps u valid and unchanged
+ * until every step enqueued before the next lbm_cde_set_velocity of this run
+ * (or lbm_cde_destroy) has run.  Each step relaxes the populations it
+ * arrives at with the field current when the step is enqueued: the field set
+ * before the call that takes a run from step n-1 to step n is u(x, t_n).
+ * Enqueued on the handle's stream (no wait); captured graphs need no
+ * rebuild.  A step that meets |u| >= 1/sqrt(3) at a node marks the run, and
+ * the next lbm_cde_reduce of the run returns EUNSTABLE.  EINVAL if the run
+ * has no velocity field or an argument is NULL. */
 int lbm_cde_set_velocity(lbm_cde_handle h, int32_t run, const double* u);
 
 /* Launch variants.  A variant is six integers: block x, block y, rows per

@@ -57,6 +57,7 @@ class lbm_cde_run_desc(ctypes.Structure):
         ("xref_drift", ctypes.c_double),
         ("max_steps", ctypes.c_int64),
         ("model", ctypes.c_int32),
+        ("skip_stability_check", ctypes.c_int32),
     ]
 
 
@@ -81,6 +82,7 @@ def load() -> ctypes.CDLL:
     P, I32, I64, D = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
     sig = {
         "lbm_cde_workspace_bytes": [ctypes.POINTER(lbm_cde_run_desc), I32, ctypes.POINTER(ctypes.c_size_t)],
+        "lbm_cde_spectral_radius": [ctypes.POINTER(lbm_cde_run_desc), ctypes.POINTER(D)],
         "lbm_cde_init": [ctypes.POINTER(lbm_cde_run_desc), I32, ctypes.POINTER(ctypes.c_void_p), P,
                          ctypes.c_size_t, P, ctypes.POINTER(ctypes.c_void_p)],
         "lbm_cde_step": [P, I64],
@@ -127,6 +129,12 @@ def lbm_cde_workspace_bytes(descs) -> int:
     out = ctypes.c_size_t(0)
     _check(load().lbm_cde_workspace_bytes(arr, len(descs), ctypes.byref(out)), "lbm_cde_workspace_bytes")
     return int(out.value)
+
+
+def lbm_cde_spectral_radius(desc) -> float:
+    out = ctypes.c_double(0.0)
+    _check(load().lbm_cde_spectral_radius(ctypes.byref(desc), ctypes.byref(out)), "lbm_cde_spectral_radius")
+    return float(out.value)
 
 
 def lbm_cde_init(descs, phi0_ptrs, workspace_ptr: int, ws_bytes: int, stream: int) -> int:

@@ -24,7 +24,7 @@ LBM_FORCEINLINE void velocity_at(const RunArgs& a, int dim, int64_t x, int64_t y
       const R* t = (const R*)a.u_tab + c * (1 + a.nx + a.ny + a.nz);
       u[c] = (double)(((t[0] * t[1 + x]) * t[1 + a.nx + y]) * t[1 + a.nx + a.ny + z]);
     } else {
-      u[c] = (double)((const R*)a.u_field)[c * N + node];
+      u[c] = (double)(R)(*a.u_slot)[c * N + node];  // rounded as the step rounds it
     }
   }
 }
@@ -232,6 +232,22 @@ __global__ __launch_bounds__(RED_THREADS) void k_batch_xmom_final(const double* 
 // Advance the device step clock (clock[0]: steps, clock[1]: history rows).
 __global__ void k_tick(int64_t* __restrict__ clock, int which) {
   if (threadIdx.x == 0) clock[which] += 1;
+}
+
+// Point a velocity slot at a field (a kernel, so that it is ordered on the
+// stream and may be captured).
+__global__ void k_store_ptr(const double** slot, const double* p) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *slot = p;
+}
+
+// Flag nodes of a velocity field [dim][N] with |u| >= c_s.
+__global__ __launch_bounds__(256) void k_check_speed(const double* __restrict__ u, int dim, int64_t N,
+                                                     unsigned* __restrict__ flag) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  double u2 = 0.0;
+  for (int c = 0; c < dim; ++c) u2 += u[c * N + i] * u[c * N + i];
+  if (!(u2 < 1.0 / 3.0)) *flag = 1u;
 }
 
 // Copy of a device FP64 array into storage precision R.

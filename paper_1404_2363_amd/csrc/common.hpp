@@ -29,7 +29,8 @@ struct RunArgs {
   int32_t u_kind;
   double u_const[3];
   const void* u_tab;        // SEPARABLE: per component: amp, X[nx], Y[ny], Z[nz] (type R)
-  const void* u_field;      // FIELD: [dim][nodes] (type R)
+  const double* const* u_slot;  // FIELD: device slot holding the current FP64 field [dim][nodes]
+  unsigned* u_flag;         // FIELD: set to 1 where |u| >= c_s = 1/sqrt(3) (sticky)
   const void* node_par;     // per-node relaxation parameters (type R) or null
   double phi_ref;
   double fp16_scale, fp16_inv_scale;
@@ -79,6 +80,12 @@ LBM_FORCEINLINE int64_t tile_of_block(int64_t b, int64_t nb, int64_t ntx, int mo
 
 template <typename R>
 LBM_FORCEINLINE R load_ro(const R* p) { return __builtin_nontemporal_load(p); }
+
+// A per-node velocity read from a FIELD run: flag speeds at or above the
+// lattice sound speed (the step is unstable there).
+LBM_FORCEINLINE void check_speed(const RunArgs& a, double u2) {
+  if (u2 >= 1.0 / 3.0) *a.u_flag = 1u;
+}
 
 template <typename R, bool NT>
 LBM_FORCEINLINE void store_pop(R* p, R v) {

@@ -182,10 +182,12 @@ LBM_FORCEINLINE void velocity2(const RunArgs& a, int64_t x, int64_t y, R& ux, R&
     ux = ((t[0] * t[1 + x]) * t[1 + a.nx + y]) * t[1 + a.nx + a.ny];
     uy = ((t1[0] * t1[1 + x]) * t1[1 + a.nx + y]) * t1[1 + a.nx + a.ny];
   } else {
-    const R* u = (const R*)a.u_field;
+    const double* u = *a.u_slot;
     const int64_t N = a.nx * a.ny;
-    ux = u[y * a.nx + x];
-    uy = u[N + y * a.nx + x];
+    const double vx = u[y * a.nx + x], vy = u[N + y * a.nx + x];
+    check_speed(a, vx * vx + vy * vy);
+    ux = (R)vx;
+    uy = (R)vy;
   }
 }
 
@@ -369,10 +371,12 @@ LBM_FORCEINLINE void tile_rows_d2q9(const RunArgs& a, int64_t tile_x, int64_t ti
     uy = ((*(const R*)(t + stride) * *(const R*)(t + stride + ox)) * *(const R*)(t + stride + oy)) *
          *(const R*)(t + stride + oz);
   } else {
-    const char* u = (const char*)a.u_field;
-    const uint32_t o = ((uint32_t)y * nx + x) * (uint32_t)sizeof(R);
-    ux = *(const R*)(u + o);
-    uy = *(const R*)(u + nx * (uint32_t)ny * (uint32_t)sizeof(R) + o);
+    const char* u = (const char*)*a.u_slot;
+    const uint32_t o = ((uint32_t)y * nx + x) * 8u;
+    const double vx = *(const double*)(u + o), vy = *(const double*)(u + nx * (uint32_t)ny * 8u + o);
+    check_speed(a, vx * vx + vy * vy);
+    ux = (R)vx;
+    uy = (R)vy;
   }
   collide_d2q9<R>(f, ux, uy, (R)a.phi_ref, const_rel2<R>(a));
   const uint32_t nb = ((uint32_t)y * nx + x) * (uint32_t)sizeof(R);

@@ -171,12 +171,14 @@ LBM_FORCEINLINE void velocity3(const RunArgs& a, int64_t x, int64_t y, int64_t z
     uy = u[1];
     uz = u[2];
   } else {
-    const R* u = (const R*)a.u_field;
+    const double* u = *a.u_slot;
     const int64_t N = a.nx * a.ny * a.nz;
     const int64_t node = (z * a.ny + y) * a.nx + x;
-    ux = u[node];
-    uy = u[N + node];
-    uz = u[2 * N + node];
+    const double vx = u[node], vy = u[N + node], vz = u[2 * N + node];
+    check_speed(a, vx * vx + vy * vy + vz * vz);
+    ux = (R)vx;
+    uy = (R)vy;
+    uz = (R)vz;
   }
 }
 

@@ -15,6 +15,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -26,6 +27,7 @@
 #include "d3q15.hpp"
 #include "adjoint_d2q9.hpp"
 #include "fp16_d2q9.hpp"
+#include "stability.hpp"
 
 using namespace lbm;
 
@@ -82,7 +84,8 @@ struct Run {
   bool split = false;                  // ... with phi stored apart
   double fp16_scale = 1.0;
   char* utab = nullptr;
-  char* ufield = nullptr;
+  char* ufield = nullptr;    // FP64 copy of the initial velocity field
+  char* uslot = nullptr;     // device pointer to the field the steps read
   char* node_par = nullptr;
   double* red_partial = nullptr;
   double* red_out = nullptr;
@@ -381,6 +384,66 @@ int check_velocity(const Run& r, int idx) {
   return LBM_CDE_OK;
 }
 
+// The relaxation matrix S of a run with constant D, row-major Q x Q: Eq. (31)
+// / (A.5) for MRT-A, Eq. (24) for the MRT-B models.
+void relaxation_matrix_of(const Run& r, double* S) {
+  const int Q = r.Q;
+  for (int i = 0; i < Q * Q; ++i) S[i] = 0.0;
+  const int flux[3] = {3, 5, 7}, heatrow[3] = {4, 6, 8};
+  for (int k = 0; k < Q; ++k) S[k * Q + k] = r.s[k];
+  for (int a = 0; a < r.dim; ++a) S[heatrow[a] * Q + heatrow[a]] = r.heat[a];
+  for (int a = 0; a < r.dim; ++a)
+    for (int b = 0; b < r.dim; ++b) {
+      S[flux[a] * Q + flux[b]] = r.A[a][b];
+      if (r.d.model == LBM_CDE_MRT_A)  // the coupling of Eq. (31); Eq. (24) has none
+        S[flux[a] * Q + heatrow[b]] = (a == b ? r.A[a][b] / 2.0 - 1.0 : r.A[a][b] / 2.0) * r.heat[b];
+    }
+}
+
+// Upper bound of the spectral radius of the linearised step of a run with
+// constant D and u (a 48^2 or 10^3 k-grid), remembered per parameter set.
+double spectral_radius_of(const Run& r) {
+  static std::mutex mu;
+  static std::map<std::string, double> cache;
+  double S[225];
+  relaxation_matrix_of(r, S);
+  std::string key = std::to_string(r.d.lattice) + ":" + std::to_string(r.d.model);
+  char buf[32];
+  for (int i = 0; i < r.Q * r.Q; ++i) {
+    std::snprintf(buf, sizeof buf, ":%a", S[i]);
+    key += buf;
+  }
+  for (int c = 0; c < r.dim; ++c) {
+    std::snprintf(buf, sizeof buf, ":%a", r.d.u_const[c]);
+    key += buf;
+  }
+  {
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = cache.find(key);
+    if (it != cache.end()) return it->second;
+  }
+  const double u[3] = {r.d.u_const[0], r.d.u_const[1], r.dim == 3 ? r.d.u_const[2] : 0.0};
+  const double rho = stability::spectral_radius(r.d.lattice, r.d.model, S, u, r.dim == 2 ? 48 : 10);
+  std::lock_guard<std::mutex> lock(mu);
+  cache[key] = rho;
+  return rho;
+}
+
+constexpr double kStabilityTol = 1e-5;  // accepted excess of the spectral-radius bound over 1
+
+// Linear stability of a run with constant D and u (unless the descriptor
+// asks to skip the check): EUNSTABLE if a Fourier mode grows.
+int check_stability(const Run& r, int idx) {
+  if (r.d.D_field || r.d.u_kind != LBM_CDE_U_CONST || r.d.skip_stability_check) return LBM_CDE_OK;
+  const double rho = spectral_radius_of(r);
+  if (rho > 1.0 + kStabilityTol)
+    return fail_init(LBM_CDE_EUNSTABLE,
+                     "run %d: the linearised step amplifies a Fourier mode by up to %.6f per step (the heat-flux "
+                     "rates, D and u give a spectral radius above 1)",
+                     idx, rho);
+  return LBM_CDE_OK;
+}
+
 // Workspace layout of one run; with base == nullptr only sizes are computed.
 size_t layout(Run& r, char* base) {
   const lbm_cde_run_desc& d = r.d;
@@ -410,10 +473,14 @@ size_t layout(Run& r, char* base) {
   }
   r.utab = nullptr;
   r.ufield = nullptr;
+  r.uslot = nullptr;
   r.node_par = nullptr;
   const size_t relem = r.dbl ? 8 : 4;  // arithmetic precision of tables and parameters
   if (d.u_kind == LBM_CDE_U_SEPARABLE) r.utab = take((size_t)r.dim * (1 + d.nx + d.ny + d.nz) * relem);
-  if (d.u_kind == LBM_CDE_U_FIELD) r.ufield = take((size_t)r.dim * r.nodes * relem);
+  if (d.u_kind == LBM_CDE_U_FIELD) {
+    r.ufield = take((size_t)r.dim * r.nodes * sizeof(double));
+    r.uslot = take(sizeof(double*));
+  }
   if (d.D_field) r.node_par = take((size_t)(r.dim == 2 ? 5 : 9) * r.nodes * relem);
   r.red_partial = (double*)take(sizeof(double) * 4 * RED_BLOCKS);
   r.red_out = (double*)take(sizeof(double) * 4);
@@ -454,7 +521,8 @@ RunArgs make_args(const lbm_cde* h, const Run& r, int parity) {
   a.u_kind = r.d.u_kind;
   for (int i = 0; i < 3; ++i) a.u_const[i] = r.d.u_const[i];
   a.u_tab = r.utab;
-  a.u_field = r.ufield;
+  a.u_slot = (const double* const*)r.uslot;
+  a.u_flag = r.flags ? (unsigned*)&r.flags[2] : nullptr;
   a.node_par = r.node_par;
   a.phi_ref = (r.dbl || r.split) ? 0.0 : r.d.phi_ref;
   for (int k = 0; k < 15; ++k) a.s[k] = r.s[k];
@@ -479,7 +547,8 @@ RunArgs make_args(const lbm_cde* h, const Run& r, int parity) {
   a.xref_drift = r.d.xref_drift;
   a.xcd_remap = r.var.xcd;
   a.rows32 = r.d.lattice == LBM_CDE_D2Q9 && !r.half && r.d.bc[0] == LBM_CDE_PERIODIC && !r.node_par &&
-             (double)r.plane * r.Q * r.elem < 4294967296.0 && r.d.nx < (1ll << 31) && r.d.ny < (1ll << 31);
+             (double)r.plane * r.Q * r.elem < 4294967296.0 && r.d.nx < (1ll << 31) && r.d.ny < (1ll << 31) &&
+             (r.d.u_kind != LBM_CDE_U_FIELD || 16.0 * (double)r.nodes < 4294967296.0);
   if (a.xcd_remap == 2 && tile_rows(r, r.var) % 8 != 0) a.xcd_remap = 0;
   a.active = 1;
   return a;
@@ -863,7 +932,7 @@ int init_runs(lbm_cde* h, const lbm_cde_run_desc* runs, int32_t nruns, const dou
     if (off + need > ws_bytes) return fail_init(LBM_CDE_ENOSPC, "init: workspace of %zu bytes is too small", ws_bytes);
     layout(r, workspace + off);
     off += need;
-    if ((rc = derive(r, i)) || (rc = check_velocity(r, i))) return rc;
+    if ((rc = derive(r, i)) || (rc = check_velocity(r, i)) || (rc = check_stability(r, i))) return rc;
     r.walls = false;
     for (int a = 0; a < r.dim; ++a) r.walls |= r.d.bc[a] != LBM_CDE_PERIODIC;
     r.var = default_variant(r.d.lattice, r.d.precision);
@@ -888,12 +957,19 @@ int init_runs(lbm_cde* h, const lbm_cde_run_desc* runs, int32_t nruns, const dou
         HIP_TRY(nullptr, hipStreamSynchronize(s));
       }
     } else if (orig.u_kind == LBM_CDE_U_FIELD) {
+      // the steps read the field through the slot: first the library's copy,
+      // later whatever lbm_cde_set_velocity points it at
       const int64_t n = r.dim * r.nodes;
       const unsigned blocks = (unsigned)((n + 255) / 256);
-      if (r.dbl)
-        hipLaunchKernelGGL(k_convert<double>, dim3(blocks), dim3(256), 0, s, orig.u_field, (double*)r.ufield, n);
-      else
-        hipLaunchKernelGGL(k_convert<float>, dim3(blocks), dim3(256), 0, s, orig.u_field, (float*)r.ufield, n);
+      hipLaunchKernelGGL(k_convert<double>, dim3(blocks), dim3(256), 0, s, orig.u_field, (double*)r.ufield, n);
+      hipLaunchKernelGGL(k_store_ptr, dim3(1), dim3(64), 0, s, (const double**)r.uslot, (const double*)r.ufield);
+      HIP_TRY(nullptr, hipMemsetAsync(&r.flags[2], 0, sizeof(unsigned long long), s));
+      hipLaunchKernelGGL(k_check_speed, dim3((unsigned)((r.nodes + 255) / 256)), dim3(256), 0, s,
+                         (const double*)r.ufield, r.dim, r.nodes, (unsigned*)&r.flags[2]);
+      unsigned long long fast = 0;
+      HIP_TRY(nullptr, hipMemcpyAsync(&fast, &r.flags[2], sizeof fast, hipMemcpyDeviceToHost, s));
+      HIP_TRY(nullptr, hipStreamSynchronize(s));
+      if (fast) return fail_init(LBM_CDE_EUNSTABLE, "run %d: |u| reaches the lattice sound speed 1/sqrt(3)", i);
     }
     if (orig.D_field) {
       HIP_TRY(nullptr, hipMemsetAsync(r.flags, 0, sizeof(unsigned long long), s));
@@ -1219,11 +1295,12 @@ int lbm_cde_workspace_bytes(const lbm_cde_run_desc* runs, int32_t nruns, size_t*
   if (!runs || nruns < 1 || !bytes) return fail_init(LBM_CDE_EINVAL, "workspace_bytes: null argument or nruns < 1");
   size_t total = 0;
   for (int i = 0; i < nruns; ++i) {
-    const int rc = validate(runs[i], i);
+    int rc = validate(runs[i], i);
     if (rc) return rc;
     Run r;
     r.d = runs[i];
     total += layout(r, nullptr);
+    if ((rc = derive(r, i)) || (rc = check_velocity(r, i)) || (rc = check_stability(r, i))) return rc;
   }
   if (batch_eligible(runs, nruns)) total += batch_bytes(nruns);
   *bytes = total;
@@ -1312,10 +1389,11 @@ int lbm_cde_reduce(lbm_cde_handle h, int32_t run, int32_t kind, double x_ref, do
   int rc = reduce_into(h, *r, kind, x_ref, r->red_out);
   if (rc) return rc;
   double res[4];
-  unsigned long long over = 0;
+  unsigned long long fl[3] = {0, 0, 0};
   HIP_TRY(h, hipMemcpyAsync(res, r->red_out, sizeof res, hipMemcpyDeviceToHost, h->stream));
-  HIP_TRY(h, hipMemcpyAsync(&over, &r->flags[1], sizeof over, hipMemcpyDeviceToHost, h->stream));
+  HIP_TRY(h, hipMemcpyAsync(fl, r->flags, sizeof fl, hipMemcpyDeviceToHost, h->stream));
   HIP_TRY(h, hipStreamSynchronize(h->stream));
+  const unsigned long long over = fl[1], fast = r->uslot ? fl[2] : 0;
   if (kind == LBM_CDE_RED_NONFINITE) {
     out[0] = res[3];
     out[1] = out[2] = 0.0;
@@ -1326,6 +1404,7 @@ int lbm_cde_reduce(lbm_cde_handle h, int32_t run, int32_t kind, double x_ref, do
     if (res[3] != 0.0) return fail(h, LBM_CDE_ENONFINITE, "reduce: %g non-finite values in the state", res[3]);
   }
   if (over) return fail(h, LBM_CDE_EOVERFLOW, "reduce: 16-bit storage of run %d saturated", run);
+  if (fast) return fail(h, LBM_CDE_EUNSTABLE, "reduce: a velocity field of run %d reached |u| >= 1/sqrt(3)", run);
   return LBM_CDE_OK;
 }
 
@@ -1408,31 +1487,30 @@ int lbm_cde_relaxation_matrix(lbm_cde_handle h, int32_t run, double* S_out) {
   Run* r = get_run(h, run);
   if (!r || !S_out) return fail(h, LBM_CDE_EINVAL, "relaxation_matrix: bad handle, run or pointer");
   if (r->node_par) return fail(h, LBM_CDE_EINVAL, "relaxation_matrix: run has a per-node D field");
-  const int Q = r->Q;
-  for (int i = 0; i < Q * Q; ++i) S_out[i] = 0.0;
-  const int flux[3] = {3, 5, 7}, heatrow[3] = {4, 6, 8};
-  for (int k = 0; k < Q; ++k) S_out[k * Q + k] = r->s[k];
-  for (int a = 0; a < r->dim; ++a) S_out[heatrow[a] * Q + heatrow[a]] = r->heat[a];
-  for (int a = 0; a < r->dim; ++a)
-    for (int b = 0; b < r->dim; ++b) {
-      S_out[flux[a] * Q + flux[b]] = r->A[a][b];
-      if (r->d.model == LBM_CDE_MRT_A)  // the coupling of Eq. (31); Eq. (24) has none
-        S_out[flux[a] * Q + heatrow[b]] = (a == b ? r->A[a][b] / 2.0 - 1.0 : r->A[a][b] / 2.0) * r->heat[b];
-    }
+  relaxation_matrix_of(*r, S_out);
+  return LBM_CDE_OK;
+}
+
+int lbm_cde_spectral_radius(const lbm_cde_run_desc* d, double* rho) {
+  if (!d || !rho) return fail_init(LBM_CDE_EINVAL, "spectral_radius: null argument");
+  int rc = validate(*d, 0);
+  if (rc) return rc;
+  Run r;
+  r.d = *d;
+  layout(r, nullptr);
+  if ((rc = derive(r, 0)) || (rc = check_velocity(r, 0))) return rc;
+  if (d->D_field || d->u_kind != LBM_CDE_U_CONST)
+    return fail_init(LBM_CDE_EUNSUPPORTED, "spectral_radius: needs a constant D and a constant u");
+  *rho = spectral_radius_of(r);
   return LBM_CDE_OK;
 }
 
 int lbm_cde_set_velocity(lbm_cde_handle h, int32_t run, const double* u) {
   Run* r = get_run(h, run);
   if (!r || !u) return fail(h, LBM_CDE_EINVAL, "set_velocity: bad handle, run or pointer");
-  if (r->d.u_kind != LBM_CDE_U_FIELD || !r->ufield)
+  if (r->d.u_kind != LBM_CDE_U_FIELD || !r->uslot)
     return fail(h, LBM_CDE_EINVAL, "set_velocity: run %d was not initialised with a velocity field", run);
-  const int64_t n = r->dim * r->nodes;
-  const unsigned blocks = (unsigned)((n + 255) / 256);
-  if (r->dbl)
-    hipLaunchKernelGGL(k_convert<double>, dim3(blocks), dim3(256), 0, h->stream, u, (double*)r->ufield, n);
-  else
-    hipLaunchKernelGGL(k_convert<float>, dim3(blocks), dim3(256), 0, h->stream, u, (float*)r->ufield, n);
+  hipLaunchKernelGGL(k_store_ptr, dim3(1), dim3(64), 0, h->stream, (const double**)r->uslot, u);
   HIP_TRY(h, hipGetLastError());
   return LBM_CDE_OK;
 }

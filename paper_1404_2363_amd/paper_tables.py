@@ -67,7 +67,11 @@ def run_hill_tables(tables=(1, 2), models=MODELS, precision: str = "fp64", devic
             for m in models:
                 runs.append(W.paper_hill(kind, HILL_TABLES[tab], n=n))
                 tags.append((tab, kind, m))
-    per_run = [{"model": m, "heat": "paper", "max_steps": int(r.steps), "phi_ref": 0.0}
+    # the printed set-up (s4 = s_xx, s6 = s_yy, u = 0.05 (1, 1)) is linearly
+    # unstable for short waves (spectral radius up to 1.012 for MRT-A, 1.006 for
+    # MRT-B2/B3), too slowly to lift round-off to a visible level over the
+    # printed run length; the stability check is skipped to repeat it
+    per_run = [{"model": m, "heat": "paper", "max_steps": int(r.steps), "phi_ref": 0.0, "stability_check": False}
                for r, (_, _, m) in zip(runs, tags)]
     s = Solver(runs, precision, device=device, per_run=per_run)
     t0 = time.perf_counter()

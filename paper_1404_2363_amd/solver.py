@@ -33,10 +33,13 @@ def _heat(desc, heat):
 
 def make_desc(wl, precision: str = "fp64", device="cuda:0", heat="lambda_min", rates=None,
               phi_ref: Optional[float] = None, max_steps: int = -1, xref0: float = 0.0,
-              xref_drift: float = 0.0, fp16_scale: float = 0.0, model: str = "A"):
+              xref_drift: float = 0.0, fp16_scale: float = 0.0, model: str = "A",
+              stability_check: bool = True):
     """Descriptor of one workload, plus the objects that must outlive init.
 
-    ``model`` is "A" (the modified model) or "B1" | "B2" | "B3" (unmodified)."""
+    ``model`` is "A" (the modified model) or "B1" | "B2" | "B3" (unmodified).
+    ``stability_check=False`` accepts a constant-u, constant-D run whose
+    linearised step is unstable (the library rejects it otherwise)."""
     keep = []
     d = L.lbm_cde_run_desc()
     d.lattice = LATTICES[wl.lattice]
@@ -82,6 +85,7 @@ def make_desc(wl, precision: str = "fp64", device="cuda:0", heat="lambda_min", r
     d.xref0, d.xref_drift = float(xref0), float(xref_drift)
     d.max_steps = int(max_steps)
     d.model = MODELS[model]
+    d.skip_stability_check = 0 if stability_check else 1
     return d, keep
 
 

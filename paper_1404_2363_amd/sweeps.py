@@ -65,7 +65,8 @@ def convergence(sizes=(128, 256, 512, 1024, 2048), precisions=("fp64", "fp32", "
     for prec in precisions:
         for n in sizes:
             runs = [_hill(k, n) for k in kinds]
-            phis, info = _run_batch(runs, prec, [{"heat": "paper", "max_steps": int(r.steps)} for r in runs])
+            phis, info = _run_batch(runs, prec, [{"heat": "paper", "max_steps": int(r.steps),
+                                                  "stability_check": False} for r in runs])
             for r, phi in zip(runs, phis):
                 ex = hill_exact(r, float(r.steps))
                 er = float(np.sqrt(((phi - ex) ** 2).sum()) / np.sqrt((ex ** 2).sum()))
@@ -104,7 +105,9 @@ def tau_sweep(taus=(0.6, 0.8, 1.0, 1.25, 1.5, 2.0), us=((0.0, 0.0), (0.05, 0.05)
                     r = _hill(kind, n, u=u, D_lat=eq44_D(kind, tau))
                     r.meta.update({"tau": tau, "model": m})
                     runs.append(r)
-                    per.append({"heat": "paper", "model": m, "max_steps": int(r.steps)})
+                    # the paper's rates; some (tau, u) points are unstable for
+                    # short waves, which the sweep repeats as printed
+                    per.append({"heat": "paper", "model": m, "max_steps": int(r.steps), "stability_check": False})
             phis, info = _run_batch(runs, precision, per)
             for r, phi in zip(runs, phis):
                 ex = hill_exact(r, float(r.steps))

@@ -153,7 +153,8 @@ def test_max_steps_budget():
 def test_relaxation_matrix_matches_oracle():
     wl = W.cellular(nx=16, ny=16, steps=1, n_hills=1, sigma=3.0)
     for heat in ("lambda_min", "paper", [0.9, 1.3]):
-        s = _solver(wl, "fp64", heat=heat)
+        # the paper's rule is unstable for this (rotated) tensor; only S is compared here
+        s = _solver(wl, "fp64", heat=heat, stability_check=heat != "paper")
         S = s.relaxation_matrix()
         prob = O.problem_for(wl, heat_rule=heat)
         Sref = prob.S.copy()

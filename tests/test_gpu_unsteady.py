@@ -105,3 +105,28 @@ def test_set_velocity_needs_a_field_run():
         s.set_velocity(np.zeros((2, 24, 32)))
     assert e.value.code == L.LBM_CDE_EINVAL
     s.close()
+
+
+def test_field_speed_limit():
+    """A field with |u| >= c_s is rejected at init; one set later marks the
+    run, and the next reduction reports EUNSTABLE."""
+    from paper_1404_2363_amd import _lib as L
+    from paper_1404_2363_amd.solver import Solver
+    wl = W.drifting_cellular(nx=40, ny=30, steps=4, n_hills=2, sigma=4.0, drift=0.0)
+    fast = np.array(wl.u_field, copy=True)
+    fast[0, 7, 11] = 0.6                               # above 1/sqrt(3) at one node
+    bad = W.drifting_cellular(nx=40, ny=30, steps=4, n_hills=2, sigma=4.0, drift=0.0)
+    bad.u_field = fast
+    with pytest.raises(L.LbmCdeError) as e:
+        Solver(bad, "fp64")
+    assert e.value.code == L.LBM_CDE_EUNSTABLE
+    for precision in ("fp64", "fp32"):
+        s = Solver(wl, precision)
+        s.step(2)
+        assert s.nonfinite() == 0                     # the run's own field is fine
+        s.set_velocity(fast)
+        s.step(1)
+        with pytest.raises(L.LbmCdeError) as e:
+            s.mass()
+        assert e.value.code == L.LBM_CDE_EUNSTABLE
+        s.close()

@@ -17,26 +17,15 @@ import pytest
 
 from oracle import lbm as O
 from paper_1404_2363_amd import workloads as W
+from state_views import populations
 
 pytestmark = pytest.mark.gpu
 
 TOL = {"fp64": 1e-12, "fp32": 1e-5, "fp16": 1e-3}
-ELEM = {"fp64": 8, "fp32": 4, "fp16": 2}
-
-
 def _populations(s, wl, precision, run=0):
     """Stored populations (Q, nodes) and, for split storage, phi (nodes)."""
     Q = 9 if wl.lattice == "d2q9" else 15
-    st = s.get_state(run).cpu().numpy()
-    n = wl.nodes
-    if precision == "fp16":
-        plane = (st.size - 4 * n) // (Q * 2)
-        pops = st[:Q * plane * 2].view(np.float16).reshape(Q, plane)[:, :n]
-        phi = st[Q * plane * 2:Q * plane * 2 + 4 * n].view(np.float32)
-        return pops.copy(), phi.copy()
-    dt = np.float64 if precision == "fp64" else np.float32
-    plane = st.size // (Q * ELEM[precision])
-    return st.view(dt).reshape(Q, plane)[:, :n].copy(), None
+    return populations(s.get_state(run).cpu().numpy(), Q, wl.nodes, precision)
 
 
 def _walk(wl, precision, steps, heat="lambda_min", min_variants=1):
