@@ -235,10 +235,14 @@ def adjoint_variant(precision="fp32"):
 
 def adjoint_segment_variant(n=2048, K=16, precision="fp32"):
     """One checkpoint segment of the adjoint on an n^2 grid with a per-node D
-    field: K forward steps recomputed from the checkpoint, then K reverse
-    steps.  Bytes per node: forward step 72 (populations) + 20 (per-node flux
-    block and heat rates, FP32); reverse step 36 (lambda) + 36 (forward
-    state) + 20 (parameters) + 48 (FP64 gradient read and written) + 36 (mu)."""
+    field (FP32): K forward steps recomputed from the checkpoint, then K
+    reverse steps.  Algorithmic bytes per node: a recomputed step reads 36
+    (populations) + 12 (per-node flux block A) and writes 36 (populations,
+    not for the last step) + 8 (v); a reverse step gathers 36 (mu), reads 8
+    (v) + 12 (A), writes 36 (mu) and moves the gradient: 12 (FP32 partial
+    written, first reverse step), 24 (partial read and written), or 12 + 48
+    (partial read, FP64 output read and written, last reverse step); the
+    last segment step adds the 8-byte injection dL/dphi."""
     import torch
     from paper_1404_2363_amd import _lib as L
     from paper_1404_2363_amd import workloads as W
@@ -253,7 +257,7 @@ def adjoint_segment_variant(n=2048, K=16, precision="fp32"):
     ck = s.get_state()
     mu = torch.zeros(nb, dtype=torch.uint8, device="cuda")
     mu_tmp = torch.empty_like(mu)
-    seg = torch.empty(nb * K, dtype=torch.uint8, device="cuda")
+    seg = torch.empty(L.lbm_cde_adjoint_scratch_bytes(s.h, 0, K), dtype=torch.uint8, device="cuda")
     grad = torch.zeros((3, n, n), dtype=torch.float64, device="cuda")
     g = torch.ones((n, n), dtype=torch.float64, device="cuda") * 1e-3
     inj = [None] * (K - 1) + [g.data_ptr()]
@@ -274,9 +278,13 @@ def adjoint_segment_variant(n=2048, K=16, precision="fp32"):
     finite = bool(torch.isfinite(grad).all())
     s.close()
     nodes = n * n
-    byts = nodes * (K * (92 + 176) + 8)
+    fwd = (K - 1) * 92 + 56
+    rev = K * 92 + 12 + (K - 2) * 24 + 60 + 8
+    byts = nodes * (fwd + rev)
     return {"precision": precision, "nodes": nodes, "segment_steps": K, "seconds_per_segment": t,
-            "forward_plus_reverse_mlups": nodes * K / t / 1e6, "bytes_per_node_step": {"forward": 92, "reverse": 176},
+            "forward_plus_reverse_mlups": nodes * K / t / 1e6,
+            "bytes_per_node": {"forward_step": 92, "reverse_step_first": 104, "reverse_step": 116,
+                               "reverse_step_last": 152, "segment": fwd + rev},
             "achieved_gbs": byts / t / 1e9, "hbm_frac": byts / t / 1e9 / HBM_PEAK_GBS, "finite": finite}
 
 

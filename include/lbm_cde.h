@@ -329,15 +329,26 @@ int lbm_cde_set_state(lbm_cde_handle h, int32_t run, const void* src, int64_t st
  * A = (D/kappa + I/2)^-1 (Eq. 36).  The heat-flux rates must be EXPLICIT
  * (fixed); otherwise EUNSUPPORTED.  All buffers are device memory. */
 
+/* Bytes of the scratch `seg` of lbm_cde_adjoint_segment for nsteps steps:
+ * two states (the recomputation's ping-pong pair), the two values
+ * v = (n3 + s4 n4 / 2, n5 + s6 n6 / 2) per node and step that the reverse
+ * steps need from the forward pass (storage precision), and an FP32 gradient
+ * partial of three values per node. */
+int lbm_cde_adjoint_scratch_bytes(lbm_cde_handle h, int32_t run, int32_t nsteps, size_t* bytes);
+
 /* Reverse sweep over one checkpoint segment of nsteps = K >= 1 steps,
  * t0 .. t0+K.  ckpt: the state p_t0 (lbm_cde_get_state layout).  seg:
- * scratch for K states.  inj: NULL, or a host array of K device pointers,
- * inj[k] = dL/dphi at step t0+k+1 (FP64 per node, x fastest) or NULL.
- * mu: in mu_{t0+K} (all zero for the last segment), out mu_{t0}; mu_tmp:
- * scratch of the same size (both state-sized, storage precision).  grad:
- * FP64 [3][ny][nx], components xx, yy, xy of dL/dD at every node (for a
- * constant D their sum over nodes), accumulated (+=).  The run's own state
- * is not touched. */
+ * scratch of lbm_cde_adjoint_scratch_bytes(h, run, K) bytes; the segment is
+ * recomputed forward from ckpt into it (bitwise the run's own steps).  inj:
+ * NULL, or a host array of K device pointers, inj[k] = dL/dphi at step
+ * t0+k+1 (FP64 per node, x fastest) or NULL.  mu: in mu_{t0+K} (all zero for
+ * the last segment), out mu_{t0}; mu_tmp: scratch of the same size (both
+ * state-sized, storage precision).  grad: FP64 [3][ny][nx], components xx,
+ * yy, xy of dL/dD at every node (for a constant D their sum over nodes),
+ * accumulated (+=).  With FP32 storage the contributions of the segment's
+ * steps are summed in FP32 (each is an FP32 product) and added to grad once;
+ * that sum adds a relative error of at most about K * 6e-8 of the sum of
+ * their magnitudes.  The run's own state is not touched. */
 int lbm_cde_adjoint_segment(lbm_cde_handle h, int32_t run, const void* ckpt, int32_t nsteps, void* seg,
                             const double* const* inj, void* mu, void* mu_tmp, double* grad);
 

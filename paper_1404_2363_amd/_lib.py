@@ -102,6 +102,7 @@ def load() -> ctypes.CDLL:
         "lbm_cde_state_bytes": [P, I32, ctypes.POINTER(ctypes.c_size_t)],
         "lbm_cde_get_state": [P, I32, P],
         "lbm_cde_set_state": [P, I32, P, I64],
+        "lbm_cde_adjoint_scratch_bytes": [P, I32, I32, ctypes.POINTER(ctypes.c_size_t)],
         "lbm_cde_adjoint_segment": [P, I32, P, I32, P, ctypes.POINTER(ctypes.c_void_p), P, P, P],
         "lbm_cde_adjoint_phi0": [P, I32, P, P, P],
         "lbm_cde_destroy": [P],
@@ -242,6 +243,12 @@ def lbm_cde_get_state(h: int, run: int, dst_ptr: int) -> None:
 
 def lbm_cde_set_state(h: int, run: int, src_ptr: int, steps: int) -> None:
     _check(load().lbm_cde_set_state(h, run, ctypes.c_void_p(src_ptr), steps), "lbm_cde_set_state", h)
+
+
+def lbm_cde_adjoint_scratch_bytes(h: int, run: int, nsteps: int) -> int:
+    out = ctypes.c_size_t(0)
+    _check(load().lbm_cde_adjoint_scratch_bytes(h, run, nsteps, ctypes.byref(out)), "lbm_cde_adjoint_scratch_bytes", h)
+    return int(out.value)
 
 
 def lbm_cde_adjoint_segment(h: int, run: int, ckpt_ptr: int, nsteps: int, seg_ptr: int, inj_ptrs,

@@ -66,7 +66,7 @@ class Rollout(torch.autograd.Function):
         dev = s.device
         mu = torch.zeros(nb, dtype=torch.uint8, device=dev)
         mu_tmp = torch.empty(nb, dtype=torch.uint8, device=dev)
-        seg = torch.empty(nb * spec.ckpt_every, dtype=torch.uint8, device=dev)
+        seg = torch.empty(L.lbm_cde_adjoint_scratch_bytes(s.h, 0, spec.ckpt_every), dtype=torch.uint8, device=dev)
         grad = torch.zeros((3, ny, nx), dtype=torch.float64, device=dev)
         T = spec.steps
         for t0 in sorted(ctx.ckpts, reverse=True):

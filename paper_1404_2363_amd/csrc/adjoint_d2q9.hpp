@@ -18,6 +18,12 @@
 // the flux block (heat-flux rates s4, s6 held fixed), and dA = -A (dD/kappa) A.
 // Pi^T gathers each population from its push destination: the neighbour
 // y + e_j, or across a wall the population that the wall rule sends there.
+//
+// mu_t does not depend on the forward state (the step is linear); the forward
+// state enters only through v.  The recomputation of a checkpoint segment
+// therefore keeps v_t (two values per node and step) instead of the states:
+// the reverse step reads 8 (FP32) bytes per node from the forward pass
+// rather than gathering nine populations.
 #pragma once
 
 #include "common.hpp"
@@ -72,45 +78,31 @@ LBM_FORCEINLINE R gather_adj(const RunArgs& a, const R* mu, int64_t x, int64_t y
   return mu[(int64_t)pop_of_d2q9(EX, EY) * a.plane + dy * a.nx + dx];
 }
 
-// One reverse step over every node: a.src = forward state p_t, mu_in =
-// mu_{t+1} (null: zero), inj = dL/dphi_{t+1} (null: none), mu_out = mu_t,
-// grad (FP64, [3][N]) accumulated.
-template <typename R, bool WALLS>
-__global__ __launch_bounds__(256) void k_adjoint_d2q9(const RunArgs a, const R* __restrict__ mu_in,
-                                                      const double* __restrict__ inj, R* __restrict__ mu_out,
-                                                      double* __restrict__ grad, double inv_kappa) {
-  // one block per 256-wide row tile (the tile index splits with scalar
-  // arithmetic; no per-thread 64-bit division)
+// v = (n3 + s4 n4 / 2, n5 + s6 n6 / 2) of the pre-collision populations f of
+// a node (n = M f - m_eq, Eq. 11 and 37; phi_ref = 0 unless shifted storage).
+template <typename R>
+LBM_FORCEINLINE void adjoint_v(const R (&f)[9], R ux, R uy, R phi_ref, const Rel2<R>& r, R& vx, R& vy) {
+  const R phi = f[0] + f[1] + f[2] + f[3] + f[4] + f[5] + f[6] + f[7] + f[8] + phi_ref;
+  const R dx13 = f[1] - f[3], dx58 = f[5] - f[6] - f[7] + f[8];
+  const R dy24 = f[2] - f[4], dy56 = f[5] + f[6] - f[7] - f[8];
+  const R n3 = dx13 + dx58 - phi * ux, n4 = dx58 - (R)2 * dx13 + phi * ux;
+  const R n5 = dy24 + dy56 - phi * uy, n6 = dy56 - (R)2 * dy24 + phi * uy;
+  vx = n3 + (R)0.5 * r.s4 * n4;
+  vy = n5 + (R)0.5 * r.s6 * n6;
+}
+
+// One forward step of the segment recomputation (256-wide row tiles): the
+// pull step of k_step_d2q9 from a.src to a.dst (when STORE; the same
+// arithmetic, so the states are bitwise those of the run), plus v of every
+// node into vout[2][N].
+template <typename R, bool WALLS, bool STORE>
+__global__ __launch_bounds__(256) void k_step_v_d2q9(const RunArgs a, R* __restrict__ vout) {
   const int64_t N = a.nx * a.ny;
   const int64_t ntx = (a.nx + 255) / 256;
   const int64_t x = (int64_t)(blockIdx.x % ntx) * 256 + threadIdx.x, y = blockIdx.x / ntx;
   if (x >= a.nx) return;
   const int64_t node = y * a.nx + x;
   const R* src = (const R*)a.src;
-
-  // adjoint populations lambda_{t+1}(y)
-  R l[9];
-  if (mu_in) {
-    l[0] = mu_in[node];
-    l[1] = gather_adj<R, WALLS, 1, 0>(a, mu_in, x, y);
-    l[2] = gather_adj<R, WALLS, 0, 1>(a, mu_in, x, y);
-    l[3] = gather_adj<R, WALLS, -1, 0>(a, mu_in, x, y);
-    l[4] = gather_adj<R, WALLS, 0, -1>(a, mu_in, x, y);
-    l[5] = gather_adj<R, WALLS, 1, 1>(a, mu_in, x, y);
-    l[6] = gather_adj<R, WALLS, -1, 1>(a, mu_in, x, y);
-    l[7] = gather_adj<R, WALLS, -1, -1>(a, mu_in, x, y);
-    l[8] = gather_adj<R, WALLS, 1, -1>(a, mu_in, x, y);
-  } else {
-#pragma unroll
-    for (int i = 0; i < 9; ++i) l[i] = (R)0;
-  }
-  if (inj) {
-    const R g = (R)inj[node];
-#pragma unroll
-    for (int i = 0; i < 9; ++i) l[i] += g;
-  }
-
-  // forward pre-collision populations g_t(y) and their non-equilibrium moments
   R f[9];
   f[0] = src[node];
   f[1] = gather_fwd<R, WALLS, 1, 0>(a, src, x, y);
@@ -123,13 +115,115 @@ __global__ __launch_bounds__(256) void k_adjoint_d2q9(const RunArgs a, const R* 
   f[8] = gather_fwd<R, WALLS, 1, -1>(a, src, x, y);
   R ux, uy;
   velocity2<R>(a, x, y, ux, uy);
+  const R phi_ref = (R)a.phi_ref;
   const Rel2<R> r = a.node_par ? node_rel2<R>(a, node) : const_rel2<R>(a);
-  const R phi = f[0] + f[1] + f[2] + f[3] + f[4] + f[5] + f[6] + f[7] + f[8] + (R)a.phi_ref;
-  const R dx13 = f[1] - f[3], dx58 = f[5] - f[6] - f[7] + f[8];
-  const R dy24 = f[2] - f[4], dy56 = f[5] + f[6] - f[7] - f[8];
-  const R n3 = dx13 + dx58 - phi * ux, n4 = dx58 - (R)2 * dx13 + phi * ux;
-  const R n5 = dy24 + dy56 - phi * uy, n6 = dy56 - (R)2 * dy24 + phi * uy;
-  const R vx = n3 + (R)0.5 * r.s4 * n4, vy = n5 + (R)0.5 * r.s6 * n6;
+  R vx, vy;
+  adjoint_v<R>(f, ux, uy, phi_ref, r, vx, vy);
+  store_pop<R, true>(vout + node, vx);
+  store_pop<R, true>(vout + N + node, vy);
+  if constexpr (STORE) {
+    collide_d2q9<R>(f, ux, uy, phi_ref, r);
+    R* dst = (R*)a.dst;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) store_pop<R, true>(dst + i * a.plane + node, f[i]);
+  }
+}
+
+// How a reverse step stores its gradient contribution g_c (c = xx, yy, xy)
+// of a node.  FP64 storage always accumulates in the FP64 output; FP32
+// storage accumulates the FP32 contributions of a checkpoint segment in an
+// FP32 partial and adds it to the FP64 output once, in the segment's last
+// reverse step:
+//   GRAD_F64       grad += g / kappa                     (read-modify-write, FP64)
+//   GRAD_F32_SET   part  = g                             (write, FP32)
+//   GRAD_F32_ADD   part += g                             (read-modify-write, FP32)
+//   GRAD_F32_FOLD  grad += ((double)part + g) / kappa     (FP32 read, FP64 read-modify-write)
+enum GradMode : int32_t { GRAD_F64 = 0, GRAD_F32_SET = 1, GRAD_F32_ADD = 2, GRAD_F32_FOLD = 3 };
+
+// One reverse step over every node: vin = v_t of the forward step t ([2][N],
+// from k_step_v_d2q9), mu_in = mu_{t+1}, inj = dL/dphi_{t+1} (read when INJ),
+// mu_out = mu_t, grad (FP64, [3][N]) and part (FP32, [3][N]) per GMODE; NT:
+// streaming stores.  One block per blockDim.x-wide row tile.  The loads of a
+// thread (adjoint populations, v, injection, gradient accumulators) are
+// issued together, without branches between them, before its first store.
+// Without walls every address is a 32-bit byte offset from a
+// kernel-argument base (the host checks that every offset fits).
+template <typename R, bool WALLS, int GMODE, bool INJ, bool NT>
+__global__ __launch_bounds__(512) void k_adjoint_d2q9(const RunArgs a, const R* __restrict__ vin,
+                                                      const R* __restrict__ mu_in, const double* __restrict__ inj,
+                                                      R* __restrict__ mu_out, double* __restrict__ grad,
+                                                      float* __restrict__ part, double inv_kappa) {
+  const int64_t N = a.nx * a.ny;
+  const uint32_t bx = blockDim.x;
+  const uint32_t ntx = (uint32_t)((a.nx + bx - 1) / bx);
+  const int64_t x = (int64_t)(blockIdx.x % ntx) * bx + threadIdx.x, y = blockIdx.x / ntx;
+  if (x >= a.nx) return;
+  const int64_t node = y * a.nx + x;
+
+  R l[9];  // adjoint populations lambda_{t+1}(y)
+  R vx, vy;  // v of the forward step at y
+  double injv = 0.0;
+  double g64[3] = {0.0, 0.0, 0.0};
+  float g32[3] = {0.0f, 0.0f, 0.0f};
+  uint32_t o_node = 0, pb = 0;  // byte offsets (no walls)
+  if constexpr (WALLS) {
+    l[0] = mu_in[node];
+    l[1] = gather_adj<R, WALLS, 1, 0>(a, mu_in, x, y);
+    l[2] = gather_adj<R, WALLS, 0, 1>(a, mu_in, x, y);
+    l[3] = gather_adj<R, WALLS, -1, 0>(a, mu_in, x, y);
+    l[4] = gather_adj<R, WALLS, 0, -1>(a, mu_in, x, y);
+    l[5] = gather_adj<R, WALLS, 1, 1>(a, mu_in, x, y);
+    l[6] = gather_adj<R, WALLS, -1, 1>(a, mu_in, x, y);
+    l[7] = gather_adj<R, WALLS, -1, -1>(a, mu_in, x, y);
+    l[8] = gather_adj<R, WALLS, 1, -1>(a, mu_in, x, y);
+    vx = vin[node];
+    vy = vin[N + node];
+    if constexpr (INJ) injv = inj[node];
+    if constexpr (GMODE == GRAD_F64 || GMODE == GRAD_F32_FOLD)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) g64[c] = grad[c * N + node];
+    if constexpr (GMODE == GRAD_F32_ADD || GMODE == GRAD_F32_FOLD)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) g32[c] = part[c * N + node];
+  } else {
+    constexpr uint32_t E = sizeof(R);
+    const uint32_t nx = (uint32_t)a.nx, ny = (uint32_t)a.ny, xu = (uint32_t)x, yu = (uint32_t)y;
+    const uint32_t xm = xu == 0 ? nx - 1u : xu - 1u, xp = xu + 1u == nx ? 0u : xu + 1u;
+    const uint32_t r0 = yu * nx, rm = (yu == 0 ? ny - 1u : yu - 1u) * nx, rp = (yu + 1u == ny ? 0u : yu + 1u) * nx;
+    pb = (uint32_t)a.plane * E;
+    o_node = (r0 + xu) * E;
+    const char* mb = (const char*)mu_in;
+    auto ld = [](const char* b, uint32_t o) { return *(const R*)(b + o); };
+    // lambda: population (ex, ey) from its push destination (x + ex, y + ey)
+    l[0] = ld(mb, o_node);
+    l[1] = ld(mb, pb + (r0 + xp) * E);
+    l[2] = ld(mb, 2u * pb + (rp + xu) * E);
+    l[3] = ld(mb, 3u * pb + (r0 + xm) * E);
+    l[4] = ld(mb, 4u * pb + (rm + xu) * E);
+    l[5] = ld(mb, 5u * pb + (rp + xp) * E);
+    l[6] = ld(mb, 6u * pb + (rp + xm) * E);
+    l[7] = ld(mb, 7u * pb + (rm + xm) * E);
+    l[8] = ld(mb, 8u * pb + (rm + xp) * E);
+    vx = ld((const char*)vin, o_node);
+    vy = ld((const char*)vin, (uint32_t)N * E + o_node);
+    const uint32_t o8 = (r0 + xu) * 8u, o4 = (r0 + xu) * 4u, n8 = (uint32_t)N * 8u, n4 = (uint32_t)N * 4u;
+    if constexpr (INJ) injv = *(const double*)((const char*)inj + o8);
+    if constexpr (GMODE == GRAD_F64 || GMODE == GRAD_F32_FOLD)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) g64[c] = *(const double*)((const char*)grad + c * n8 + o8);
+    if constexpr (GMODE == GRAD_F32_ADD || GMODE == GRAD_F32_FOLD)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) g32[c] = *(const float*)((const char*)part + c * n4 + o4);
+  }
+  R ux, uy;
+  velocity2<R>(a, x, y, ux, uy);
+  const Rel2<R> r = a.node_par ? node_rel2<R>(a, node) : const_rel2<R>(a);
+
+  if constexpr (INJ) {
+    const R g = (R)injv;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) l[i] += g;
+  }
 
   // w = M^-T lambda (moments of lambda over the squared row norms)
   const R sa = l[1] + l[2] + l[3] + l[4], sd = l[5] + l[6] + l[7] + l[8];
@@ -144,9 +238,7 @@ __global__ __launch_bounds__(256) void k_adjoint_d2q9(const RunArgs a, const R* 
   // gradient with respect to the D components (xx, yy, xy) of this node
   const R awx = r.axx * w3 + r.axy * w5, awy = r.axy * w3 + r.ayy * w5;
   const R avx = r.axx * vx + r.axy * vy, avy = r.axy * vx + r.ayy * vy;
-  grad[node] += inv_kappa * (double)(awx * avx);
-  grad[N + node] += inv_kappa * (double)(awy * avy);
-  grad[2 * N + node] += inv_kappa * (double)(awx * avy + awy * avx);
+  const R gc[3] = {awx * avx, awy * avy, awx * avy + awy * avx};
 
   // z = S^T w (Eq. 31 transposed)
   const R z1 = r.s1 * w1, z2 = r.s2 * w2;
@@ -168,8 +260,36 @@ __global__ __launch_bounds__(256) void k_adjoint_d2q9(const RunArgs a, const R* 
   m[6] = l[6] - (dg - p3 + p5 - z8) + ez;
   m[7] = l[7] - (dg - p3 - p5 + z8) + ez;
   m[8] = l[8] - (dg + p3 - p5 - z8) + ez;
+  double gout[3];
+  float pout[3];
 #pragma unroll
-  for (int i = 0; i < 9; ++i) mu_out[i * a.plane + node] = m[i];
+  for (int c = 0; c < 3; ++c) {
+    if constexpr (GMODE == GRAD_F64) gout[c] = g64[c] + inv_kappa * (double)gc[c];
+    else if constexpr (GMODE == GRAD_F32_FOLD) gout[c] = g64[c] + inv_kappa * ((double)g32[c] + (double)gc[c]);
+    else pout[c] = g32[c] + (float)gc[c];
+  }
+  if constexpr (WALLS) {
+#pragma unroll
+    for (int i = 0; i < 9; ++i) store_pop<R, NT>(mu_out + i * a.plane + node, m[i]);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      if constexpr (GMODE == GRAD_F64 || GMODE == GRAD_F32_FOLD) store_pop<double, NT>(grad + c * N + node, gout[c]);
+      else store_pop<float, NT>(part + c * N + node, pout[c]);
+    }
+  } else {
+    char* ob = (char*)mu_out;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) store_pop<R, NT>((R*)(ob + (uint32_t)i * pb + o_node), m[i]);
+    const uint32_t o8 = o_node / (uint32_t)sizeof(R) * 8u, o4 = o_node / (uint32_t)sizeof(R) * 4u;
+    const uint32_t n8 = (uint32_t)N * 8u, n4 = (uint32_t)N * 4u;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      if constexpr (GMODE == GRAD_F64 || GMODE == GRAD_F32_FOLD)
+        store_pop<double, NT>((double*)((char*)grad + c * n8 + o8), gout[c]);
+      else
+        store_pop<float, NT>((float*)((char*)part + c * n4 + o4), pout[c]);
+    }
+  }
 }
 
 // dL/dphi0 from lambda_0 = Pi^T mu_0 + dL/dphi_0: the initial state is

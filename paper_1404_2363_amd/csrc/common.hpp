@@ -32,6 +32,7 @@ struct RunArgs {
   const double* const* u_slot;  // FIELD: device slot holding the current FP64 field [dim][nodes]
   unsigned* u_flag;         // FIELD: set to 1 where |u| >= c_s = 1/sqrt(3) (sticky)
   const void* node_par;     // per-node relaxation parameters (type R) or null
+  int32_t node_heat_const;  // node_par's heat-flux rates equal heat[] at every node (not read)
   double phi_ref;
   double fp16_scale, fp16_inv_scale;
   void* fp16_flags;         // 16-bit storage: set to 1 when a value saturates

@@ -69,11 +69,13 @@ LBM_FORCEINLINE Rel2<R> const_rel2(const RunArgs& a) {
   return make_rel2<R>((R)a.A[0][0], (R)a.A[0][1], (R)a.A[1][1], (R)a.heat[0], (R)a.heat[1], a);
 }
 
-// Per-node relaxation parameters (D field): axx, axy, ayy, s4, s6 planes.
+// Per-node relaxation parameters (D field): axx, axy, ayy, s4, s6 planes; the
+// last two are not read when the heat-flux rates are the same at every node.
 template <typename R>
 LBM_FORCEINLINE Rel2<R> node_rel2(const RunArgs& a, int64_t node) {
   const R* p = (const R*)a.node_par;
   const int64_t N = a.nx * a.ny;
+  if (a.node_heat_const) return make_rel2<R>(p[node], p[N + node], p[2 * N + node], (R)a.heat[0], (R)a.heat[1], a);
   return make_rel2<R>(p[node], p[N + node], p[2 * N + node], p[3 * N + node], p[4 * N + node], a);
 }
 

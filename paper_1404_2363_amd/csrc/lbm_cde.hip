@@ -131,6 +131,8 @@ struct lbm_cde {
   bool env16_set = false;     // LBM_CDE_TILE16 = BXxBY[xNT[xORDER]]: split 16-bit launch variant
   Variant env16{64, 4, 1, false, 0};
   double* scratch_dev = nullptr;  // device address of `scratch` on the handle's GPU
+  int adj_bx = 256;                // row-tile width of the reverse (adjoint) kernel
+  bool adj_nt = true;              // streaming stores in the reverse kernel
 };
 
 namespace {
@@ -524,6 +526,7 @@ RunArgs make_args(const lbm_cde* h, const Run& r, int parity) {
   a.u_slot = (const double* const*)r.uslot;
   a.u_flag = r.flags ? (unsigned*)&r.flags[2] : nullptr;
   a.node_par = r.node_par;
+  a.node_heat_const = r.node_par && r.d.heat_rule == LBM_CDE_HEAT_EXPLICIT;
   a.phi_ref = (r.dbl || r.split) ? 0.0 : r.d.phi_ref;
   for (int k = 0; k < 15; ++k) a.s[k] = r.s[k];
   for (int i = 0; i < 3; ++i)
@@ -811,6 +814,13 @@ void parse_env(lbm_cde* h) {
   const char* xcd = std::getenv("LBM_CDE_XCD");
   const char* t16 = std::getenv("LBM_CDE_TILE16");
   int bx16, by16, nt16 = 0, xcd16 = 0;
+  if (const char* adj = std::getenv("LBM_CDE_ADJ")) {  // "BX[xNT]": reverse-kernel tile width, stores
+    int bx = 256, ntv = 0;
+    if (std::sscanf(adj, "%dx%d", &bx, &ntv) >= 1 && (bx == 64 || bx == 128 || bx == 256 || bx == 512)) {
+      h->adj_bx = bx;
+      h->adj_nt = ntv != 0;
+    }
+  }
   if (t16 && std::sscanf(t16, "%dx%dx%dx%d", &bx16, &by16, &nt16, &xcd16) >= 2) {
     h->env16_set = true;
     h->env16 = Variant{bx16, by16, 1, nt16 != 0, xcd16};
@@ -1273,16 +1283,86 @@ int check_adjoint_run(lbm_cde* h, Run* r) {
   return LBM_CDE_OK;
 }
 
-template <typename R>
-void launch_adjoint(const Run& r, const RunArgs& a, const void* mu_in, const double* inj, void* mu_out,
-                    double* grad, double inv_kappa, hipStream_t s) {
-  const unsigned blocks = (unsigned)((r.d.nx + 255) / 256 * r.d.ny);  // 256-wide row tiles
-  if (r.walls)
-    hipLaunchKernelGGL((k_adjoint_d2q9<R, true>), dim3(blocks), dim3(256), 0, s, a, (const R*)mu_in, inj,
-                       (R*)mu_out, grad, inv_kappa);
+// The buffers of one reverse step.
+struct AdjBufs {
+  const void* v;      // v_t of the forward step, [2][N]
+  const void* mu_in;  // mu_{t+1}
+  const double* inj;  // dL/dphi_{t+1} or null
+  void* mu_out;       // mu_t
+  double* grad;       // FP64 output [3][N]
+  float* part;        // FP32 partial [3][N]
+};
+
+template <typename R, bool WALLS, int GMODE, bool NT>
+void launch_adjoint_g(const RunArgs& a, unsigned blocks, unsigned bx, const AdjBufs& b, double inv_kappa,
+                      hipStream_t s) {
+  if (b.inj)
+    hipLaunchKernelGGL((k_adjoint_d2q9<R, WALLS, GMODE, true, NT>), dim3(blocks), dim3(bx), 0, s, a, (const R*)b.v,
+                       (const R*)b.mu_in, b.inj, (R*)b.mu_out, b.grad, b.part, inv_kappa);
   else
-    hipLaunchKernelGGL((k_adjoint_d2q9<R, false>), dim3(blocks), dim3(256), 0, s, a, (const R*)mu_in, inj,
-                       (R*)mu_out, grad, inv_kappa);
+    hipLaunchKernelGGL((k_adjoint_d2q9<R, WALLS, GMODE, false, NT>), dim3(blocks), dim3(bx), 0, s, a, (const R*)b.v,
+                       (const R*)b.mu_in, b.inj, (R*)b.mu_out, b.grad, b.part, inv_kappa);
+}
+
+template <typename R, bool WALLS, bool NT>
+void launch_adjoint_w(const RunArgs& a, unsigned blocks, unsigned bx, const AdjBufs& b, int gmode,
+                      double inv_kappa, hipStream_t s) {
+  if constexpr (sizeof(R) == 4) {
+    if (gmode == GRAD_F32_SET) return launch_adjoint_g<R, WALLS, GRAD_F32_SET, NT>(a, blocks, bx, b, inv_kappa, s);
+    if (gmode == GRAD_F32_ADD) return launch_adjoint_g<R, WALLS, GRAD_F32_ADD, NT>(a, blocks, bx, b, inv_kappa, s);
+    if (gmode == GRAD_F32_FOLD) return launch_adjoint_g<R, WALLS, GRAD_F32_FOLD, NT>(a, blocks, bx, b, inv_kappa, s);
+  }
+  launch_adjoint_g<R, WALLS, GRAD_F64, NT>(a, blocks, bx, b, inv_kappa, s);
+}
+
+// Every byte offset of the wall-free reverse kernel fits 32 bits: the Q
+// population planes and the three FP64 gradient planes.
+bool adjoint_offsets32(const Run& r) {
+  return (double)r.Q * r.plane * r.elem < 4294967296.0 && 24.0 * (double)r.nodes < 4294967296.0;
+}
+
+template <typename R>
+void launch_adjoint(const lbm_cde* h, const Run& r, const RunArgs& a, const AdjBufs& b, int gmode, double inv_kappa,
+                    hipStream_t s) {
+  const unsigned bx = (unsigned)h->adj_bx;
+  const unsigned blocks = (unsigned)((r.d.nx + bx - 1) / bx * r.d.ny);  // bx-wide row tiles
+  // periodic runs whose offsets do not fit 32 bits take the general kernel
+  const bool walls = r.walls || !adjoint_offsets32(r);
+  if (h->adj_nt) {
+    if (walls) launch_adjoint_w<R, true, true>(a, blocks, bx, b, gmode, inv_kappa, s);
+    else launch_adjoint_w<R, false, true>(a, blocks, bx, b, gmode, inv_kappa, s);
+  } else {
+    if (walls) launch_adjoint_w<R, true, false>(a, blocks, bx, b, gmode, inv_kappa, s);
+    else launch_adjoint_w<R, false, false>(a, blocks, bx, b, gmode, inv_kappa, s);
+  }
+}
+
+// One recomputed forward step of a segment: state and v, or only v (STORE false).
+template <typename R>
+void launch_step_v(const Run& r, const RunArgs& a, void* v, bool store, hipStream_t s) {
+  const unsigned blocks = (unsigned)((r.d.nx + 255) / 256 * r.d.ny);
+  if (r.walls) {
+    if (store) hipLaunchKernelGGL((k_step_v_d2q9<R, true, true>), dim3(blocks), dim3(256), 0, s, a, (R*)v);
+    else hipLaunchKernelGGL((k_step_v_d2q9<R, true, false>), dim3(blocks), dim3(256), 0, s, a, (R*)v);
+  } else {
+    if (store) hipLaunchKernelGGL((k_step_v_d2q9<R, false, true>), dim3(blocks), dim3(256), 0, s, a, (R*)v);
+    else hipLaunchKernelGGL((k_step_v_d2q9<R, false, false>), dim3(blocks), dim3(256), 0, s, a, (R*)v);
+  }
+}
+
+// Scratch of a segment of K steps: two ping-pong states, v of every step
+// ([K][2][N] in the storage precision) and the FP32 gradient partial [3][N].
+struct SegLayout {
+  size_t state, v_step, v, part, total;
+};
+SegLayout seg_layout(const Run& r, int64_t K) {
+  SegLayout L;
+  L.state = align_up((size_t)r.Q * r.plane * r.elem);
+  L.v_step = align_up(2 * (size_t)r.nodes * r.elem);
+  L.v = 2 * L.state;
+  L.part = L.v + (size_t)K * L.v_step;
+  L.total = L.part + align_up(3 * sizeof(float) * (size_t)r.nodes);
+  return L;
 }
 
 }  // namespace
@@ -1648,6 +1728,15 @@ int lbm_cde_set_state(lbm_cde_handle h, int32_t run, const void* src, int64_t st
   return LBM_CDE_OK;
 }
 
+int lbm_cde_adjoint_scratch_bytes(lbm_cde_handle h, int32_t run, int32_t nsteps, size_t* bytes) {
+  Run* r = get_run(h, run);
+  int rc = check_adjoint_run(h, r);
+  if (rc) return rc;
+  if (nsteps < 1 || !bytes) return fail(h, LBM_CDE_EINVAL, "adjoint_scratch_bytes: nsteps < 1 or null pointer");
+  *bytes = seg_layout(*r, nsteps).total;
+  return LBM_CDE_OK;
+}
+
 int lbm_cde_adjoint_segment(lbm_cde_handle h, int32_t run, const void* ckpt, int32_t nsteps, void* seg,
                             const double* const* inj, void* mu, void* mu_tmp, double* grad) {
   Run* r = get_run(h, run);
@@ -1655,28 +1744,36 @@ int lbm_cde_adjoint_segment(lbm_cde_handle h, int32_t run, const void* ckpt, int
   if (rc) return rc;
   if (!ckpt || nsteps < 1 || !seg || !mu || !mu_tmp || !grad)
     return fail(h, LBM_CDE_EINVAL, "adjoint_segment: null buffer or nsteps < 1");
-  const size_t sb = (size_t)r->Q * r->plane * r->elem;
+  const SegLayout L = seg_layout(*r, nsteps);
   char* segc = (char*)seg;
-  // recompute the forward states p_t0 .. p_t0+K-1 of the segment
-  HIP_TRY(h, hipMemcpyAsync(segc, ckpt, sb, hipMemcpyDeviceToDevice, h->stream));
-  StepFn step = pick_step(h, *r);
-  for (int k = 1; k < nsteps; ++k) {
+  char* P[2] = {segc, segc + L.state};
+  float* part = (float*)(segc + L.part);
+  // recompute the forward steps t0 .. t0+K-1 from the checkpoint, keeping v
+  // of each step (the last step needs no state)
+  for (int k = 0; k < nsteps; ++k) {
     RunArgs a = make_args(h, *r, 0);
-    a.src = segc + (size_t)(k - 1) * sb;
-    a.dst = segc + (size_t)k * sb;
-    step(a, h->stream);
+    a.src = k == 0 ? ckpt : P[k & 1];
+    a.dst = P[(k + 1) & 1];
+    void* v = segc + L.v + (size_t)k * L.v_step;
+    if (r->dbl) launch_step_v<double>(*r, a, v, k + 1 < nsteps, h->stream);
+    else launch_step_v<float>(*r, a, v, k + 1 < nsteps, h->stream);
   }
-  // reverse sweep: mu_{t+1} -> mu_t for t = t0+K-1 .. t0
+  // reverse sweep: mu_{t+1} -> mu_t for t = t0+K-1 .. t0.  FP32 storage
+  // gathers the segment's gradient in the FP32 partial and folds it into the
+  // FP64 output in the last reverse step.
   void* cur = mu;
   void* nxt = mu_tmp;
   for (int k = nsteps - 1; k >= 0; --k) {
-    RunArgs a = make_args(h, *r, 0);
-    a.src = segc + (size_t)k * sb;
-    const double* injk = inj ? inj[k] : nullptr;
-    if (r->dbl) launch_adjoint<double>(*r, a, cur, injk, nxt, grad, 1.0 / r->kappa, h->stream);
-    else launch_adjoint<float>(*r, a, cur, injk, nxt, grad, 1.0 / r->kappa, h->stream);
+    const RunArgs a = make_args(h, *r, 0);
+    const AdjBufs b{segc + L.v + (size_t)k * L.v_step, cur, inj ? inj[k] : nullptr, nxt, grad, part};
+    int gmode = GRAD_F64;
+    if (!r->dbl && nsteps >= 2)
+      gmode = k == nsteps - 1 ? GRAD_F32_SET : (k == 0 ? GRAD_F32_FOLD : GRAD_F32_ADD);
+    if (r->dbl) launch_adjoint<double>(h, *r, a, b, gmode, 1.0 / r->kappa, h->stream);
+    else launch_adjoint<float>(h, *r, a, b, gmode, 1.0 / r->kappa, h->stream);
     std::swap(cur, nxt);
   }
+  const size_t sb = (size_t)r->Q * r->plane * r->elem;
   if (cur != mu) HIP_TRY(h, hipMemcpyAsync(mu, cur, sb, hipMemcpyDeviceToDevice, h->stream));
   HIP_TRY(h, hipGetLastError());
   return LBM_CDE_OK;

@@ -37,6 +37,7 @@ def _setup(nx, ny, steps, snap, walls=("periodic", "periodic"), seed=5):
 
 @pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("fp32", 1e-4)])
 @pytest.mark.parametrize("walls,ckpt", [(("periodic", "periodic"), 20), (("periodic", "periodic"), 25),
+                                        (("periodic", "periodic"), 1), (("periodic", "periodic"), 2),
                                         (("periodic", "specular"), 20), (("bounce", "specular"), 30)])
 def test_adjoint_matches_oracle(precision, tol, walls, ckpt):
     import torch
@@ -74,6 +75,22 @@ def test_adjoint_rejects_adaptive_heat_rates():
                                   buf.data_ptr(), grad.data_ptr())
     assert e.value.code == L.LBM_CDE_EUNSUPPORTED
     s.close()
+
+
+def test_adjoint_scratch_is_smaller_than_the_states():
+    """The segment scratch holds two states and 2 values per node and step
+    (plus an FP32 partial), far less than the K states it replaces."""
+    from paper_1404_2363_amd import _lib as L
+    from paper_1404_2363_amd.solver import Solver
+    wl, d_trial, phi0, obs = _setup(64, 48, 10, 5)
+    for precision, elem in (("fp32", 4), ("fp64", 8)):
+        s = Solver(wl, precision, heat=[1.0, 1.0])
+        nb = s.state_bytes()
+        for K in (1, 7, 100):
+            b = L.lbm_cde_adjoint_scratch_bytes(s.h, 0, K)
+            assert 2 * nb + K * 2 * elem * wl.nodes <= b <= 2 * nb + K * (2 * elem * wl.nodes + 256) + 12 * wl.nodes + 256
+        assert L.lbm_cde_adjoint_scratch_bytes(s.h, 0, 100) < 0.25 * 100 * nb
+        s.close()
 
 
 def test_checkpoint_restart_is_bitwise():
