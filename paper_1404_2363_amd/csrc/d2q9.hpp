@@ -43,25 +43,31 @@ struct Rel2 {
 };
 
 template <typename R>
-LBM_FORCEINLINE Rel2<R> make_rel2(R axx, R axy, R ayy, R s4, R s6, const RunArgs& a) {
+LBM_FORCEINLINE Rel2<R> make_rel2_vals(R axx, R axy, R ayy, R s4, R s6, double s1, double s2, double s7, double s8,
+                                       int model) {
   Rel2<R> r;
-  r.s1 = (R)a.s[1];
-  r.s2 = (R)a.s[2];
-  r.s7 = (R)a.s[7];
-  r.s8 = (R)a.s[8];
+  r.s1 = (R)s1;
+  r.s2 = (R)s2;
+  r.s7 = (R)s7;
+  r.s8 = (R)s8;
   r.s4 = s4;
   r.s6 = s6;
   r.axx = axx;
   r.axy = axy;
   r.ayy = ayy;
-  const bool modified = a.model == LBM_CDE_MRT_A;
+  const bool modified = model == LBM_CDE_MRT_A;
   r.c34 = modified ? (axx * (R)0.5 - (R)1) * s4 : (R)0;
   r.c36 = modified ? (axy * (R)0.5) * s6 : (R)0;
   r.c54 = modified ? (axy * (R)0.5) * s4 : (R)0;
   r.c56 = modified ? (ayy * (R)0.5 - (R)1) * s6 : (R)0;
-  r.nl = (a.model == LBM_CDE_MRT_B1 || a.model == LBM_CDE_MRT_B2) ? (R)1 : (R)0;
-  r.c2 = a.model == LBM_CDE_MRT_B1 ? (R)1 : (R)2;
+  r.nl = (model == LBM_CDE_MRT_B1 || model == LBM_CDE_MRT_B2) ? (R)1 : (R)0;
+  r.c2 = model == LBM_CDE_MRT_B1 ? (R)1 : (R)2;
   return r;
+}
+
+template <typename R>
+LBM_FORCEINLINE Rel2<R> make_rel2(R axx, R axy, R ayy, R s4, R s6, const RunArgs& a) {
+  return make_rel2_vals<R>(axx, axy, ayy, s4, s6, a.s[1], a.s[2], a.s[7], a.s[8], a.model);
 }
 
 template <typename R>
@@ -429,6 +435,149 @@ __global__ __launch_bounds__(BX) void k_batch_d2q9(const RunArgs* __restrict__ r
     const int64_t ntx = (a.nx + BX - 1) / BX;
     if (a.rows32) tile_rows_d2q9<R, BX, NT>(a, local % ntx, local / ntx);
     else tile_d2q9<R, BX, 1, 1, true, NT>(a, local % ntx, local / ntx);
+  }
+}
+
+// ---- lean batched step ------------------------------------------------------
+//
+// A batch whose runs all take the row-tile path (x periodic, constant D,
+// 32-bit offsets) is stepped from a compact per-run record in device memory
+// instead of the full RunArgs: the tile's run is found by a binary search of
+// 32-bit tile starts, the row by one multiplication with the run's
+// reciprocal tile count, and every access is a global-address-space base
+// plus a 32-bit byte offset.  The collision is the same function with the
+// same operands, so the state is bitwise that of the other step kernels.
+
+struct BatchRun {
+  const char* pop[2];            // population buffers of parity 0 and 1
+  const char* u_tab;             // SEPARABLE: tables (type R)
+  const double* const* u_slot;   // FIELD: slot of the current FP64 field
+  unsigned* u_flag;              // FIELD: set where |u| >= c_s
+  uint32_t nx, ny, pb, ntx;      // grid, bytes per population plane, row tiles per row
+  uint32_t tile0;                // first tile of the run in the flat list
+  int32_t bc_y, u_kind, model;
+  int64_t max_steps;             // < 0: unlimited
+  double inv_ntx;                // 1 / ntx
+  double u_const[2], phi_ref;
+  double s1, s2, s7, s8, axx, axy, ayy, s4, s6;
+};
+
+template <typename T>
+LBM_FORCEINLINE T gld(const char* base, uint32_t off) {
+  return *(const __attribute__((address_space(1))) T*)(base + off);
+}
+
+template <typename T, bool NT>
+LBM_FORCEINLINE void gst(char* base, uint32_t off, T v) {
+  __attribute__((address_space(1))) T* p = (__attribute__((address_space(1))) T*)(base + off);
+  if constexpr (NT) __builtin_nontemporal_store(v, p);
+  else *p = v;
+}
+
+// Where population (EX, EY) of row y comes from (row_source_d2q9 on the
+// compact record).
+template <int EX, int EY>
+LBM_FORCEINLINE void row_source_b(int32_t bc_y, int32_t y, int32_t ny, int& pop, int32_t& sy, int& dx) {
+  pop = pop_of_d2q9(EX, EY);
+  dx = -EX;
+  sy = y - EY;
+  if (EY != 0 && (sy < 0 || sy >= ny)) {
+    if (bc_y == LBM_CDE_PERIODIC) {
+      sy = sy < 0 ? sy + ny : sy - ny;
+    } else if (bc_y == LBM_CDE_BOUNCE_BACK) {
+      pop = pop_of_d2q9(-EX, -EY);
+      sy = y;
+      dx = 0;
+    } else {
+      pop = pop_of_d2q9(EX, -EY);
+      sy = bc_y == LBM_CDE_NODE_MIRROR ? y + EY : y;
+    }
+  }
+}
+
+template <typename R, int BX, bool NT>
+__global__ __launch_bounds__(BX) void k_batch_rows_d2q9(const BatchRun* __restrict__ runs,
+                                                        const uint32_t* __restrict__ tile_start, int nruns,
+                                                        const int64_t* __restrict__ clock) {
+  const int64_t t_global = clock[0];
+  // active runs: a prefix of the list (runs are stored by decreasing budget)
+  int na;
+  {
+    int lo = 0, hi = nruns;
+    while (lo < hi) {
+      const int mid = (lo + hi) / 2;
+      const int64_t ms = runs[mid].max_steps;
+      if (ms >= 0 && t_global >= ms) hi = mid;
+      else lo = mid + 1;
+    }
+    na = lo;
+  }
+  const uint32_t total = tile_start[na];
+  const int par = (int)(t_global & 1);
+  for (uint32_t t = blockIdx.x; t < total; t += gridDim.x) {
+    int lo = 0, hi = na - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) / 2;
+      if (tile_start[mid] <= t) lo = mid;
+      else hi = mid - 1;
+    }
+    const BatchRun& br = runs[lo];
+    const uint32_t local = t - br.tile0;
+    const uint32_t row = (uint32_t)(((double)local + 0.5) * br.inv_ntx);
+    const uint32_t tx = local - row * br.ntx;
+    const uint32_t nx = br.nx;
+    const int32_t ny = (int32_t)br.ny;
+    const uint32_t x = tx * BX + threadIdx.x;
+    if (x >= nx) continue;
+    const int32_t y = (int32_t)row;
+    const uint32_t xm = x == 0 ? nx - 1u : x - 1u, xp = x + 1u == nx ? 0u : x + 1u;
+    const char* src = br.pop[par];
+    char* dst = (char*)br.pop[par ^ 1];
+    const uint32_t pb = br.pb;
+    R f[9];
+#define LBM_BATCH_PULL(I, EX, EY)                                                                      \
+  {                                                                                                  \
+    int pop, dx;                                                                                     \
+    int32_t sy;                                                                                      \
+    row_source_b<EX, EY>(br.bc_y, y, ny, pop, sy, dx);                                               \
+    const uint32_t sx = dx < 0 ? xm : (dx > 0 ? xp : x);                                             \
+    f[I] = gld<R>(src, (uint32_t)pop * pb + ((uint32_t)sy * nx + sx) * (uint32_t)sizeof(R));         \
+  }
+    LBM_BATCH_PULL(0, 0, 0)
+    LBM_BATCH_PULL(1, 1, 0)
+    LBM_BATCH_PULL(2, 0, 1)
+    LBM_BATCH_PULL(3, -1, 0)
+    LBM_BATCH_PULL(4, 0, -1)
+    LBM_BATCH_PULL(5, 1, 1)
+    LBM_BATCH_PULL(6, -1, 1)
+    LBM_BATCH_PULL(7, -1, -1)
+    LBM_BATCH_PULL(8, 1, -1)
+#undef LBM_BATCH_PULL
+    R ux, uy;
+    if (br.u_kind == U_CONST) {
+      ux = (R)br.u_const[0];
+      uy = (R)br.u_const[1];
+    } else if (br.u_kind == U_SEPARABLE) {
+      const char* tb = br.u_tab;
+      const uint32_t stride = (1u + nx + (uint32_t)ny + 1u) * (uint32_t)sizeof(R);
+      const uint32_t ox = (1u + x) * (uint32_t)sizeof(R), oy = (1u + nx + (uint32_t)y) * (uint32_t)sizeof(R);
+      const uint32_t oz = (1u + nx + (uint32_t)ny) * (uint32_t)sizeof(R);
+      ux = ((gld<R>(tb, 0) * gld<R>(tb, ox)) * gld<R>(tb, oy)) * gld<R>(tb, oz);
+      uy = ((gld<R>(tb, stride) * gld<R>(tb, stride + ox)) * gld<R>(tb, stride + oy)) * gld<R>(tb, stride + oz);
+    } else {
+      const char* u = (const char*)*br.u_slot;
+      const uint32_t o = ((uint32_t)y * nx + x) * 8u;
+      const double vx = gld<double>(u, o), vy = gld<double>(u, nx * (uint32_t)ny * 8u + o);
+      if (vx * vx + vy * vy >= 1.0 / 3.0) *br.u_flag = 1u;
+      ux = (R)vx;
+      uy = (R)vy;
+    }
+    const Rel2<R> rc = make_rel2_vals<R>((R)br.axx, (R)br.axy, (R)br.ayy, (R)br.s4, (R)br.s6, br.s1, br.s2, br.s7,
+                                         br.s8, br.model);
+    collide_d2q9<R>(f, ux, uy, (R)br.phi_ref, rc);
+    const uint32_t nb = ((uint32_t)y * nx + x) * (uint32_t)sizeof(R);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) gst<R, NT>(dst, (uint32_t)i * pb + nb, f[i]);
   }
 }
 

@@ -116,6 +116,9 @@ struct lbm_cde {
   int32_t* dev_order = nullptr;      // run of each tile-list position (decreasing step budget)
   int64_t* dev_clock = nullptr;      // [0] global steps, [1] history rows written
   std::vector<int32_t> batch_order;  // host copy of dev_order
+  bool batch_lean = false;           // every run takes the row-tile path: compact records
+  BatchRun* dev_brun = nullptr;      // compact records in tile-list order
+  uint32_t* dev_tiles32 = nullptr;   // 32-bit tile starts of the compact launch
   double* batch_partial = nullptr;   // reduction partials [nruns][kBatchRedBlocks][3]
   int64_t global_steps = 0;
   Variant batch_var{256, 1, 1, true, 0, 0};  // row-tile width, stores and grid of the batched launch
@@ -571,7 +574,8 @@ bool batch_eligible(const lbm_cde_run_desc* runs, int32_t nruns) {
 size_t batch_bytes(int32_t nruns) {
   return align_up(sizeof(RunArgs) * nruns) + align_up(sizeof(int64_t) * (nruns + 1)) +
          align_up(sizeof(int32_t) * nruns) + align_up(2 * sizeof(int64_t)) +
-         align_up(sizeof(double) * 3 * kBatchRedBlocks * nruns);
+         align_up(sizeof(double) * 3 * kBatchRedBlocks * nruns) + align_up(sizeof(BatchRun) * nruns) +
+         align_up(sizeof(uint32_t) * (nruns + 1));
 }
 
 // ---- kernel dispatch ------------------------------------------------------
@@ -870,8 +874,12 @@ struct BatchEntry {
 };
 template <typename R, int BX, bool NT>
 void launch_batch(const lbm_cde* h, hipStream_t s) {
-  hipLaunchKernelGGL((k_batch_d2q9<R, BX, NT>), dim3(h->batch_grid), dim3(BX), 0, s, h->dev_runs, h->dev_tiles,
-                     h->dev_order, (int)h->runs.size(), h->dev_clock);
+  if (h->batch_lean)
+    hipLaunchKernelGGL((k_batch_rows_d2q9<R, BX, NT>), dim3(h->batch_grid), dim3(BX), 0, s, h->dev_brun,
+                       h->dev_tiles32, (int)h->runs.size(), h->dev_clock);
+  else
+    hipLaunchKernelGGL((k_batch_d2q9<R, BX, NT>), dim3(h->batch_grid), dim3(BX), 0, s, h->dev_runs, h->dev_tiles,
+                       h->dev_order, (int)h->runs.size(), h->dev_clock);
 }
 #define BATCH_ENTRY(BX, NT) \
   BatchEntry { BX, NT, {launch_batch<float, BX, NT>, launch_batch<double, BX, NT>} }
@@ -918,6 +926,46 @@ int apply_batch_variant(lbm_cde* h, const Variant& v, std::vector<int64_t>* tile
   }
   if (tiles.back() >= ((int64_t)1 << 31)) return fail(h, LBM_CDE_EINVAL, "batch: too many tiles");
   HIP_TRY(h, hipMemcpyAsync(h->dev_tiles, tiles.data(), sizeof(int64_t) * (nruns + 1), hipMemcpyHostToDevice,
+                            h->stream));
+  // compact records of the lean launch, in tile-list order
+  std::vector<BatchRun> br(nruns);
+  std::vector<uint32_t> t32(nruns + 1);
+  for (int32_t k = 0; k <= nruns; ++k) t32[k] = (uint32_t)tiles[k];
+  for (int32_t k = 0; k < nruns; ++k) {
+    const Run& r = h->runs[h->batch_order[k]];
+    const RunArgs a = make_args(h, r, 0);
+    BatchRun& b = br[k];
+    std::memset(&b, 0, sizeof b);
+    b.pop[0] = (const char*)r.pop[0];
+    b.pop[1] = (const char*)r.pop[1];
+    b.u_tab = (const char*)a.u_tab;
+    b.u_slot = a.u_slot;
+    b.u_flag = a.u_flag;
+    b.nx = (uint32_t)r.d.nx;
+    b.ny = (uint32_t)r.d.ny;
+    b.pb = (uint32_t)(r.plane * (int64_t)r.elem);
+    b.ntx = (uint32_t)((r.d.nx + v.bx - 1) / v.bx);
+    b.inv_ntx = 1.0 / (double)b.ntx;
+    b.tile0 = t32[k];
+    b.bc_y = r.d.bc[1];
+    b.u_kind = r.d.u_kind;
+    b.model = r.d.model;
+    b.max_steps = r.d.max_steps;
+    b.u_const[0] = a.u_const[0];
+    b.u_const[1] = a.u_const[1];
+    b.phi_ref = a.phi_ref;
+    b.s1 = a.s[1];
+    b.s2 = a.s[2];
+    b.s7 = a.s[7];
+    b.s8 = a.s[8];
+    b.axx = a.A[0][0];
+    b.axy = a.A[0][1];
+    b.ayy = a.A[1][1];
+    b.s4 = a.heat[0];
+    b.s6 = a.heat[1];
+  }
+  HIP_TRY(h, hipMemcpyAsync(h->dev_brun, br.data(), sizeof(BatchRun) * nruns, hipMemcpyHostToDevice, h->stream));
+  HIP_TRY(h, hipMemcpyAsync(h->dev_tiles32, t32.data(), sizeof(uint32_t) * (nruns + 1), hipMemcpyHostToDevice,
                             h->stream));
   HIP_TRY(h, hipStreamSynchronize(h->stream));
   drop_graphs(h);
@@ -1027,8 +1075,17 @@ int init_runs(lbm_cde* h, const lbm_cde_run_desc* runs, int32_t nruns, const dou
     h->dev_clock = (int64_t*)p;
     p += align_up(2 * sizeof(int64_t));
     h->batch_partial = (double*)p;
+    p += align_up(sizeof(double) * 3 * kBatchRedBlocks * nruns);
+    h->dev_brun = (BatchRun*)p;
+    p += align_up(sizeof(BatchRun) * nruns);
+    h->dev_tiles32 = (uint32_t*)p;
     std::vector<RunArgs> args;
-    for (auto& r : h->runs) args.push_back(make_args(h, r, 0));
+    h->batch_lean = true;
+    for (auto& r : h->runs) {
+      args.push_back(make_args(h, r, 0));
+      h->batch_lean = h->batch_lean && args.back().rows32;
+    }
+    if (std::getenv("LBM_CDE_BATCH_GENERAL")) h->batch_lean = false;  // the general kernel for every batch
     // tile list in order of decreasing step budget (unlimited first), so that
     // the active runs always own a prefix of it
     std::vector<int32_t> order(nruns);

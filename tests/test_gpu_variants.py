@@ -209,3 +209,49 @@ def test_batch_tuner_keeps_state():
     for i in range(len(wls)):
         np.testing.assert_array_equal(a.phi(i).cpu().numpy(), b.phi(i).cpu().numpy())
     print("batch tuner picked", a.variant(), flush=True)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_batch_general_kernel_equals_compact_kernel(precision, monkeypatch):
+    """A batch whose runs all have periodic x and constant D is stepped from
+    compact per-run records; the general batched kernel (forced here) gives
+    bitwise the same states, in every listed variant plus a 7-block grid."""
+    wls, per, make = _batch(precision)
+    s = make()
+    cands = s.variants()
+    s.close()
+    picks = [cands[0], cands[7], cands[-1], {**cands[3], "grid": 7}]
+    for v in picks:
+        outs = []
+        for general in (False, True):
+            if general:
+                monkeypatch.setenv("LBM_CDE_BATCH_GENERAL", "1")
+            else:
+                monkeypatch.delenv("LBM_CDE_BATCH_GENERAL", raising=False)
+            s = make()
+            s.set_variant(v)
+            s.step(40)
+            outs.append([s.phi(i).cpu().numpy() for i in range(len(wls))])
+            s.close()
+        for i in range(len(wls)):
+            np.testing.assert_array_equal(outs[0][i], outs[1][i], err_msg=f"{v} run {i}")
+
+
+def test_batch_with_walls_in_x_uses_general_kernel():
+    """A run with walls across x (no row-tile path) makes the batch take the
+    general kernel; each run still equals the oracle at its own budget."""
+    from paper_1404_2363_amd.solver import Solver
+    wls, per, _ = _batch("fp64")
+    walled = W.taylor_aris_channel(10, 9.0, 1.2, nx=90, wall="specular", steps=40)
+    walled.walls = ("bounce", "specular")
+    wls = wls + [walled]
+    per = per + [{"max_steps": 29, "heat": [1 / 1.2, 1 / 1.2]}]
+    s = Solver(wls, "fp64", per_run=per)
+    s.set_variant({**s.variant(), "grid": 5})
+    s.step(40)
+    for i, (wl, p) in enumerate(zip(wls, per)):
+        steps = 40 if p["max_steps"] < 0 else p["max_steps"]
+        r, _ = O.run_workload(wl, steps=steps, heat_rule=p["heat"])
+        err = float(np.abs(s.phi(i).cpu().numpy() - r).max() / np.abs(r).max())
+        assert err <= 1e-12, (i, err)
+    s.close()
