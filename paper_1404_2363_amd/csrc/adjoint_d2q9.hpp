@@ -96,10 +96,10 @@ LBM_FORCEINLINE void adjoint_v(const R (&f)[9], R ux, R uy, R phi_ref, const Rel
 // arithmetic, so the states are bitwise those of the run), plus v of every
 // node into vout[2][N].
 template <typename R, bool WALLS, bool STORE>
-__global__ __launch_bounds__(256) void k_step_v_d2q9(const RunArgs a, R* __restrict__ vout) {
+__global__ __launch_bounds__(256) void k_step_v_d2q9(const RunArgs a, R* __restrict__ vout, const FastDiv ntx) {
   const int64_t N = a.nx * a.ny;
-  const int64_t ntx = (a.nx + 255) / 256;
-  const int64_t x = (int64_t)(blockIdx.x % ntx) * 256 + threadIdx.x, y = blockIdx.x / ntx;
+  const uint32_t yq = fdiv(blockIdx.x, ntx);
+  const int64_t x = (int64_t)(blockIdx.x - yq * ntx.d) * 256 + threadIdx.x, y = yq;
   if (x >= a.nx) return;
   const int64_t node = y * a.nx + x;
   const R* src = (const R*)a.src;
@@ -152,11 +152,11 @@ template <typename R, bool WALLS, int GMODE, bool INJ, bool NT>
 __global__ __launch_bounds__(512) void k_adjoint_d2q9(const RunArgs a, const R* __restrict__ vin,
                                                       const R* __restrict__ mu_in, const double* __restrict__ inj,
                                                       R* __restrict__ mu_out, double* __restrict__ grad,
-                                                      float* __restrict__ part, double inv_kappa) {
+                                                      float* __restrict__ part, double inv_kappa, const FastDiv ntx) {
   const int64_t N = a.nx * a.ny;
   const uint32_t bx = blockDim.x;
-  const uint32_t ntx = (uint32_t)((a.nx + bx - 1) / bx);
-  const int64_t x = (int64_t)(blockIdx.x % ntx) * bx + threadIdx.x, y = blockIdx.x / ntx;
+  const uint32_t yq = fdiv(blockIdx.x, ntx);
+  const int64_t x = (int64_t)(blockIdx.x - yq * ntx.d) * bx + threadIdx.x, y = yq;
   if (x >= a.nx) return;
   const int64_t node = y * a.nx + x;
 

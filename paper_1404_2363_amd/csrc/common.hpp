@@ -12,6 +12,25 @@
 
 namespace lbm {
 
+// n / d for n < 2^31 with one multiply-high: m = floor(2^(31+s) / d) + 1,
+// s = ceil(log2 d) (s = 0 for d = 1).  For 2^(s-1) < d <= 2^s the error of
+// m / 2^(31+s) against 1/d keeps floor(n m / 2^(31+s)) = floor(n / d) for
+// every n < 2^31.  Computed on the host; the kernels' tile decompositions
+// then need no integer division.
+struct FastDiv {
+  uint32_t d, m, s;
+};
+
+inline FastDiv make_fastdiv(uint32_t d) {
+  FastDiv f{d, 0u, 0u};
+  if (d <= 1) return f;
+  uint32_t s = 0;
+  while ((1ull << s) < d) ++s;
+  f.s = s;
+  f.m = (uint32_t)(((uint64_t)1 << (31 + s)) / d + 1);
+  return f;
+}
+
 // Velocity description in the precision R of the arithmetic.
 enum UKind : int32_t { U_CONST = 0, U_SEPARABLE = 1, U_FIELD = 2 };
 
@@ -29,6 +48,7 @@ struct RunArgs {
   int32_t u_kind;
   double u_const[3];
   const void* u_tab;        // SEPARABLE: per component: amp, X[nx], Y[ny], Z[nz] (type R)
+  int32_t u_z_unit;         // SEPARABLE 2D: Z[0] == 1 exactly for both components
   const double* const* u_slot;  // FIELD: device slot holding the current FP64 field [dim][nodes]
   unsigned* u_flag;         // FIELD: set to 1 where |u| >= c_s = 1/sqrt(3) (sticky)
   const void* node_par;     // per-node relaxation parameters (type R) or null
@@ -46,7 +66,9 @@ struct RunArgs {
   float split_g[14];
   float split_inv;
   void* split_dst[9];       // base of each destination half plane (periodic split step)
-  int32_t xcd_remap;        // block order (see tile_of_block)
+  int32_t xcd_remap;        // block order (see tile_of_block32)
+  FastDiv tiles_x;          // x tiles of the launch's block shape
+  FastDiv tiles_y;          // tile rows per z plane (D3Q15)
   int32_t rows32;           // D2Q9 batch: x periodic, constant D, every byte offset < 4 GiB
   int32_t active;           // 0: run has used its step budget
   int64_t max_steps;        // step budget (< 0: unlimited), used by batched launches
@@ -79,8 +101,38 @@ LBM_FORCEINLINE int64_t tile_of_block(int64_t b, int64_t nb, int64_t ntx, int mo
   return b;
 }
 
+LBM_FORCEINLINE uint32_t fdiv(uint32_t n, const FastDiv& f) { return f.s == 0 ? n : __umulhi(n, f.m) >> (f.s - 1); }
+
+// tile_of_block in 32 bits with the host's division by the x-tile count.
+LBM_FORCEINLINE uint32_t tile_of_block32(uint32_t b, uint32_t nb, const FastDiv& ntx, int mode) {
+  if (mode == 1) {
+    const uint32_t xcd = b & 7u, local = b >> 3, per = nb >> 3, rem = nb & 7u;
+    return xcd * per + (xcd < rem ? xcd : rem) + local;
+  }
+  if (mode == 2) {
+    const uint32_t xcd = b & 7u, local = b >> 3;
+    const uint32_t group = fdiv(local, ntx), tx = local - group * ntx.d;
+    return (group * 8u + xcd) * ntx.d + tx;
+  }
+  return b;
+}
+
 template <typename R>
 LBM_FORCEINLINE R load_ro(const R* p) { return __builtin_nontemporal_load(p); }
+
+// Load / store through a global-address-space base and a 32-bit byte offset
+// (the base-plus-offset addressing of the memory instructions).
+template <typename T>
+LBM_FORCEINLINE T gld(const char* base, uint32_t off) {
+  return *(const __attribute__((address_space(1))) T*)(base + off);
+}
+
+template <typename T, bool NT>
+LBM_FORCEINLINE void gst(char* base, uint32_t off, T v) {
+  __attribute__((address_space(1))) T* p = (__attribute__((address_space(1))) T*)(base + off);
+  if constexpr (NT) __builtin_nontemporal_store(v, p);
+  else *p = v;
+}
 
 // A per-node velocity read from a FIELD run: flag speeds at or above the
 // lattice sound speed (the step is unstable there).

@@ -305,9 +305,9 @@ LBM_FORCEINLINE void tile_d2q9(const RunArgs& a, int64_t tile_x, int64_t tile_y)
 // One step of one run: one block per tile, in the chosen block order.
 template <typename R, int BX, int BY, int NY, bool WALLS, bool NT>
 __global__ __launch_bounds__(BX * BY) void k_step_d2q9(const RunArgs a) {
-  const int64_t ntx = (a.nx + BX - 1) / BX;
-  const int64_t b = tile_of_block(blockIdx.x, gridDim.x, ntx, a.xcd_remap);
-  tile_d2q9<R, BX, BY, NY, WALLS, NT>(a, b % ntx, b / ntx);
+  const uint32_t b = tile_of_block32(blockIdx.x, gridDim.x, a.tiles_x, a.xcd_remap);
+  const uint32_t ty = fdiv(b, a.tiles_x);
+  tile_d2q9<R, BX, BY, NY, WALLS, NT>(a, b - ty * a.tiles_x.d, ty);
 }
 
 // Where population (EX, EY) of row y comes from when x is periodic: the
@@ -461,18 +461,6 @@ struct BatchRun {
   double u_const[2], phi_ref;
   double s1, s2, s7, s8, axx, axy, ayy, s4, s6;
 };
-
-template <typename T>
-LBM_FORCEINLINE T gld(const char* base, uint32_t off) {
-  return *(const __attribute__((address_space(1))) T*)(base + off);
-}
-
-template <typename T, bool NT>
-LBM_FORCEINLINE void gst(char* base, uint32_t off, T v) {
-  __attribute__((address_space(1))) T* p = (__attribute__((address_space(1))) T*)(base + off);
-  if constexpr (NT) __builtin_nontemporal_store(v, p);
-  else *p = v;
-}
 
 // Where population (EX, EY) of row y comes from (row_source_d2q9 on the
 // compact record).

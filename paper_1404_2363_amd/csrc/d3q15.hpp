@@ -229,12 +229,10 @@ LBM_FORCEINLINE int64_t pull_index_d3q15(const RunArgs& a, int64_t x, int64_t y,
 // thread owns NY rows (y, y + BY, ...).  Loads precede collisions.
 template <typename R, int BX, int BY, int NY, bool WALLS, bool NT>
 __global__ __launch_bounds__(BX * BY) void k_step_d3q15(const RunArgs a) {
-  const int64_t ntx = (a.nx + BX - 1) / BX;
-  const int64_t nty = (a.ny + BY * NY - 1) / (BY * NY);
-  const int64_t b = tile_of_block(blockIdx.x, gridDim.x, ntx, a.xcd_remap);
-  const int64_t tile_x = b % ntx;
-  const int64_t rest = b / ntx;
-  const int64_t tile_y = rest % nty, z = rest / nty;
+  const uint32_t b = tile_of_block32(blockIdx.x, gridDim.x, a.tiles_x, a.xcd_remap);
+  const uint32_t rest = fdiv(b, a.tiles_x), zq = fdiv(rest, a.tiles_y);
+  const int64_t tile_x = b - rest * a.tiles_x.d;
+  const int64_t tile_y = rest - zq * a.tiles_y.d, z = zq;
   const int64_t x = tile_x * BX + threadIdx.x;
   if (x >= a.nx || z >= a.nz) return;
   const R* __restrict__ src = (const R*)a.src;

@@ -187,9 +187,9 @@ template <int BX, int BY, bool WALLS>
 __global__ __launch_bounds__(BX * BY) void k_step_d2q9_split(const RunArgs a, unsigned* __restrict__ overflow) {
   // phi, phi ux, phi uy of the tile and its one-node halo
   __shared__ float sphi[BY + 2][BX + 2], sjx[BY + 2][BX + 2], sjy[BY + 2][BX + 2];
-  const int64_t ntx = (a.nx + BX - 1) / BX;
-  const int64_t b = tile_of_block(blockIdx.x, gridDim.x, ntx, a.xcd_remap);
-  const int64_t tx0 = (b % ntx) * BX, ty0 = (b / ntx) * BY;
+  const uint32_t b = tile_of_block32(blockIdx.x, gridDim.x, a.tiles_x, a.xcd_remap);
+  const uint32_t tyi = fdiv(b, a.tiles_x);
+  const int64_t tx0 = (int64_t)(b - tyi * a.tiles_x.d) * BX, ty0 = (int64_t)tyi * BY;
   const float* __restrict__ phis = (const float*)a.src_phi;
   const int tid = threadIdx.y * BX + threadIdx.x;
   const bool px = a.bc[0] == LBM_CDE_PERIODIC, py = a.bc[1] == LBM_CDE_PERIODIC;
@@ -273,26 +273,29 @@ LBM_FORCEINLINE uint32_t mod3n(uint32_t x, uint32_t n) {
 // barrier, and the stored part comes straight out of the moment-space
 // collision, already scaled.  A separable u is multiplied in the same order
 // as velocity2, so both kernels give bitwise the same state.  NT: streaming
-// stores.
-template <int BX, int BY, bool NT>
+// stores.  UK: the velocity, 0 constant, 1 separable, 2 separable with unit
+// z factors (exactly 1, so the last product of velocity2's order is skipped).
+template <int BX, int BY, bool NT, int UK>
 __global__ __launch_bounds__(BX * BY) void k_step_d2q9_split_p(const RunArgs a, unsigned* __restrict__ overflow) {
   constexpr int NT_ = BX * BY, RN = 2 * (BX + 2) + 2 * BY;  // ring (halo) entries of the tile
   constexpr int NR = (RN + NT_ - 1) / NT_;                      // ring entries per thread
   // w phi, phi ux, phi uy of the tile and its halo
   __shared__ float swp[BY + 2][BX + 2], sjx[BY + 2][BX + 2], sjy[BY + 2][BX + 2];
   const uint32_t nx = (uint32_t)a.nx, ny = (uint32_t)a.ny;
-  const uint32_t ntx = (nx + BX - 1) / BX;
-  const uint32_t b = (uint32_t)tile_of_block(blockIdx.x, gridDim.x, ntx, a.xcd_remap);
-  const uint32_t tx0 = (b % ntx) * BX, ty0 = (b / ntx) * BY;
+  const uint32_t b = tile_of_block32(blockIdx.x, gridDim.x, a.tiles_x, a.xcd_remap);
+  const uint32_t tyi = fdiv(b, a.tiles_x);
+  const uint32_t tx0 = (b - tyi * a.tiles_x.d) * BX, ty0 = tyi * BY;
   const char* __restrict__ phis = (const char*)a.src_phi;
   const int tid = threadIdx.y * BX + threadIdx.x;
-  const bool sep = a.u_kind == U_SEPARABLE;
+  constexpr bool sep = UK != 0;
   const char* __restrict__ tb = (const char*)a.u_tab;
   const uint32_t tstride = (1u + nx + ny + 1u) * 4u;  // bytes per velocity component table
   const float ax0 = sep ? *(const float*)tb : 0.0f, ay0 = sep ? *(const float*)(tb + tstride) : 0.0f;
-  const float zx = sep ? *(const float*)(tb + (1u + nx + ny) * 4u) : 0.0f;
-  const float zy = sep ? *(const float*)(tb + tstride + (1u + nx + ny) * 4u) : 0.0f;
+  const float zx = UK == 1 ? *(const float*)(tb + (1u + nx + ny) * 4u) : 1.0f;
+  const float zy = UK == 1 ? *(const float*)(tb + tstride + (1u + nx + ny) * 4u) : 1.0f;
   const float cux = (float)a.u_const[0], cuy = (float)a.u_const[1];
+  // velocity2's product order; a unit z factor is exact and skipped
+  auto su = [&](float a0, float xv, float yv, float z) { return UK == 1 ? ((a0 * xv) * yv) * z : (a0 * xv) * yv; };
   // Loads in the order their results are needed, all issued before the first
   // wait: this thread's node (phi, velocity factors), one ring entry of the
   // tile's halo, then the nine stored halves (waited for after the barrier).
@@ -303,7 +306,7 @@ __global__ __launch_bounds__(BX * BY) void k_step_d2q9_split_p(const RunArgs a, 
   const uint32_t x = xr < nx ? xr : xr - nx, y = yr < ny ? yr : yr - ny;
   const float ph_own = *(const float*)(phis + (y * nx + x) * 4u);
   float ox = 0.0f, oy = 0.0f, px = 0.0f, py = 0.0f;
-  if (sep) {
+  if constexpr (sep) {
     ox = *(const float*)(tb + (1u + x) * 4u);
     oy = *(const float*)(tb + (1u + nx + y) * 4u);
     px = *(const float*)(tb + tstride + (1u + x) * 4u);
@@ -335,7 +338,7 @@ __global__ __launch_bounds__(BX * BY) void k_step_d2q9_split_p(const RunArgs a, 
     const uint32_t gx = mod3n(tx0 + (uint32_t)lx + nx - 1u, nx), gy = mod3n(ty0 + (uint32_t)ly + ny - 1u, ny);
     hphi[j] = *(const float*)(phis + (gy * nx + gx) * 4u);
     hx[j] = hy[j] = vx[j] = vy[j] = 0.0f;
-    if (sep) {
+    if constexpr (sep) {
       hx[j] = *(const float*)(tb + (1u + gx) * 4u);
       vx[j] = *(const float*)(tb + (1u + nx + gy) * 4u);
       hy[j] = *(const float*)(tb + tstride + (1u + gx) * 4u);
@@ -351,16 +354,16 @@ __global__ __launch_bounds__(BX * BY) void k_step_d2q9_split_p(const RunArgs a, 
 #pragma unroll
   for (int i = 0; i < 9; ++i) raw[i] = *(const __half*)(src + i * pb + off[i] * 2u);
   // w phi, phi ux, phi uy of the tile; u in velocity2's product order
-  const float ux = sep ? ((ax0 * ox) * oy) * zx : cux;
-  const float uy = sep ? ((ay0 * px) * py) * zy : cuy;
+  const float ux = sep ? su(ax0, ox, oy, zx) : cux;
+  const float uy = sep ? su(ay0, px, py, zy) : cuy;
   swp[threadIdx.y + 1][threadIdx.x + 1] = ph_own * kW1;
   sjx[threadIdx.y + 1][threadIdx.x + 1] = ph_own * ux;
   sjy[threadIdx.y + 1][threadIdx.x + 1] = ph_own * uy;
 #pragma unroll
   for (int j = 0; j < NR; ++j) {
     if (tid + j * NT_ < RN) {
-      const float hux = sep ? ((ax0 * hx[j]) * vx[j]) * zx : cux;
-      const float huy = sep ? ((ay0 * hy[j]) * vy[j]) * zy : cuy;
+      const float hux = sep ? su(ax0, hx[j], vx[j], zx) : cux;
+      const float huy = sep ? su(ay0, hy[j], vy[j], zy) : cuy;
       (&swp[0][0])[hl[j]] = hphi[j] * kW1;
       (&sjx[0][0])[hl[j]] = hphi[j] * hux;
       (&sjy[0][0])[hl[j]] = hphi[j] * huy;
@@ -414,9 +417,9 @@ __global__ __launch_bounds__(BX * BY) void k_step_d2q9_split_p(const RunArgs a, 
 // Literal half storage of the shifted populations, same step as FP32.
 template <int BX, bool WALLS>
 __global__ __launch_bounds__(BX) void k_step_d2q9_half(const RunArgs a, unsigned* __restrict__ overflow) {
-  const int64_t ntx = (a.nx + BX - 1) / BX;
-  const int64_t b = tile_of_block(blockIdx.x, gridDim.x, ntx, a.xcd_remap);
-  const int64_t x = (b % ntx) * BX + threadIdx.x, y = b / ntx;
+  const uint32_t b = tile_of_block32(blockIdx.x, gridDim.x, a.tiles_x, a.xcd_remap);
+  const uint32_t yq = fdiv(b, a.tiles_x);
+  const int64_t x = (int64_t)(b - yq * a.tiles_x.d) * BX + threadIdx.x, y = yq;
   if (x >= a.nx) return;
   const __half* __restrict__ src = (const __half*)a.src;
   const float inv = (float)a.fp16_inv_scale;

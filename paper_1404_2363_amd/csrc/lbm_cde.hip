@@ -84,6 +84,7 @@ struct Run {
   bool split = false;                  // ... with phi stored apart
   double fp16_scale = 1.0;
   char* utab = nullptr;
+  int32_t u_z_unit = 0;      // SEPARABLE 2D: every component's z factor is exactly 1
   char* ufield = nullptr;    // FP64 copy of the initial velocity field
   char* uslot = nullptr;     // device pointer to the field the steps read
   char* node_par = nullptr;
@@ -526,6 +527,7 @@ RunArgs make_args(const lbm_cde* h, const Run& r, int parity) {
   a.u_kind = r.d.u_kind;
   for (int i = 0; i < 3; ++i) a.u_const[i] = r.d.u_const[i];
   a.u_tab = r.utab;
+  a.u_z_unit = r.u_z_unit;
   a.u_slot = (const double* const*)r.uslot;
   a.u_flag = r.flags ? (unsigned*)&r.flags[2] : nullptr;
   a.node_par = r.node_par;
@@ -552,6 +554,12 @@ RunArgs make_args(const lbm_cde* h, const Run& r, int parity) {
   a.xref0 = r.d.xref0;
   a.xref_drift = r.d.xref_drift;
   a.xcd_remap = r.var.xcd;
+  // tile counts of the launch's block shape (16-bit runs: the split kernels
+  // tile BX x BY nodes; the literal kernel 256 x 1)
+  const int64_t tbx = r.half && !r.split ? 256 : r.var.bx;
+  const int64_t tby = r.half && !r.split ? 1 : (int64_t)r.var.by * (r.half ? 1 : r.var.ny);
+  a.tiles_x = make_fastdiv((uint32_t)((r.d.nx + tbx - 1) / tbx));
+  a.tiles_y = make_fastdiv((uint32_t)((r.d.ny + tby - 1) / tby));
   a.rows32 = r.d.lattice == LBM_CDE_D2Q9 && !r.half && r.d.bc[0] == LBM_CDE_PERIODIC && !r.node_par &&
              (double)r.plane * r.Q * r.elem < 4294967296.0 && r.d.nx < (1ll << 31) && r.d.ny < (1ll << 31) &&
              (r.d.u_kind != LBM_CDE_U_FIELD || 16.0 * (double)r.nodes < 4294967296.0);
@@ -660,9 +668,15 @@ bool split_fast_ok(const RunArgs& a, int bx, int by) {
 template <int BX, int BY, bool WALLS, bool NT>
 void launch_split(const RunArgs a, hipStream_t s) {
   const int64_t ntx = (a.nx + BX - 1) / BX, nty = (a.ny + BY - 1) / BY;
-  if (!WALLS && split_fast_ok(a, BX, BY))
-    hipLaunchKernelGGL((k_step_d2q9_split_p<BX, BY, NT>), dim3((unsigned)(ntx * nty)), dim3(BX, BY), 0, s, a,
-                       (unsigned*)a.fp16_flags);
+  if (!WALLS && split_fast_ok(a, BX, BY)) {
+    const dim3 g((unsigned)(ntx * nty)), b(BX, BY);
+    if (a.u_kind == U_CONST)
+      hipLaunchKernelGGL((k_step_d2q9_split_p<BX, BY, NT, 0>), g, b, 0, s, a, (unsigned*)a.fp16_flags);
+    else if (a.u_z_unit)
+      hipLaunchKernelGGL((k_step_d2q9_split_p<BX, BY, NT, 2>), g, b, 0, s, a, (unsigned*)a.fp16_flags);
+    else
+      hipLaunchKernelGGL((k_step_d2q9_split_p<BX, BY, NT, 1>), g, b, 0, s, a, (unsigned*)a.fp16_flags);
+  }
   else
     hipLaunchKernelGGL((k_step_d2q9_split<BX, BY, WALLS>), dim3((unsigned)(ntx * nty)), dim3(BX, BY), 0, s, a,
                        (unsigned*)a.fp16_flags);
@@ -1005,6 +1019,10 @@ int init_runs(lbm_cde* h, const lbm_cde_run_desc* runs, int32_t nruns, const dou
     hipStream_t s = h->stream;
     if (orig.u_kind == LBM_CDE_U_SEPARABLE) {
       const size_t n = (size_t)r.dim * (1 + orig.nx + orig.ny + orig.nz);
+      if (r.dim == 2) {
+        const size_t st = 1 + orig.nx + orig.ny + orig.nz;
+        r.u_z_unit = orig.u_tables[st - 1] == 1.0 && orig.u_tables[2 * st - 1] == 1.0;
+      }
       if (r.dbl) {
         HIP_TRY(nullptr, hipMemcpyAsync(r.utab, orig.u_tables, n * 8, hipMemcpyHostToDevice, s));
         HIP_TRY(nullptr, hipStreamSynchronize(s));  // the caller's table may go away after init
@@ -1353,12 +1371,13 @@ struct AdjBufs {
 template <typename R, bool WALLS, int GMODE, bool NT>
 void launch_adjoint_g(const RunArgs& a, unsigned blocks, unsigned bx, const AdjBufs& b, double inv_kappa,
                       hipStream_t s) {
+  const FastDiv ntx = make_fastdiv((uint32_t)((a.nx + bx - 1) / bx));
   if (b.inj)
     hipLaunchKernelGGL((k_adjoint_d2q9<R, WALLS, GMODE, true, NT>), dim3(blocks), dim3(bx), 0, s, a, (const R*)b.v,
-                       (const R*)b.mu_in, b.inj, (R*)b.mu_out, b.grad, b.part, inv_kappa);
+                       (const R*)b.mu_in, b.inj, (R*)b.mu_out, b.grad, b.part, inv_kappa, ntx);
   else
     hipLaunchKernelGGL((k_adjoint_d2q9<R, WALLS, GMODE, false, NT>), dim3(blocks), dim3(bx), 0, s, a, (const R*)b.v,
-                       (const R*)b.mu_in, b.inj, (R*)b.mu_out, b.grad, b.part, inv_kappa);
+                       (const R*)b.mu_in, b.inj, (R*)b.mu_out, b.grad, b.part, inv_kappa, ntx);
 }
 
 template <typename R, bool WALLS, bool NT>
@@ -1398,12 +1417,13 @@ void launch_adjoint(const lbm_cde* h, const Run& r, const RunArgs& a, const AdjB
 template <typename R>
 void launch_step_v(const Run& r, const RunArgs& a, void* v, bool store, hipStream_t s) {
   const unsigned blocks = (unsigned)((r.d.nx + 255) / 256 * r.d.ny);
+  const FastDiv ntx = make_fastdiv((uint32_t)((r.d.nx + 255) / 256));
   if (r.walls) {
-    if (store) hipLaunchKernelGGL((k_step_v_d2q9<R, true, true>), dim3(blocks), dim3(256), 0, s, a, (R*)v);
-    else hipLaunchKernelGGL((k_step_v_d2q9<R, true, false>), dim3(blocks), dim3(256), 0, s, a, (R*)v);
+    if (store) hipLaunchKernelGGL((k_step_v_d2q9<R, true, true>), dim3(blocks), dim3(256), 0, s, a, (R*)v, ntx);
+    else hipLaunchKernelGGL((k_step_v_d2q9<R, true, false>), dim3(blocks), dim3(256), 0, s, a, (R*)v, ntx);
   } else {
-    if (store) hipLaunchKernelGGL((k_step_v_d2q9<R, false, true>), dim3(blocks), dim3(256), 0, s, a, (R*)v);
-    else hipLaunchKernelGGL((k_step_v_d2q9<R, false, false>), dim3(blocks), dim3(256), 0, s, a, (R*)v);
+    if (store) hipLaunchKernelGGL((k_step_v_d2q9<R, false, true>), dim3(blocks), dim3(256), 0, s, a, (R*)v, ntx);
+    else hipLaunchKernelGGL((k_step_v_d2q9<R, false, false>), dim3(blocks), dim3(256), 0, s, a, (R*)v, ntx);
   }
 }
 
