@@ -599,6 +599,55 @@ def x_moments(phi: np.ndarray, x_ref: float):
     return (math.fsum(pbar.tolist()), math.fsum((d * pbar).tolist()), math.fsum((d * d * pbar).tolist()))
 
 
+def channel_step_symbol(prob: Problem, k: float) -> np.ndarray:
+    """One step of the oracle on the Fourier mode exp(i k x) of a channel.
+
+    ``prob`` is the problem of a channel periodic in x with three columns
+    (nx = 3, the walls and velocity profile of the channel across y; the
+    flow must not vary in x).  A population field v(i, y) exp(i k x) is
+    mapped by one step (Eq. 10-14, then Eq. 5 with the wall rule) to
+    (G v)(i, y) exp(i k x); G (shape (Q ny, Q ny), index i * ny + y) is built
+    from the oracle's own collision, applied to unit populations of the
+    middle column, and its own streaming table, whose x displacement of each
+    population gives the phase exp(-i k dx)."""
+    if prob.shape[0] != 3 or prob.walls[0] != "periodic" or prob.node_axes:
+        raise ValueError("a channel problem with nx = 3, periodic x and halfway walls is needed")
+    lat = prob.lat
+    Q, ny = lat.Q, prob.shape[1]
+    C = np.zeros((ny, Q, Q))
+    for j in range(Q):
+        f = np.zeros((Q, ny, 3))
+        f[j] = 1.0
+        C[:, :, j] = prob.collide(f)[:, :, 1].T
+    n = Q * ny
+    G = np.zeros((n, n), complex)
+    for i in range(Q):
+        pop, node = prob._dest[i]
+        for y in range(ny):
+            src = y * 3 + 1
+            d = int(node[src])
+            dx = d % 3 - 1
+            row = int(pop[src]) * ny + d // 3
+            G[row, np.arange(Q) * ny + y] += np.exp(-1j * k * dx) * C[y, i, :]
+    return G
+
+
+def channel_dispersion(prob: Problem, k: float = 1e-3):
+    """Asymptotic longitudinal dispersion coefficient and drift of the
+    scheme in a channel (Sec. 3.2, Eq. 46-47).  The cross-section sum of phi
+    of a mode exp(i k x) decays and travels with the eigenvalue lambda(k) of
+    ``channel_step_symbol`` nearest to 1, log lambda(k) = -i U k - K k^2 +
+    O(k^3), and the variance of a pulse grows at 2 K for long times (the
+    rate that Eq. 46-47 measure).  Returns (K, U), K from Richardson
+    extrapolation of -Re log lambda / k^2 at k and 2k."""
+    def at(kk):
+        ev = np.linalg.eigvals(channel_step_symbol(prob, kk))
+        lg = np.log(ev[np.argmax(ev.real)])
+        return -lg.real / kk ** 2, -lg.imag / kk
+    (K1, U1), (K2, U2) = at(k), at(2 * k)
+    return (4.0 * K1 - K2) / 3.0, (4.0 * U1 - U2) / 3.0
+
+
 def variance_from_moments(S0, S1, S2) -> float:
     """Eq. (47)."""
     return S2 / S0 - (S1 / S0) ** 2

@@ -6,6 +6,9 @@ from captured graphs); each run is compared with the FP64 oracle run alone,
 at its own budget.  The in-graph x-moment history is compared with the
 oracle's moments at the sampled times.
 """
+import json
+import os
+
 import numpy as np
 import pytest
 
@@ -109,15 +112,28 @@ def test_mixed_precisions_fall_back_to_separate_launches():
 
 
 def test_taylor_aris_ensemble_dispersion():
-    """The three cheapest channels of the seeded ensemble, run batched to
-    their own horizons: K / (D (1 + Pe^2/210)) - 1 within 1 %."""
+    """The three cheapest channels of the seeded ensemble and the two with
+    the largest Peclet numbers (whose horizon is set by the period, the
+    widest pulse then 8 sigma), run batched to their own horizons: the
+    fitted K within 1 % of D (1 + Pe^2/210) and within 0.3 % of the
+    scheme's own asymptotic K from the oracle's one-step symbol (stored in
+    golden/taylor_aris_spectral.json; the window of the fit and FP32
+    storage account for the rest)."""
     from paper_1404_2363_amd.taylor_aris import run_ensemble
-    runs = sorted(W.taylor_aris_batch(), key=lambda r: r.nodes * r.steps)[:3]
-    res, info = run_ensemble(runs, "fp32", every=100)
-    for r in res:
-        print(f"h={r['h']} Pe={r['Pe']:.1f} tau={r['tau']:.2f} steps={r['steps']}: K/K_TA - 1 = {r['rel_err']:.4%}",
-              flush=True)
+    golden = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "taylor_aris_spectral.json")))
+    ens = W.taylor_aris_batch()
+    cheap = sorted(range(len(ens)), key=lambda i: ens[i].nodes * ens[i].steps)[:3]
+    fast = sorted(range(len(ens)), key=lambda i: -golden["channels"][i]["Pe"])[:2]
+    pick = cheap + fast
+    print(f"case taylor_aris channels {pick}", flush=True)
+    res, info = run_ensemble([ens[i] for i in pick], "fp32", every=100)
+    for i, r in zip(pick, res):
+        g = golden["channels"][i]
+        dev = r["K"] / g["K_scheme"] - 1
+        print(f"h={r['h']} Pe={r['Pe']:.1f} tau={r['tau']:.3f} steps={r['steps']}: K/K_TA - 1 = {r['rel_err']:.4%}, "
+              f"K/K_scheme - 1 = {dev:.4%}", flush=True)
         assert abs(r["rel_err"]) <= 1e-2, r
+        assert abs(dev) <= 3e-3, (r, g)
     assert info["nonfinite"] == 0
 
 
