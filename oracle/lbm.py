@@ -599,37 +599,72 @@ def x_moments(phi: np.ndarray, x_ref: float):
     return (math.fsum(pbar.tolist()), math.fsum((d * pbar).tolist()), math.fsum((d * d * pbar).tolist()))
 
 
-def channel_step_symbol(prob: Problem, k: float) -> np.ndarray:
-    """One step of the oracle on the Fourier mode exp(i k x) of a channel.
-
-    ``prob`` is the problem of a channel periodic in x with three columns
-    (nx = 3, the walls and velocity profile of the channel across y; the
-    flow must not vary in x).  A population field v(i, y) exp(i k x) is
-    mapped by one step (Eq. 10-14, then Eq. 5 with the wall rule) to
-    (G v)(i, y) exp(i k x); G (shape (Q ny, Q ny), index i * ny + y) is built
-    from the oracle's own collision, applied to unit populations of the
-    middle column, and its own streaming table, whose x displacement of each
-    population gives the phase exp(-i k dx)."""
-    if prob.shape[0] != 3 or prob.walls[0] != "periodic" or prob.node_axes:
-        raise ValueError("a channel problem with nx = 3, periodic x and halfway walls is needed")
-    lat = prob.lat
-    Q, ny = lat.Q, prob.shape[1]
-    C = np.zeros((ny, Q, Q))
-    for j in range(Q):
-        f = np.zeros((Q, ny, 3))
-        f[j] = 1.0
-        C[:, :, j] = prob.collide(f)[:, :, 1].T
+def channel_transfer(prob: Problem) -> dict:
+    """The oracle's step (Eq. 10-14, then Eq. 5 with the wall rule) on a
+    channel that is periodic in x and uniform along it, split by x offset:
+    T[dx] (shape (Q ny, Q ny), index i * ny + y) maps the populations of one
+    column to their contribution dx columns further on.  ``prob`` has three
+    columns (nx = 3) holding the channel's cross-section (walls, velocity
+    profile, rates); unit populations are placed in the middle column and
+    stepped, and since a population moves at most one column per step the
+    three output columns are the three offsets."""
+    if prob.shape[0] != 3 or prob.walls[0] != "periodic" or prob.lat.dim != 2:
+        raise ValueError("a D2Q9 channel problem with nx = 3 and periodic x is needed")
+    Q, ny = prob.lat.Q, prob.shape[1]
     n = Q * ny
-    G = np.zeros((n, n), complex)
-    for i in range(Q):
-        pop, node = prob._dest[i]
+    T = {dx: np.zeros((n, n)) for dx in (-1, 0, 1)}
+    for j in range(Q):
         for y in range(ny):
-            src = y * 3 + 1
-            d = int(node[src])
-            dx = d % 3 - 1
-            row = int(pop[src]) * ny + d // 3
-            G[row, np.arange(Q) * ny + y] += np.exp(-1j * k * dx) * C[y, i, :]
-    return G
+            f = np.zeros((Q, ny, 3))
+            f[j, y, 1] = 1.0
+            g = prob.step(f)
+            for dx in (-1, 0, 1):
+                T[dx][:, j * ny + y] = g[:, :, 1 + dx].reshape(n)
+    return T
+
+
+def channel_step_symbol(prob: Problem, k: float) -> np.ndarray:
+    """One step of the oracle on the Fourier mode exp(i k x) of a channel:
+    a population field v(i, y) exp(i k x) becomes (G v)(i, y) exp(i k x)
+    with G = sum over dx of T[dx] exp(-i k dx) (``channel_transfer``)."""
+    T = channel_transfer(prob)
+    return sum(np.exp(-1j * k * dx) * T[dx] for dx in (-1, 0, 1))
+
+
+def channel_moment_history(prob: Problem, weights: np.ndarray, steps: int, every: int, drift: float = 0.0):
+    """Exact x-moments of a pulse released at one cross-section of an
+    unbounded channel (Sec. 3.2): the response to f(x, 0) = delta(x) e0(i, y)
+    with e0 the equilibrium of phi = 1 at the local velocity (Eq. 17).
+
+    With P_t, Q_t, R_t the population fields summed over x with weights
+    1, x - c t, (x - c t)^2 (c = ``drift``), one step maps
+        P -> sum T[dx] P,
+        Q -> sum T[dx] (Q + (dx - c) P),
+        R -> sum T[dx] (R + 2 (dx - c) Q + (dx - c)^2 P)
+    (``channel_transfer``), and S_m = sum over i, y of weights[y] times the
+    field.  A pulse of any x-profile that is uniform across the gap has
+    these cumulants plus its own, so variance increments (Eq. 46-47) do not
+    depend on it.  Returns (t, S0, S1, S2) sampled every ``every`` steps."""
+    T = channel_transfer(prob)
+    Q, ny = prob.lat.Q, prob.shape[1]
+    phi1 = np.ones((ny, 3))
+    e0 = prob.equilibrium(phi1)[:, :, 1].reshape(Q * ny)
+    wv = np.tile(np.asarray(weights, np.float64), Q)
+    P, Qm, R = e0.copy(), np.zeros_like(e0), np.zeros_like(e0)
+    ts, out = [], []
+    for t in range(1, steps + 1):
+        nP, nQ, nR = np.zeros_like(P), np.zeros_like(P), np.zeros_like(P)
+        for dx in (-1, 0, 1):
+            a = dx - drift
+            nP += T[dx] @ P
+            nQ += T[dx] @ (Qm + a * P)
+            nR += T[dx] @ (R + 2.0 * a * Qm + a * a * P)
+        P, Qm, R = nP, nQ, nR
+        if t % every == 0:
+            ts.append(t)
+            out.append((wv @ P, wv @ Qm, wv @ R))
+    out = np.array(out)
+    return np.array(ts), out[:, 0], out[:, 1], out[:, 2]
 
 
 def channel_dispersion(prob: Problem, k: float = 1e-3):

@@ -9,7 +9,8 @@ has decayed below 1e-9 by step 1000 on a 416-node channel (the asymptotic
 value does not depend on the channel length while the pulse fits in it).
 The unmodified models MRT-B1/B2/B3 reproduce the printed values to within
 1 % of Er (they agree to 0.6 %); MRT-A does not (its printed value is 0.76
-of the oracle's; the difference is recorded, not asserted).
+of the oracle's; test_oracle_mrt_a_tables.py tries every silent point and
+finds the printed column consistent with a different s2 only).
 """
 import json
 import os
