@@ -36,24 +36,18 @@ BYTES_PER_LU = {("d2q9", "fp64"): 144, ("d2q9", "fp32"): 72, ("d2q9", "fp16"): 4
 COPY_PROBE_BYTES = 1 << 30     # bytes read (and written) by one calibration copy
 
 
-def kernel_tag(name, launch):
-    """Name of the step kernel a launch variant runs, as rocprofv3 prints it,
-    plus the block order (a kernel argument, not part of the name)."""
+def kernel_tag(launch):
+    """Key of a launch variant in the committed counter profile: tile shape,
+    rows per thread, streaming stores, block order (and the persistent grid
+    of a batched launch)."""
     bx, by = launch["block"]
-    nt = "true" if launch["nt_stores"] else "false"
-    if name.startswith("d2q9") and name.endswith("fp16"):
-        kern = f"lbm::k_step_d2q9_split_p<{bx}, {by}, {nt}>"
-    elif name.startswith("d2q9"):
-        kern = f"lbm::k_step_d2q9<float, {bx}, {by}, {launch['rows_per_thread']}, false, {nt}>"
-    else:
-        kern = f"lbm::k_step_d3q15<float, {bx}, {by}, {launch['rows_per_thread']}, false, {nt}>"
-    return f"{kern}|order{launch['block_order']}"
+    tag = f"{bx}x{by}x{launch['rows_per_thread']}x{int(bool(launch['nt_stores']))}|order{launch['block_order']}"
+    return tag + (f"|grid{launch['grid']}" if launch.get("grid") else "")
 
 
-def profiled_traffic(name, launch):
-    """HBM bytes per launch from the committed PMC profile of this kernel and
-    launch variant, or None when the kernel source or the variant differs from
-    what the counters were taken on."""
+def _profile(name):
+    """The committed PMC record of a workload, or None when its kernel
+    sources differ from what the counters were taken on."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "traffic.json")
     try:
@@ -63,10 +57,32 @@ def profiled_traffic(name, launch):
     h = hashlib.sha256()
     for f in rec["source_files"]:
         h.update(open(os.path.join(ROOT, "paper_1404_2363_amd", "csrc", f), "rb").read())
-    if h.hexdigest()[:16] != rec["source_sha"]:
-        return None
-    k = rec["kernels"].get(kernel_tag(name, launch))
+    return rec if h.hexdigest()[:16] == rec["source_sha"] else None
+
+
+def profiled_traffic(name, launch):
+    """HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, calibrated on a 1 GiB
+    copy) from the committed PMC profile of this kernel and launch variant,
+    or None when the kernel source or the variant differs from what the
+    counters were taken on."""
+    rec = _profile(name)
+    k = None if rec is None else rec["kernels"].get(kernel_tag(launch))
     return None if k is None else k["traffic_bytes_per_launch"]
+
+
+def profiled_segment_traffic(K):
+    """HBM bytes of one adjoint checkpoint segment of K steps from the
+    per-kernel counters: K - 1 recomputed steps that store their state, one
+    that does not, and the first, K - 2 middle and last reverse steps."""
+    rec = _profile("adjoint_segment_2048_fp32")
+    if rec is None:
+        return None
+    t = {k: v["traffic_bytes_per_launch"] for k, v in rec["kernels"].items()}
+    need = ("forward_v", "forward_v_last", "reverse_first", "reverse", "reverse_last")
+    if any(n not in t for n in need):
+        return None
+    return ((K - 1) * t["forward_v"] + t["forward_v_last"] + t["reverse_first"] + (K - 2) * t["reverse"]
+            + t["reverse_last"])
 
 
 def log(msg):
@@ -391,6 +407,8 @@ def main():
         k = args.steps
         log(f"taylor_aris_batch: {len(runs)} channels, {k} steps")
         out["taylor_aris_batch_fp32"] = batch_variant(runs, "fp32", k, args.warmup, tune)
+        out["taylor_aris_batch_fp32"]["traffic"] = profiled_traffic("taylor_aris_batch_fp32",
+                                                                    out["taylor_aris_batch_fp32"]["launch"])
         log(f"taylor_aris_batch: {out['taylor_aris_batch_fp32']['mlups']:.0f} MLUPS")
     if (not args.only and not args.quick) or args.only == "unsteady":
         k = args.steps
@@ -400,6 +418,8 @@ def main():
     if (not args.only and not args.quick) or args.only == "adjoint":
         log("adjoint: one 2048^2 checkpoint segment of 16 steps (forward recompute + reverse)")
         out["adjoint_segment_2048_fp32"] = adjoint_segment_variant()
+        seg = out["adjoint_segment_2048_fp32"]
+        seg["traffic"] = profiled_segment_traffic(seg["segment_steps"])
         log(f"adjoint segment: {out['adjoint_segment_2048_fp32']['achieved_gbs']:.0f} GB/s")
         log("adjoint: one 512^2 x 2000-step gradient")
         out["inverse_adjoint_fp32"] = adjoint_variant("fp32")
