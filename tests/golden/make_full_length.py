@@ -1,0 +1,64 @@
+"""Writes full_length.json: phi of the FP64 reference after the full length of
+the two large workloads, at seeded sample nodes, with sum phi before and after.
+
+* D2Q9 4096^2 cellular flow (rotated anisotropic D), 5000 steps;
+* D3Q15 256^3 sinusoidal flow (random anisotropic D), 2000 steps.
+
+The initial populations are the Python oracle's equilibrium of phi0 and u;
+the run is the C reference (oracle/lbm_ref.c, pinned to the Python oracle in
+tests/test_oracle_ref.py).  Uses only the oracle and the seeded workloads.
+About 20 min (2D) and 40 min (3D) on 8 host cores.
+
+    OMP_NUM_THREADS=8 python tests/golden/make_full_length.py [d2q9|d3q15]
+"""
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+sys.path.insert(0, ROOT)
+
+from oracle import lbm as O                                   # noqa: E402
+from oracle import ref as R                                   # noqa: E402
+from paper_1404_2363_amd import workloads as W                # noqa: E402
+
+OUT = os.path.join(os.path.dirname(os.path.abspath(__file__)), "full_length.json")
+SAMPLES = 4096
+CASES = {"d2q9": (lambda: W.cellular(), 11), "d3q15": (lambda: W.sine3d(), 12)}
+
+
+def one(case):
+    make, seed = CASES[case]
+    wl = make()
+    t0 = time.time()
+    prob = O.problem_for(wl)
+    f0 = prob.equilibrium(wl.phi0())
+    print(f"{case}: {wl.shape} x {wl.steps} steps, set-up {time.time() - t0:.0f} s", flush=True)
+    t0 = time.time()
+    f = R.run(prob, f0, wl.steps)
+    print(f"{case}: reference run {time.time() - t0:.0f} s", flush=True)
+    phi = f.sum(0).ravel()
+    rng = np.random.default_rng([14042363, 900 + seed])
+    nodes = np.sort(rng.choice(phi.size, SAMPLES, replace=False))
+    return {"workload": wl.name, "lattice": wl.lattice, "shape": list(wl.shape), "steps": int(wl.steps),
+            "heat_rule": "lambda_min", "nodes": nodes.tolist(), "phi": [float(v) for v in phi[nodes]],
+            "sum_phi0": float(f0.sum()), "sum_phi": float(phi.sum()), "max_abs_phi": float(np.abs(phi).max())}
+
+
+def main():
+    cases = sys.argv[1:] or list(CASES)
+    data = json.load(open(OUT)) if os.path.exists(OUT) else {}
+    data["source"] = ("C reference oracle/lbm_ref.c (FP64) from the oracle's equilibrium of phi0; "
+                      "seeded workloads paper_1404_2363_amd.workloads.cellular() and sine3d()")
+    for c in cases:
+        data[c] = one(c)
+        with open(OUT, "w") as fh:
+            json.dump(data, fh)
+        print(f"wrote {OUT} [{c}]", flush=True)
+
+
+if __name__ == "__main__":
+    main()

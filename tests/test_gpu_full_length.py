@@ -1,10 +1,14 @@
 """The precision forms over the full length of the large workloads.
 
-The oracle cannot run 5000 steps of a 4096^2 grid (8e10 updates) in a test,
-and a sampled node then depends on the whole grid, so at full length the
-reduced-precision steps are compared with the FP64 GPU step, which equals the
-oracle to 1e-12 on the same kernels (full size over 40 steps node by node,
-smaller grids over full runs; test_gpu_d2q9.py, test_gpu_d3q15.py):
+Against the FP64 reference: the C reference (oracle/lbm_ref.c, pinned to the
+Python oracle) ran both workloads to their full length on the host and
+stored phi at 4096 seeded nodes (golden/full_length.json, written by
+golden/make_full_length.py).  Each precision, in the tuned launch variant,
+must match those values within its tolerance (1e-12, 1e-5, 1e-3 of max |phi|)
+and the reference's sum phi.
+
+Over the whole field, the reduced-precision steps are also compared with the
+FP64 GPU step:
 
 * D2Q9 4096^2 cellular flow, 5000 steps: FP32 shifted within 1e-5 and FP16
   split within 1e-3 of max |phi| (the stated tolerances); the literal FP16
@@ -13,6 +17,9 @@ smaller grids over full runs; test_gpu_d2q9.py, test_gpu_d3q15.py):
 * D3Q15 256^3 sine flow, 2000 steps: FP32 shifted within 1e-5; sum phi
   conserved.
 """
+import json
+import os
+
 import numpy as np
 import pytest
 
@@ -65,3 +72,29 @@ def test_d3q15_256_full_length_fp32():
     print(f"fp32: max |dphi| / max |phi| = {err:.3e}, mass drift {abs(b - a) / a:.2e}", flush=True)
     assert err <= 1e-5
     assert abs(b - a) <= 1e-6 * a
+
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "full_length.json")
+
+
+@pytest.mark.parametrize("case,precision,tol", [
+    ("d2q9", "fp64", 1e-12), ("d2q9", "fp32", 1e-5), ("d2q9", "fp16", 1e-3)])
+def test_full_length_against_fp64_reference(case, precision, tol):
+    from paper_1404_2363_amd.solver import Solver
+    gold = json.load(open(GOLDEN))[case]
+    wl = W.cellular() if case == "d2q9" else W.sine3d()
+    assert list(wl.shape) == gold["shape"] and wl.steps == gold["steps"]
+    s = Solver(wl, precision)
+    s.tune()
+    print(f"case {case} {wl.shape} x {wl.steps} {precision}, tuned variant {s.variant()}", flush=True)
+    s.step(wl.steps)
+    phi = s.phi().cpu().numpy().ravel()
+    mass = s.mass()
+    assert s.nonfinite() == 0
+    s.close()
+    nodes = np.asarray(gold["nodes"])
+    err = float(np.abs(phi[nodes] - np.asarray(gold["phi"])).max() / gold["max_abs_phi"])
+    dm = abs(mass - gold["sum_phi"]) / gold["sum_phi0"]
+    print(f"max |dphi| / max |phi| at {nodes.size} nodes = {err:.3e}; sum phi vs reference {dm:.2e}", flush=True)
+    assert err <= tol
+    assert dm <= {"fp64": 1e-12, "fp32": 1e-6, "fp16": 1e-6}[precision]
