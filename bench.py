@@ -334,31 +334,35 @@ def host_description():
     return ncpu, model
 
 
-def cpu_baseline(wl, steps=4):
-    """The FP64 oracle as it stands on the same grid, timed twice: with one
-    BLAS thread and with one BLAS thread per available CPU (the oracle's
-    dense 9 x 9 transforms run in BLAS; its streaming is single-threaded
-    numpy, so extra threads help only the transforms)."""
+def cpu_baseline(wl, steps_all=10, steps_one=2):
+    """The oracle's FP64 step on the same 4096^2 grid on the host: the C
+    reference of the oracle (oracle/lbm_ref.c, plain C with OpenMP over rows,
+    pinned to the numpy oracle), timed with one thread and with every
+    available one (the box's share: OMP_NUM_THREADS when set), after one
+    untimed step that touches both buffers."""
     from oracle import lbm as O
-    from threadpoolctl import threadpool_limits
+    from oracle import ref as R
     ncpu, model = host_description()
+    nall = max(1, min(ncpu, int(os.environ.get("OMP_NUM_THREADS", ncpu))))
+    t0 = time.perf_counter()
     prob = O.problem_for(wl)
-    f0 = prob.equilibrium(wl.phi0())
+    run = R.Run(prob, prob.equilibrium(wl.phi0()))
+    run.advance(1, nall)
+    log(f"cpu baseline: set-up {time.perf_counter() - t0:.1f} s")
     res = {}
-    for threads in (1, ncpu):
-        with threadpool_limits(threads):
-            f = f0
-            t0 = time.perf_counter()
-            for _ in range(steps):
-                f = prob.step(f)
-            res[threads] = time.perf_counter() - t0
-        log(f"cpu baseline: {steps} oracle steps with {threads} BLAS thread(s): {res[threads]:.1f} s")
-    best = min(res, key=lambda k: res[k])
-    return {"value": wl.nodes * steps / res[best] / 1e6, "unit": "MLUPS", "cores": best, "kind": "oracle",
-            "sample": f"{steps} FP64 oracle steps (numpy) of the full {wl.shape[0]}x{wl.shape[1]} D2Q9 grid, "
-                      f"{res[best]:.1f} s with {best} BLAS thread(s)",
-            "host": {"cpus_available": ncpu, "cpu_model": model},
-            "by_threads": {str(k): {"mlups": wl.nodes * steps / v / 1e6, "seconds": v} for k, v in res.items()}}
+    for threads, steps in ((1, steps_one), (nall, steps_all)):
+        t0 = time.perf_counter()
+        run.advance(steps, threads)
+        res[threads] = (steps, time.perf_counter() - t0)
+        log(f"cpu baseline: {steps} reference steps with {threads} thread(s): {res[threads][1]:.1f} s")
+    best = max(res, key=lambda k: res[k][0] / res[k][1])
+    steps, secs = res[best]
+    return {"value": wl.nodes * steps / secs / 1e6, "unit": "MLUPS", "cores": best, "kind": "oracle",
+            "sample": f"{steps} FP64 steps of the full {wl.shape[0]}x{wl.shape[1]} D2Q9 grid with the oracle's C "
+                      f"reference (OpenMP over rows), {secs:.1f} s on {best} thread(s)",
+            "host": {"cpus_available": ncpu, "threads_all": nall, "cpu_model": model},
+            "by_threads": {str(k): {"mlups": wl.nodes * v[0] / v[1] / 1e6, "steps": v[0], "seconds": v[1]}
+                           for k, v in res.items()}}
 
 
 def main():

@@ -399,8 +399,12 @@ class Problem:
             node += dest_c[a] * stride
             stride *= self.shape[a]
         vel = np.stack(vel, -1)
-        table = {tuple(self.lat.e[j, :dim]): j for j in range(self.lat.Q)}
-        pop = np.vectorize(lambda *v: table[v])(*[vel[..., a] for a in range(dim)]) if vel.size else vel
+        # population index of each velocity vector: a table over the 3^dim
+        # vectors with components in {-1, 0, 1}, indexed by sum_a (v_a + 1) 3^a
+        code = lambda v: sum((np.asarray(v[..., a]) + 1) * 3 ** a for a in range(dim))
+        table = np.full(3 ** dim, -1, dtype=np.int64)
+        table[code(self.lat.e[:, :dim])] = np.arange(self.lat.Q)
+        pop = table[code(vel)]
         pop = np.where(crossed["node"], -1, pop)
         return np.asarray(pop, dtype=np.int64).ravel(), node.ravel()
 

@@ -24,9 +24,9 @@
 #include <string.h>
 
 static void one_step(int Q, int dim, int64_t nx, int64_t ny, int64_t nz, const int* e, const double* Cm,
-                     const double* b, const double* u, const double* src, double* dst) {
+                     const double* b, const double* u, const double* src, double* dst, int threads) {
   const int64_t N = nx * ny * nz;
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) num_threads(threads)
   for (int64_t row = 0; row < ny * nz; ++row) {
     const int64_t y = row % ny, z = row / ny;
     double fi[15], fo[15];
@@ -55,20 +55,20 @@ static void one_step(int Q, int dim, int64_t nx, int64_t ny, int64_t nz, const i
   }
 }
 
-/* Advance f (Q x N, updated in place) by `steps` steps; g is scratch of the
- * same size.  shape = (nx, ny, nz) (nz = 1 in 2D).  Returns 0, or -1 for
- * arguments outside what is built (Q > 15, a velocity component outside
- * {-1, 0, 1}, an axis shorter than 1). */
+/* Advance f (Q x N, updated in place) by `steps` steps on `threads` OpenMP
+ * threads; g is scratch of the same size.  shape = (nx, ny, nz) (nz = 1 in
+ * 2D).  Returns 0, or -1 for arguments outside what is built (Q > 15, a
+ * velocity component outside {-1, 0, 1}, an axis shorter than 1, threads < 1). */
 int lbm_ref_run(int Q, int dim, const int64_t* shape, const int* e, const double* Cm, const double* b,
-                const double* u, double* f, double* g, int64_t steps) {
+                const double* u, double* f, double* g, int64_t steps, int threads) {
   const int64_t nx = shape[0], ny = shape[1], nz = shape[2];
-  if (Q < 1 || Q > 15 || dim < 1 || dim > 3 || nx < 1 || ny < 1 || nz < 1 || steps < 0) return -1;
+  if (Q < 1 || Q > 15 || dim < 1 || dim > 3 || nx < 1 || ny < 1 || nz < 1 || steps < 0 || threads < 1) return -1;
   for (int k = 0; k < 3 * Q; ++k)
     if (e[k] < -1 || e[k] > 1) return -1;
   double* src = f;
   double* dst = g;
   for (int64_t t = 0; t < steps; ++t) {
-    one_step(Q, dim, nx, ny, nz, e, Cm, b, u, src, dst);
+    one_step(Q, dim, nx, ny, nz, e, Cm, b, u, src, dst, threads);
     double* tmp = src;
     src = dst;
     dst = tmp;

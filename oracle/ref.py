@@ -35,7 +35,7 @@ def _lib():
     lib = ctypes.CDLL(build())
     lib.lbm_ref_run.restype = ctypes.c_int
     p = ctypes.c_void_p
-    lib.lbm_ref_run.argtypes = [ctypes.c_int, ctypes.c_int, p, p, p, p, p, p, p, ctypes.c_int64]
+    lib.lbm_ref_run.argtypes = [ctypes.c_int, ctypes.c_int, p, p, p, p, p, p, p, ctypes.c_int64, ctypes.c_int]
     return lib
 
 
@@ -60,20 +60,38 @@ def collision_form(prob: O.Problem):
     return np.ascontiguousarray(Cm), np.ascontiguousarray(np.stack(b))
 
 
-def run(prob: O.Problem, f: np.ndarray, steps: int) -> np.ndarray:
+class Run:
+    """Populations of a periodic problem held for the C reference; advance()
+    steps them in place, .f holds them (Q, *grid)."""
+
+    def __init__(self, prob: O.Problem, f: np.ndarray):
+        if any(w != "periodic" for w in prob.walls):
+            raise ValueError("the C reference is periodic on every axis")
+        lat = prob.lat
+        self.Q, self.dim = lat.Q, lat.dim
+        self.Cm, self.b = collision_form(prob)
+        grid = f.shape[1:]
+        self.shape = np.array(list(reversed(grid)) + [1] * (3 - len(grid)), dtype=np.int64)
+        self.e = np.ascontiguousarray(lat.e[:, :3].astype(np.int32))
+        self.u = np.ascontiguousarray(np.broadcast_to(prob.u, (lat.dim,) + grid), dtype=np.float64)
+        self.f = np.ascontiguousarray(f, dtype=np.float64).copy()
+        self.g = np.zeros_like(self.f)
+        self.lib = _lib()
+
+    def advance(self, steps: int, threads: int = 0):
+        """`steps` steps on `threads` OpenMP threads (0: the OpenMP default)."""
+        ptr = lambda a: a.ctypes.data_as(ctypes.c_void_p)
+        n = threads if threads > 0 else (os.cpu_count() or 1)
+        if "OMP_NUM_THREADS" in os.environ and threads <= 0:
+            n = int(os.environ["OMP_NUM_THREADS"])
+        rc = self.lib.lbm_ref_run(self.Q, self.dim, ptr(self.shape), ptr(self.e), ptr(self.Cm), ptr(self.b),
+                                  ptr(self.u), ptr(self.f), ptr(self.g), steps, n)
+        if rc != 0:
+            raise ValueError("lbm_ref_run rejected its arguments")
+
+
+def run(prob: O.Problem, f: np.ndarray, steps: int, threads: int = 0) -> np.ndarray:
     """Advance populations f (shape (Q, *grid), FP64) by `steps` periodic steps."""
-    if any(w != "periodic" for w in prob.walls):
-        raise ValueError("the C reference is periodic on every axis")
-    lat = prob.lat
-    Cm, b = collision_form(prob)
-    grid = f.shape[1:]
-    shape = np.array(list(reversed(grid)) + [1] * (3 - len(grid)), dtype=np.int64)
-    e = np.ascontiguousarray(lat.e[:, :3].astype(np.int32))
-    u = np.ascontiguousarray(np.broadcast_to(prob.u, (lat.dim,) + grid), dtype=np.float64)
-    fa = np.ascontiguousarray(f, dtype=np.float64).copy()
-    g = np.empty_like(fa)
-    ptr = lambda a: a.ctypes.data_as(ctypes.c_void_p)
-    rc = _lib().lbm_ref_run(lat.Q, lat.dim, ptr(shape), ptr(e), ptr(Cm), ptr(b), ptr(u), ptr(fa), ptr(g), steps)
-    if rc != 0:
-        raise ValueError("lbm_ref_run rejected its arguments")
-    return fa
+    r = Run(prob, f)
+    r.advance(steps, threads)
+    return r.f
