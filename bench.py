@@ -334,7 +334,7 @@ def host_description():
     return ncpu, model
 
 
-def cpu_baseline(wl, steps_all=10, steps_one=2):
+def cpu_baseline(wl, steps_all=40, steps_one=6):
     """The oracle's FP64 step on the same 4096^2 grid on the host: the C
     reference of the oracle (oracle/lbm_ref.c, plain C with OpenMP over rows,
     pinned to the numpy oracle), timed with one thread and with every
