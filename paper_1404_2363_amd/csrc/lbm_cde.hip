@@ -125,8 +125,10 @@ struct lbm_cde {
   Variant batch_var{256, 1, 1, true, 0, 0};  // row-tile width, stores and grid of the batched launch
   int64_t batch_tiles = 0;           // tiles of the flat list at batch_var.bx
   unsigned batch_grid = 0;
-  hipGraphExec_t batch_graph = nullptr;
-  hipGraphExec_t sample_graph = nullptr;
+  // captured batched steps (and sampled blocks) per launch grid: late in an
+  // ensemble the grid shrinks with the active prefix of the tile list
+  std::map<unsigned, hipGraphExec_t> batch_graphs, sample_graphs;
+  std::vector<int64_t> batch_prefix;  // tile-list prefix, in batch order (host copy)
   int64_t sample_every = 0;
   double* sample_hist = nullptr;
   bool env_variant = false;   // LBM_CDE_TILE / _NT / _XCD override every run
@@ -745,11 +747,10 @@ void drop_graphs(lbm_cde* h) {
       (void)hipGraphExecDestroy(g);
       g = nullptr;
     }
-  for (hipGraphExec_t* g : {&h->batch_graph, &h->sample_graph})
-    if (*g) {
-      (void)hipGraphExecDestroy(*g);
-      *g = nullptr;
-    }
+  for (auto* m : {&h->batch_graphs, &h->sample_graphs}) {
+    for (auto& kv : *m) (void)hipGraphExecDestroy(kv.second);
+    m->clear();
+  }
 }
 
 // Capture kGraphSteps steps starting from parity p on the private stream.
@@ -880,19 +881,19 @@ int choose_fp16_scale(Run& r, lbm_cde* h, const double* phi0, hipStream_t s) {
 }
 
 // Batched launch variants (row-tile width, streaming stores) compiled into the library.
-using BatchFn = void (*)(const lbm_cde*, hipStream_t);
+using BatchFn = void (*)(const lbm_cde*, hipStream_t, unsigned);
 struct BatchEntry {
   int bx;
   bool nt;
   BatchFn fn[2];  // [double?]
 };
 template <typename R, int BX, bool NT>
-void launch_batch(const lbm_cde* h, hipStream_t s) {
+void launch_batch(const lbm_cde* h, hipStream_t s, unsigned grid) {
   if (h->batch_lean)
-    hipLaunchKernelGGL((k_batch_rows_d2q9<R, BX, NT>), dim3(h->batch_grid), dim3(BX), 0, s, h->dev_brun,
-                       h->dev_tiles32, (int)h->runs.size(), h->dev_clock);
+    hipLaunchKernelGGL((k_batch_rows_d2q9<R, BX, NT>), dim3(grid), dim3(BX), 0, s, h->dev_brun, h->dev_tiles32,
+                       (int)h->runs.size(), h->dev_clock);
   else
-    hipLaunchKernelGGL((k_batch_d2q9<R, BX, NT>), dim3(h->batch_grid), dim3(BX), 0, s, h->dev_runs, h->dev_tiles,
+    hipLaunchKernelGGL((k_batch_d2q9<R, BX, NT>), dim3(grid), dim3(BX), 0, s, h->dev_runs, h->dev_tiles,
                        h->dev_order, (int)h->runs.size(), h->dev_clock);
 }
 #define BATCH_ENTRY(BX, NT) \
@@ -986,6 +987,7 @@ int apply_batch_variant(lbm_cde* h, const Variant& v, std::vector<int64_t>* tile
   h->batch_var = v;
   h->batch_tiles = tiles.back();
   h->batch_grid = (unsigned)(v.grid > 0 ? std::min<int64_t>(v.grid, tiles.back()) : tiles.back());
+  h->batch_prefix = tiles;
   if (tiles_out) *tiles_out = tiles;
   return LBM_CDE_OK;
 }
@@ -1130,9 +1132,28 @@ int init_runs(lbm_cde* h, const lbm_cde_run_desc* runs, int32_t nruns, const dou
   return LBM_CDE_OK;
 }
 
+// Launch grid for steps from global step t on: the variant's grid, but no
+// more blocks than the tiles of the runs still active at t (the runs are
+// listed by decreasing budget, so they own a prefix of the tile list; the
+// count only falls as t grows), rounded up to a power of two so that few
+// distinct graphs are captured.  The kernel finds the active prefix itself
+// every step, so any grid of at least one block is correct; this only keeps
+// the finished runs' tiles from costing blocks that exit at once.
+unsigned batch_grid_at(const lbm_cde* h, int64_t t) {
+  int64_t active = 0;
+  for (size_t k = 0; k < h->batch_order.size(); ++k) {
+    const int64_t ms = h->runs[h->batch_order[k]].d.max_steps;
+    if (ms >= 0 && t >= ms) break;
+    active = h->batch_prefix[k + 1];
+  }
+  unsigned g = 64;
+  while ((int64_t)g < active && g < h->batch_grid) g *= 2;
+  return std::min(g, h->batch_grid);
+}
+
 // One batched step: the persistent kernel, then the clock tick.
-void launch_batch_step(lbm_cde* h, hipStream_t s) {
-  find_batch(h->batch_var)->fn[h->runs[0].dbl ? 1 : 0](h, s);
+void launch_batch_step(lbm_cde* h, hipStream_t s, unsigned grid) {
+  find_batch(h->batch_var)->fn[h->runs[0].dbl ? 1 : 0](h, s, grid);
   hipLaunchKernelGGL(k_tick, dim3(1), dim3(64), 0, s, h->dev_clock, 0);
 }
 
@@ -1151,10 +1172,11 @@ void launch_batch_sample(lbm_cde* h, hipStream_t s, double* hist) {
   hipLaunchKernelGGL(k_tick, dim3(1), dim3(64), 0, s, h->dev_clock, 1);
 }
 
-// Capture `steps` batched steps (and, with hist, one sample) as a graph.
-int capture_batch(lbm_cde* h, int64_t steps, double* hist, hipGraphExec_t* out) {
+// Capture `steps` batched steps of the given grid (and, with hist, one
+// sample) as a graph.
+int capture_batch(lbm_cde* h, int64_t steps, double* hist, unsigned grid, hipGraphExec_t* out) {
   HIP_TRY(h, hipStreamBeginCapture(h->capture, hipStreamCaptureModeThreadLocal));
-  for (int64_t t = 0; t < steps; ++t) launch_batch_step(h, h->capture);
+  for (int64_t t = 0; t < steps; ++t) launch_batch_step(h, h->capture, grid);
   if (hist) launch_batch_sample(h, h->capture, hist);
   hipGraph_t g = nullptr;
   hipError_t e = hipStreamEndCapture(h->capture, &g);
@@ -1174,16 +1196,21 @@ void advance_host_clock(lbm_cde* h, int64_t n) {
 int batch_step(lbm_cde* h, int64_t n) {
   int64_t done = 0;
   while (done < n) {
+    const unsigned grid = batch_grid_at(h, h->global_steps);
     if (n - done >= kGraphSteps) {
-      if (!h->batch_graph) {
-        const int rc = capture_batch(h, kGraphSteps, nullptr, &h->batch_graph);
-        if (rc) return rc;
+      hipGraphExec_t& g = h->batch_graphs[grid];
+      if (!g) {
+        const int rc = capture_batch(h, kGraphSteps, nullptr, grid, &g);
+        if (rc) {
+          h->batch_graphs.erase(grid);
+          return rc;
+        }
       }
-      HIP_TRY(h, hipGraphLaunch(h->batch_graph, h->stream));
+      HIP_TRY(h, hipGraphLaunch(g, h->stream));
       advance_host_clock(h, kGraphSteps);
       done += kGraphSteps;
     } else {
-      launch_batch_step(h, h->stream);
+      launch_batch_step(h, h->stream, grid);
       HIP_TRY(h, hipGetLastError());
       advance_host_clock(h, 1);
       done += 1;
@@ -1268,9 +1295,9 @@ int time_batch(lbm_cde* h, int trials, double* ms) {
   hipEvent_t e0, e1;
   HIP_TRY(h, hipEventCreate(&e0));
   HIP_TRY(h, hipEventCreate(&e1));
-  fn(h, h->stream);  // warm-up
+  fn(h, h->stream, h->batch_grid);  // warm-up
   HIP_TRY(h, hipEventRecord(e0, h->stream));
-  for (int t = 0; t < trials; ++t) fn(h, h->stream);
+  for (int t = 0; t < trials; ++t) fn(h, h->stream, h->batch_grid);
   HIP_TRY(h, hipEventRecord(e1, h->stream));
   HIP_TRY(h, hipEventSynchronize(e1));
   float elapsed = 0.f;
@@ -1602,16 +1629,23 @@ int lbm_cde_run_sampled(lbm_cde_handle h, int64_t n, int64_t every, double* hist
     return fail(h, LBM_CDE_EINVAL, "run_sampled: history capacity %lld exceeded", (long long)capacity);
   const int64_t nr = (int64_t)h->runs.size();
   if (h->batched) {
-    if (!h->sample_graph || h->sample_every != every || h->sample_hist != hist) {
-      if (h->sample_graph) (void)hipGraphExecDestroy(h->sample_graph);
-      h->sample_graph = nullptr;
-      const int rc = capture_batch(h, every, hist, &h->sample_graph);
-      if (rc) return rc;
+    if (h->sample_every != every || h->sample_hist != hist) {
+      for (auto& kv : h->sample_graphs) (void)hipGraphExecDestroy(kv.second);
+      h->sample_graphs.clear();
       h->sample_every = every;
       h->sample_hist = hist;
     }
     for (int64_t k = 0; k < rows; ++k) {
-      HIP_TRY(h, hipGraphLaunch(h->sample_graph, h->stream));
+      const unsigned grid = batch_grid_at(h, h->global_steps);
+      hipGraphExec_t& g = h->sample_graphs[grid];
+      if (!g) {
+        const int rc = capture_batch(h, every, hist, grid, &g);
+        if (rc) {
+          h->sample_graphs.erase(grid);
+          return rc;
+        }
+      }
+      HIP_TRY(h, hipGraphLaunch(g, h->stream));
       advance_host_clock(h, every);
     }
     h->sample_rows += rows;
