@@ -7,7 +7,7 @@ the two large workloads, at seeded sample nodes, with sum phi before and after.
 The initial populations are the Python oracle's equilibrium of phi0 and u;
 the run is the C reference (oracle/lbm_ref.c, pinned to the Python oracle in
 tests/test_oracle_ref.py).  Uses only the oracle and the seeded workloads.
-About 20 min (2D) and 40 min (3D) on 8 host cores.
+About 20 min each (2D, 3D) on 8 host cores.
 
     OMP_NUM_THREADS=8 python tests/golden/make_full_length.py [d2q9|d3q15]
 """

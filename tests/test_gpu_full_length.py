@@ -78,7 +78,8 @@ GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "full_length.json")
 
 
 @pytest.mark.parametrize("case,precision,tol", [
-    ("d2q9", "fp64", 1e-12), ("d2q9", "fp32", 1e-5), ("d2q9", "fp16", 1e-3)])
+    ("d2q9", "fp64", 1e-12), ("d2q9", "fp32", 1e-5), ("d2q9", "fp16", 1e-3),
+    ("d3q15", "fp64", 1e-12), ("d3q15", "fp32", 1e-5)])
 def test_full_length_against_fp64_reference(case, precision, tol):
     from paper_1404_2363_amd.solver import Solver
     gold = json.load(open(GOLDEN))[case]
