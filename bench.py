@@ -249,6 +249,44 @@ def adjoint_variant(precision="fp32"):
             "forward + recompute + reverse (3 passes)"}
 
 
+def adjoint_all_ics_variant(precision="fp32"):
+    """The gradient of the total misfit over all 10 initial conditions of the
+    512^2 inverse problem, the rollouts run one after another (one autograd
+    graph over ten rollouts) and side by side (misfit_many: a stream per
+    condition).  One warm-up each, then one timed gradient each."""
+    import torch
+    from paper_1404_2363_amd import workloads as W
+    from paper_1404_2363_amd.adjoint import RolloutSpec, misfit, misfit_many
+    inv = W.inverse_dfield()
+    dev = "cuda:0"
+    specs = [RolloutSpec(ic, inv["steps"], inv["snap_every"], inv["ckpt_every"], precision, (1.0, 1.0))
+             for ic in inv["ics"]]
+    phi0s = [torch.tensor(ic.phi0(), dtype=torch.float64, device=dev) for ic in inv["ics"]]
+    obs = [torch.zeros((inv["steps"] // inv["snap_every"],) + ic.grid, dtype=torch.float64, device=dev)
+           for ic in inv["ics"]]
+    D = torch.tensor(inv["D_trial"], dtype=torch.float64, device=dev, requires_grad=True)
+
+    def sequential():
+        return sum(misfit(D, p, o, sp) for p, o, sp in zip(phi0s, obs, specs))
+
+    def side_by_side():
+        return misfit_many(D, phi0s, obs, specs)
+
+    out = {"precision": precision, "initial_conditions": len(specs), "nodes": specs[0].workload.nodes,
+           "steps": inv["steps"]}
+    for name, fn in (("sequential", sequential), ("side_by_side", side_by_side)):
+        fn().backward()
+        D.grad = None
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fn().backward()
+        torch.cuda.synchronize()
+        out[f"seconds_{name}"] = time.perf_counter() - t0
+        D.grad = None
+    out["speedup_side_by_side"] = out["seconds_sequential"] / out["seconds_side_by_side"]
+    return out
+
+
 def adjoint_segment_variant(n=2048, K=16, precision="fp32"):
     """One checkpoint segment of the adjoint on an n^2 grid with a per-node D
     field (FP32): K forward steps recomputed from the checkpoint, then K
@@ -428,6 +466,11 @@ def main():
         log("adjoint: one 512^2 x 2000-step gradient")
         out["inverse_adjoint_fp32"] = adjoint_variant("fp32")
         log(f"adjoint: {out['inverse_adjoint_fp32']['seconds_per_gradient']:.3f} s per gradient")
+        log("adjoint: the gradient over all 10 initial conditions, sequential and side by side")
+        out["inverse_adjoint_10ics_fp32"] = adjoint_all_ics_variant("fp32")
+        a = out["inverse_adjoint_10ics_fp32"]
+        log(f"adjoint 10 ICs: {a['seconds_sequential']:.3f} s sequential, {a['seconds_side_by_side']:.3f} s "
+            f"side by side")
     if "d2q9_4096_fp32" not in out:
         out["d2q9_4096_fp32"] = gpu_variant(wl2, "fp32", args.steps, args.warmup, tune)
     main_v = out["d2q9_4096_fp32"]

@@ -85,6 +85,104 @@ class Rollout(torch.autograd.Function):
         return grad.to(ctx.D_dtype), dphi0, None
 
 
+class RolloutMany(torch.autograd.Function):
+    """J = sum over initial conditions k of 1/2 sum (phi_k - obs_k)^2 for one
+    D field, the rollouts of all initial conditions advanced side by side: each
+    has its own handle on a stream of its own (default priority), and the host
+    issues their checkpoint segments in turn, so that the GPU overlaps runs
+    that alone fill only part of it (a 512^2 step).  Forward and backward are
+    those of ``Rollout``; the gradient is the sum of the per-condition
+    gradients in the order of the conditions."""
+
+    @staticmethod
+    def forward(ctx, D_field, phi0s, obs, specs):
+        dev = D_field.device
+        main = torch.cuda.current_stream(dev)
+        streams = [torch.cuda.Stream(device=dev) for _ in specs]
+        runs = []
+        for st, p0, spec in zip(streams, phi0s, specs):
+            st.wait_stream(main)
+            with torch.cuda.stream(st):
+                wl = dataclasses.replace(spec.workload, D_field=D_field)
+                s = Solver(wl, spec.precision, device=spec.device, heat=list(spec.heat), phi0=[p0])
+            runs.append({"s": s, "ckpts": {}, "snaps": [], "t": 0})
+        T = specs[0].steps
+        if any(sp.steps != T or sp.snap_every != specs[0].snap_every or sp.ckpt_every != specs[0].ckpt_every
+               for sp in specs):
+            raise ValueError("misfit_many needs one schedule (steps, snapshots, checkpoints) for every condition")
+        spec0 = specs[0]
+        t = 0
+        while t < T:
+            nxt = min((t // spec0.ckpt_every + 1) * spec0.ckpt_every, (t // spec0.snap_every + 1) * spec0.snap_every, T)
+            for st, r in zip(streams, runs):
+                with torch.cuda.stream(st):
+                    if t % spec0.ckpt_every == 0:
+                        r["ckpts"][t] = r["s"].get_state()
+                    r["s"].step(nxt - t)
+                    if nxt % spec0.snap_every == 0:
+                        r["snaps"].append(r["s"].phi())
+            t = nxt
+        J = torch.zeros((), dtype=torch.float64, device=dev)
+        resid = []
+        for st, r, o in zip(streams, runs, obs):
+            with torch.cuda.stream(st):
+                d = torch.stack(r["snaps"]) - o
+                resid.append(d)
+                Jk = 0.5 * (d * d).sum()
+            main.wait_stream(st)
+            J = J + Jk
+        ctx.runs, ctx.resid, ctx.streams, ctx.specs = runs, resid, streams, specs
+        ctx.D_dtype = D_field.dtype
+        return J
+
+    @staticmethod
+    def backward(ctx, grad_J):
+        runs, streams, spec0 = ctx.runs, ctx.streams, ctx.specs[0]
+        dev = runs[0]["s"].device
+        main = torch.cuda.current_stream(dev)
+        ny, nx = runs[0]["s"].runs[0].grid
+        T = spec0.steps
+        bufs = []
+        for st, r, d in zip(streams, runs, ctx.resid):
+            st.wait_stream(main)
+            with torch.cuda.stream(st):
+                s = r["s"]
+                nb = s.state_bytes()
+                g = (grad_J.to(torch.float64) * d).contiguous()
+                bufs.append({"g": g, "mu": torch.zeros(nb, dtype=torch.uint8, device=dev),
+                             "mu_tmp": torch.empty(nb, dtype=torch.uint8, device=dev),
+                             "seg": torch.empty(L.lbm_cde_adjoint_scratch_bytes(s.h, 0, spec0.ckpt_every),
+                                                dtype=torch.uint8, device=dev),
+                             "grad": torch.zeros((3, ny, nx), dtype=torch.float64, device=dev)})
+        for t0 in sorted(runs[0]["ckpts"], reverse=True):
+            K = min(spec0.ckpt_every, T - t0)
+            for st, r, b in zip(streams, runs, bufs):
+                inj = []
+                for k in range(K):
+                    t1 = t0 + k + 1
+                    inj.append(b["g"][t1 // spec0.snap_every - 1].data_ptr() if t1 % spec0.snap_every == 0 else None)
+                with torch.cuda.stream(st):
+                    L.lbm_cde_adjoint_segment(r["s"].h, 0, r["ckpts"][t0].data_ptr(), K, b["seg"].data_ptr(), inj,
+                                              b["mu"].data_ptr(), b["mu_tmp"].data_ptr(), b["grad"].data_ptr())
+        grad = torch.zeros((3, ny, nx), dtype=torch.float64, device=dev)
+        for st, b in zip(streams, bufs):
+            main.wait_stream(st)
+            grad += b["grad"]
+        for st in streams:
+            st.synchronize()
+        for r in runs:
+            r["s"].close()
+        ctx.runs = None
+        return grad.to(ctx.D_dtype), None, None, None
+
+
+def misfit_many(D_field: torch.Tensor, phi0s: Sequence[torch.Tensor], obs: Sequence[torch.Tensor],
+                specs: Sequence[RolloutSpec]) -> torch.Tensor:
+    """Sum over initial conditions of the snapshot misfits, the rollouts run
+    side by side (differentiable with respect to D_field only)."""
+    return RolloutMany.apply(D_field, list(phi0s), list(obs), list(specs))
+
+
 def misfit(D_field: torch.Tensor, phi0: torch.Tensor, obs: torch.Tensor, spec: RolloutSpec) -> torch.Tensor:
     """J = 1/2 sum over snapshots and nodes of (phi - obs)^2 (differentiable)."""
     snaps = Rollout.apply(D_field, phi0, spec)

@@ -145,3 +145,35 @@ def test_inverse_problem_gradient_vs_finite_differences():
         worst = max(worst, err)
         print(f"node ({x},{y}) comp {c}: adjoint {g[c, y, x]:.6e} fd {fd:.6e} rel {err:.2e}", flush=True)
     assert worst <= 1e-4, worst
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_misfit_many_equals_sequential(precision):
+    """The initial conditions run side by side, each on its own stream, give
+    the gradient of the same total misfit as running them one after another
+    (same kernels per condition; only the order of the final sum differs)."""
+    import torch
+    from paper_1404_2363_amd.adjoint import RolloutSpec, forward_snapshots, misfit, misfit_many
+    inv = W.inverse_dfield(n=96, n_ic=3, steps=400, snap_every=100, ckpt_every=50, sigma0=8.0)
+    dev = "cuda:0"
+    print(f"case misfit_many 96^2, 3 ICs x 400 steps, {precision}", flush=True)
+    specs = [RolloutSpec(ic, inv["steps"], inv["snap_every"], inv["ckpt_every"], precision, (1.0, 1.0))
+             for ic in inv["ics"]]
+    spec64 = [RolloutSpec(ic, inv["steps"], inv["snap_every"], inv["ckpt_every"], "fp64", (1.0, 1.0))
+              for ic in inv["ics"]]
+    phi0s = [torch.tensor(ic.phi0(), dtype=torch.float64, device=dev) for ic in inv["ics"]]
+    D_true = torch.tensor(inv["D_true"], dtype=torch.float64, device=dev)
+    obs = [forward_snapshots(D_true, p, sp) for p, sp in zip(phi0s, spec64)]
+    D1 = torch.tensor(inv["D_trial"], dtype=torch.float64, device=dev, requires_grad=True)
+    J1 = sum(misfit(D1, p, o, sp) for p, o, sp in zip(phi0s, obs, specs))
+    J1.backward()
+    D2 = torch.tensor(inv["D_trial"], dtype=torch.float64, device=dev, requires_grad=True)
+    J2 = misfit_many(D2, phi0s, obs, specs)
+    J2.backward()
+    torch.cuda.synchronize()
+    g1, g2 = D1.grad.cpu().numpy(), D2.grad.cpu().numpy()
+    err = float(np.abs(g1 - g2).max() / np.abs(g1).max())
+    j1, j2 = float(J1.detach()), float(J2.detach())
+    print(f"J {j1:.12e} vs {j2:.12e}; gradient difference {err:.2e}", flush=True)
+    assert abs(j1 - j2) <= 1e-12 * abs(j1)
+    assert err <= 1e-12
