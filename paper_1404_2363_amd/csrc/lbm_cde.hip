@@ -16,6 +16,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <tuple>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -45,6 +46,7 @@ thread_local std::string g_init_error;
 
 constexpr size_t kAlign = 256;
 constexpr int kGraphSteps = 32;   // steps per captured graph (an even number)
+constexpr size_t kMaxAdjGraphs = 16;  // captured adjoint-segment parts kept per handle
 constexpr int kBatchRedBlocks = 64;  // reduction blocks per run in batched sampling
 
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
@@ -128,6 +130,9 @@ struct lbm_cde {
   // captured batched steps (and sampled blocks) per launch grid: late in an
   // ensemble the grid shrinks with the active prefix of the tile list
   std::map<unsigned, hipGraphExec_t> batch_graphs, sample_graphs;
+  // captured parts of adjoint segments: (run, K, seg, mu, mu_tmp, grad, part)
+  std::map<std::tuple<int32_t, int32_t, const void*, const void*, const void*, const void*, int>, hipGraphExec_t>
+      adj_graphs;
   std::vector<int64_t> batch_prefix;  // tile-list prefix, in batch order (host copy)
   int64_t sample_every = 0;
   double* sample_hist = nullptr;
@@ -751,6 +756,8 @@ void drop_graphs(lbm_cde* h) {
     for (auto& kv : *m) (void)hipGraphExecDestroy(kv.second);
     m->clear();
   }
+  for (auto& kv : h->adj_graphs) (void)hipGraphExecDestroy(kv.second);
+  h->adj_graphs.clear();
 }
 
 // Capture kGraphSteps steps starting from parity p on the private stream.
@@ -1859,33 +1866,86 @@ int lbm_cde_adjoint_segment(lbm_cde_handle h, int32_t run, const void* ckpt, int
   char* segc = (char*)seg;
   char* P[2] = {segc, segc + L.state};
   float* part = (float*)(segc + L.part);
-  // recompute the forward steps t0 .. t0+K-1 from the checkpoint, keeping v
-  // of each step (the last step needs no state)
-  for (int k = 0; k < nsteps; ++k) {
+  const int K = nsteps;
+  // forward step k of the recomputation (from the checkpoint for k = 0),
+  // keeping v of each step (the last step needs no state)
+  auto fwd = [&](int k, hipStream_t s) {
     RunArgs a = make_args(h, *r, 0);
     a.src = k == 0 ? ckpt : P[k & 1];
     a.dst = P[(k + 1) & 1];
     void* v = segc + L.v + (size_t)k * L.v_step;
-    if (r->dbl) launch_step_v<double>(*r, a, v, k + 1 < nsteps, h->stream);
-    else launch_step_v<float>(*r, a, v, k + 1 < nsteps, h->stream);
-  }
-  // reverse sweep: mu_{t+1} -> mu_t for t = t0+K-1 .. t0.  FP32 storage
-  // gathers the segment's gradient in the FP32 partial and folds it into the
-  // FP64 output in the last reverse step.
-  void* cur = mu;
-  void* nxt = mu_tmp;
-  for (int k = nsteps - 1; k >= 0; --k) {
+    if (r->dbl) launch_step_v<double>(*r, a, v, k + 1 < K, s);
+    else launch_step_v<float>(*r, a, v, k + 1 < K, s);
+  };
+  // reverse step k: mu_{t+1} (cur) -> mu_t (nxt).  FP32 storage gathers the
+  // segment's gradient in the FP32 partial and folds it into the FP64 output
+  // in the last reverse step.
+  auto rev = [&](int k, void* cur, void* nxt, const double* injk, hipStream_t s) {
     const RunArgs a = make_args(h, *r, 0);
-    const AdjBufs b{segc + L.v + (size_t)k * L.v_step, cur, inj ? inj[k] : nullptr, nxt, grad, part};
+    const AdjBufs b{segc + L.v + (size_t)k * L.v_step, cur, injk, nxt, grad, part};
     int gmode = GRAD_F64;
-    if (!r->dbl && nsteps >= 2)
-      gmode = k == nsteps - 1 ? GRAD_F32_SET : (k == 0 ? GRAD_F32_FOLD : GRAD_F32_ADD);
-    if (r->dbl) launch_adjoint<double>(h, *r, a, b, gmode, 1.0 / r->kappa, h->stream);
-    else launch_adjoint<float>(h, *r, a, b, gmode, 1.0 / r->kappa, h->stream);
-    std::swap(cur, nxt);
-  }
+    if (!r->dbl && K >= 2) gmode = k == K - 1 ? GRAD_F32_SET : (k == 0 ? GRAD_F32_FOLD : GRAD_F32_ADD);
+    if (r->dbl) launch_adjoint<double>(h, *r, a, b, gmode, 1.0 / r->kappa, s);
+    else launch_adjoint<float>(h, *r, a, b, gmode, 1.0 / r->kappa, s);
+  };
   const size_t sb = (size_t)r->Q * r->plane * r->elem;
-  if (cur != mu) HIP_TRY(h, hipMemcpyAsync(mu, cur, sb, hipMemcpyDeviceToDevice, h->stream));
+  // Graphs: with K >= 2 and no injection before the segment's last step,
+  // everything but the first forward step (which reads the caller's
+  // checkpoint) and the first reverse step (which reads the injection) has
+  // the same arguments in every call with the same K and buffers: those two
+  // are launched directly and the rest replayed from two captured graphs.
+  bool graphs = K >= 2;
+  if (inj)
+    for (int k = 0; k + 1 < K; ++k) graphs = graphs && !inj[k];
+  if (const char* e = std::getenv("LBM_CDE_ADJ_GRAPHS")) graphs = graphs && std::atoi(e) != 0;
+  if (!graphs) {
+    for (int k = 0; k < K; ++k) fwd(k, h->stream);
+    void* cur = mu;
+    void* nxt = mu_tmp;
+    for (int k = K - 1; k >= 0; --k) {
+      rev(k, cur, nxt, inj ? inj[k] : nullptr, h->stream);
+      std::swap(cur, nxt);
+    }
+    if (cur != mu) HIP_TRY(h, hipMemcpyAsync(mu, cur, sb, hipMemcpyDeviceToDevice, h->stream));
+    HIP_TRY(h, hipGetLastError());
+    return LBM_CDE_OK;
+  }
+  auto graph = [&](int which, auto body) -> hipGraphExec_t {
+    const auto key = std::make_tuple(run, K, (const void*)seg, (const void*)mu, (const void*)mu_tmp,
+                                     (const void*)grad, which);
+    auto it = h->adj_graphs.find(key);
+    if (it != h->adj_graphs.end()) return it->second;
+    if (h->adj_graphs.size() >= kMaxAdjGraphs) {  // callers that change buffers every call
+      if (hipStreamSynchronize(h->stream) != hipSuccess) return nullptr;
+      for (auto& kv : h->adj_graphs) (void)hipGraphExecDestroy(kv.second);
+      h->adj_graphs.clear();
+    }
+    if (hipStreamBeginCapture(h->capture, hipStreamCaptureModeThreadLocal) != hipSuccess) return nullptr;
+    body(h->capture);
+    hipGraph_t g = nullptr;
+    hipGraphExec_t x = nullptr;
+    const hipError_t e = hipStreamEndCapture(h->capture, &g);
+    if (e == hipSuccess && hipGraphInstantiate(&x, g, nullptr, nullptr, 0) == hipSuccess) h->adj_graphs[key] = x;
+    if (g) (void)hipGraphDestroy(g);
+    return x;
+  };
+  hipGraphExec_t ga = graph(0, [&](hipStream_t s) {
+    for (int k = 1; k < K; ++k) fwd(k, s);
+  });
+  hipGraphExec_t gb = graph(1, [&](hipStream_t s) {
+    void* cur = mu_tmp;
+    void* nxt = mu;
+    for (int k = K - 2; k >= 0; --k) {
+      rev(k, cur, nxt, nullptr, s);
+      std::swap(cur, nxt);
+    }
+    if (cur != mu) (void)hipMemcpyAsync(mu, cur, sb, hipMemcpyDeviceToDevice, s);
+  });
+  if (!ga || !gb) return fail(h, LBM_CDE_EHIP, "adjoint_segment: graph capture failed");
+  fwd(0, h->stream);
+  HIP_TRY(h, hipGraphLaunch(ga, h->stream));
+  rev(K - 1, mu, mu_tmp, inj ? inj[K - 1] : nullptr, h->stream);
+  HIP_TRY(h, hipGraphLaunch(gb, h->stream));
   HIP_TRY(h, hipGetLastError());
   return LBM_CDE_OK;
 }

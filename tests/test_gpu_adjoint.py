@@ -4,7 +4,9 @@ adjoint and against central finite differences.
 * Parity: dJ/dD (per node, 3 components), dJ/dphi0 and J from the GPU
   rollout + backward equal the oracle's misfit_gradient on small grids,
   periodic and with walls, with checkpoint segments that do and do not divide
-  the run length.  Bounds: 1e-10 (FP64) and 1e-4 (FP32) of max |grad|.
+  the run length, with snapshots inside segments and at segment ends only.
+  Bounds: 1e-10 (FP64) and 1e-4 (FP32) of max |grad|.
+* Segments replayed from captured graphs equal step-by-step launches bitwise.
 * Finite differences: on the inverse-problem workload (512^2, smooth random
   D field, 10 Gaussian initial conditions, 2000 steps, snapshots every 200,
   checkpoints every 100) the FP32 adjoint gradient agrees with central
@@ -35,16 +37,21 @@ def _setup(nx, ny, steps, snap, walls=("periodic", "periodic"), seed=5):
     return wl, d_trial, phi0, obs
 
 
+PP = ("periodic", "periodic")
+
+
+# snap < ckpt puts snapshots inside segments (launched step by step); snap >=
+# ckpt puts them at segment ends only (the captured-graph replay of a segment)
 @pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("fp32", 1e-4)])
-@pytest.mark.parametrize("walls,ckpt", [(("periodic", "periodic"), 20), (("periodic", "periodic"), 25),
-                                        (("periodic", "periodic"), 1), (("periodic", "periodic"), 2),
-                                        (("periodic", "specular"), 20), (("bounce", "specular"), 30)])
-def test_adjoint_matches_oracle(precision, tol, walls, ckpt):
+@pytest.mark.parametrize("walls,snap,ckpt", [(PP, 10, 20), (PP, 10, 25), (PP, 10, 1), (PP, 10, 2),
+                                             (("periodic", "specular"), 10, 20), (("bounce", "specular"), 10, 30),
+                                             (PP, 20, 10), (PP, 20, 20), (("bounce", "specular"), 20, 7)])
+def test_adjoint_matches_oracle(precision, tol, walls, snap, ckpt):
     import torch
     from paper_1404_2363_amd.adjoint import RolloutSpec, misfit
-    nx, ny, steps, snap = 24, 20, 60, 10
+    nx, ny, steps = 24, 20, 60
     wl, d_trial, phi0, obs = _setup(nx, ny, steps, snap, walls)
-    print(f"case adjoint {nx}x{ny} x {steps} {walls} ckpt {ckpt} {precision}", flush=True)
+    print(f"case adjoint {nx}x{ny} x {steps} {walls} snap {snap} ckpt {ckpt} {precision}", flush=True)
     J_ref, g_ref, dphi_ref = O.misfit_gradient(O.Problem("d2q9", (nx, ny), walls, wl.u(), d_trial,
                                                          heat_rule=[1.0, 1.0]), phi0, obs, snap, return_dphi0=True)
     dev = "cuda:0"
@@ -59,6 +66,33 @@ def test_adjoint_matches_oracle(precision, tol, walls, ckpt):
     assert np.abs(g - g_ref).max() <= tol * np.abs(g_ref).max(), np.abs(g - g_ref).max() / np.abs(g_ref).max()
     dp = p0.grad.cpu().numpy()
     assert np.abs(dp - dphi_ref).max() <= tol * np.abs(dphi_ref).max()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_segment_graphs_equal_direct_launches(precision, monkeypatch):
+    """A segment replayed from its captured graphs launches the same kernels
+    with the same arguments as the step-by-step path: the gradients are
+    bitwise equal.  Checkpoints every 20, 40 and 7 steps with snapshots every
+    40 cover whole-graph segments, a shorter last segment (a second pair of
+    graphs) and segments with a snapshot inside (step by step)."""
+    import torch
+    from paper_1404_2363_amd.adjoint import RolloutSpec, misfit
+    nx, ny, steps, snap = 64, 48, 120, 40
+    wl, d_trial, phi0, obs = _setup(nx, ny, steps, snap, ("bounce", "specular"))
+    dev = "cuda:0"
+    ob = torch.tensor(np.stack(obs), dtype=torch.float64, device=dev)
+    for ckpt in (20, 40, 7):
+        out = []
+        for graphs in ("1", "0"):
+            monkeypatch.setenv("LBM_CDE_ADJ_GRAPHS", graphs)
+            print(f"case segment graphs={graphs} {precision} ckpt {ckpt}", flush=True)
+            D = torch.tensor(d_trial, dtype=torch.float64, device=dev, requires_grad=True)
+            p0 = torch.tensor(phi0, dtype=torch.float64, device=dev, requires_grad=True)
+            misfit(D, p0, ob, RolloutSpec(wl, steps, snap, ckpt, precision, (1.0, 1.0))).backward()
+            out.append((D.grad.cpu().numpy(), p0.grad.cpu().numpy()))
+        np.testing.assert_array_equal(out[0][0], out[1][0])
+        np.testing.assert_array_equal(out[0][1], out[1][1])
+        assert np.abs(out[0][0]).max() > 0
 
 
 def test_adjoint_rejects_adaptive_heat_rates():
