@@ -39,10 +39,11 @@ COPY_PROBE_BYTES = 1 << 30     # bytes read (and written) by one calibration cop
 def kernel_tag(launch):
     """Key of a launch variant in the committed counter profile: tile shape,
     rows per thread, streaming stores, block order (and the persistent grid
-    of a batched launch)."""
+    of a batched launch, the steps per launch of a multi-step one)."""
     bx, by = launch["block"]
     tag = f"{bx}x{by}x{launch['rows_per_thread']}x{int(bool(launch['nt_stores']))}|order{launch['block_order']}"
-    return tag + (f"|grid{launch['grid']}" if launch.get("grid") else "")
+    tag += f"|grid{launch['grid']}" if launch.get("grid") else ""
+    return tag + (f"|steps{launch['steps_per_launch']}" if launch.get("steps_per_launch", 1) > 1 else "")
 
 
 def _profile(name):

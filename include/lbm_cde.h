@@ -261,19 +261,26 @@ int lbm_cde_relaxation_matrix(lbm_cde_handle h, int32_t run, double* S_out);
  * has no velocity field or an argument is NULL. */
 int lbm_cde_set_velocity(lbm_cde_handle h, int32_t run, const double* u);
 
-/* Launch variants.  A variant is six integers: block x, block y, rows per
+/* Launch variants.  A variant is seven integers: block x, block y, rows per
  * thread, streaming stores (0/1), block order (0: hardware order, 1: each
  * XCD takes a contiguous range of tiles, 2: tile rows interleaved over the 8
- * XCDs with all x-tiles of a row on one XCD) and, for a batched handle
+ * XCDs with all x-tiles of a row on one XCD), for a batched handle
  * (several D2Q9 runs in one FP64 or FP32 precision, stepped by one persistent
- * launch over a flat list of block-x-wide row tiles), the number of blocks
+ * launch over a flat list of block-x-wide row tiles) the number of blocks
  * of that launch (0: one block per tile; otherwise each block walks every
- * grid-th tile).  A batched handle has one variant for all its runs; the
- * run index only has to be valid.  Results are bitwise the same for every
- * variant. */
+ * grid-th tile), and the number of steps one launch takes.  More than one
+ * step per launch is built for D2Q9 FP64/FP32 runs periodic on both axes
+ * whose axes span the tile (block x by block y times rows per thread nodes)
+ * plus that many steps minus one nodes on each side: the launch keeps the
+ * intermediate steps of a tile and its halo in LDS (Eq. 5: a population
+ * moves one node per step), so the state crosses HBM once per launch; the
+ * steps left over when a call's count is not a multiple go one per launch.
+ * A batched handle has one variant for all its runs; the run index only has
+ * to be valid.  Results are bitwise the same for every variant. */
 
 /* Autotuner: time `trials` launches of every compiled variant (those listed
- * by lbm_cde_variant_at) and keep the fastest, per run, or once for a
+ * by lbm_cde_variant_at) and keep the one with the least time per step, per
+ * run (and the fastest one-step variant for left-over steps), or once for a
  * batched handle.  Each timed launch reads the current state and overwrites
  * only the other population buffer, so the simulation state is unchanged.
  * If the environment variable LBM_CDE_TUNE_CACHE names a file, results are
@@ -282,7 +289,7 @@ int lbm_cde_set_velocity(lbm_cde_handle h, int32_t run, const double* u);
  * and new ones appended.  Waits for the stream.  EINVAL for trials < 1. */
 int lbm_cde_tune(lbm_cde_handle h, int32_t trials);
 
-/* The launch variant of run `run` into out[0..5] (layout above; out[5] is
+/* The launch variant of run `run` into out[0..6] (layout above; out[5] is
  * the launch's actual number of blocks on a batched handle, else 0).  The
  * environment variables LBM_CDE_TILE = "BXxBYxNY", LBM_CDE_TILE3,
  * LBM_CDE_NT, LBM_CDE_XCD, LBM_CDE_TILE16 = "BXxBY[xNT[xORDER]]" and
@@ -293,11 +300,11 @@ int lbm_cde_get_variant(lbm_cde_handle h, int32_t run, int32_t* out);
 /* Number of compiled launch variants of run `run` (the tuner's candidates). */
 int lbm_cde_variant_count(lbm_cde_handle h, int32_t run, int32_t* count);
 
-/* Candidate `index` (0 <= index < count) of run `run` into out[0..5].
+/* Candidate `index` (0 <= index < count) of run `run` into out[0..6].
  * EINVAL for an index out of range. */
 int lbm_cde_variant_at(lbm_cde_handle h, int32_t run, int32_t index, int32_t* out);
 
-/* Make v[0..5] the launch variant of run `run` (of the whole batch on a
+/* Make v[0..6] the launch variant of run `run` (of the whole batch on a
  * batched handle).  Captured graphs are rebuilt on the next step.  EINVAL
  * if the variant is not compiled for the run (a block count must be 0 for a
  * run stepped alone, >= 0 for a batch; the row-interleaved order needs a

@@ -198,18 +198,22 @@ def lbm_cde_tune(h: int, trials: int) -> None:
     _check(load().lbm_cde_tune(h, trials), "lbm_cde_tune", h)
 
 
+VARIANT_INTS = 7                # integers of a launch variant (see include/lbm_cde.h)
+
+
 def _variant_dict(out) -> dict:
     return {"block": (out[0], out[1]), "rows_per_thread": out[2], "nt_stores": bool(out[3]),
-            "block_order": int(out[4]), "grid": int(out[5])}
+            "block_order": int(out[4]), "grid": int(out[5]), "steps_per_launch": int(out[6])}
 
 
 def variant_tuple(v: dict) -> tuple:
-    """The six integers of a variant dict (as returned by lbm_cde_get_variant)."""
-    return (v["block"][0], v["block"][1], v["rows_per_thread"], int(v["nt_stores"]), v["block_order"], v["grid"])
+    """The seven integers of a variant dict (as returned by lbm_cde_get_variant)."""
+    return (v["block"][0], v["block"][1], v["rows_per_thread"], int(v["nt_stores"]), v["block_order"], v["grid"],
+            v.get("steps_per_launch", 1))
 
 
 def lbm_cde_get_variant(h: int, run: int):
-    out = (ctypes.c_int32 * 6)()
+    out = (ctypes.c_int32 * VARIANT_INTS)()
     _check(load().lbm_cde_get_variant(h, run, out), "lbm_cde_get_variant", h)
     return _variant_dict(out)
 
@@ -221,13 +225,13 @@ def lbm_cde_variant_count(h: int, run: int) -> int:
 
 
 def lbm_cde_variant_at(h: int, run: int, index: int):
-    out = (ctypes.c_int32 * 6)()
+    out = (ctypes.c_int32 * VARIANT_INTS)()
     _check(load().lbm_cde_variant_at(h, run, index, out), "lbm_cde_variant_at", h)
     return _variant_dict(out)
 
 
 def lbm_cde_set_variant(h: int, run: int, v: dict) -> None:
-    arr = (ctypes.c_int32 * 6)(*variant_tuple(v))
+    arr = (ctypes.c_int32 * VARIANT_INTS)(*variant_tuple(v))
     _check(load().lbm_cde_set_variant(h, run, arr), "lbm_cde_set_variant", h)
 
 

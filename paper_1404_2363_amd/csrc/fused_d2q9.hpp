@@ -1,0 +1,178 @@
+// Several D2Q9 steps per launch for runs periodic on both axes (temporal
+// blocking through LDS).
+//
+// A population moves at most one node per step (Eq. 5), so the state of an
+// output tile T steps later depends only on the stored state within T nodes
+// of it.  A block owns a tile of TX x TY output nodes and:
+//   step 1      pulls the stored state from HBM for the tile widened by T-1
+//               nodes on every side, collides, and keeps the result in LDS;
+//   steps 2..T-1 pull from LDS and update it in place over a ring that
+//               shrinks by one node per step (all reads, barrier, writes,
+//               barrier);
+//   step T      pulls from LDS for the tile itself and stores to HBM.
+// Every node's step uses the same pull, velocity, relaxation and collision
+// arithmetic as the one-step kernel (tile_d2q9 without walls), so T steps of
+// this kernel equal T one-step launches bitwise.  HBM sees one read and one
+// write of the state per T steps (72 B per node for FP32, 144 B for FP64)
+// instead of per step; the price is the recomputed rings (the widened tiles'
+// extra collisions) and LDS traffic.  Halo nodes take periodic images, which
+// needs nx >= TX + 2(T-1) and ny >= TY + 2(T-1) (one wrap per coordinate).
+//
+// UK selects the velocity: 0 constant, 1 separable (a product of per-axis
+// factors: the block stages the widened tile's column and row factors in LDS
+// once and multiplies them in the one-step kernel's order), 2 a per-node
+// field (read from memory at every step).  Byte offsets within a population
+// plane are 32-bit (nodes * sizeof(R) < 2^32).
+#pragma once
+
+#include "d2q9.hpp"
+
+namespace lbm {
+
+// Velocity components of population i (Eq. 2), in the order of d2q9.hpp.
+__device__ constexpr int kEx9[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+__device__ constexpr int kEy9[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+
+LBM_FORCEINLINE int32_t wrap_once(int32_t v, int32_t n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
+
+// Block (BX, BY) threads; output tile BX x (BY * NY); T steps per launch.
+template <typename R, int BX, int BY, int NY, int T, int UK>
+__global__ __launch_bounds__(BX * BY) void k_fused_d2q9(const RunArgs a) {
+  static_assert(T >= 2, "one step per launch is k_step_d2q9");
+  constexpr int NTH = BX * BY, TX = BX, TY = BY * NY, RG = T - 1;
+  constexpr int W0 = TX + 2 * RG, H0 = TY + 2 * RG, C0 = W0 * H0;
+  constexpr int K0 = (C0 + NTH - 1) / NTH;
+  static_assert(W0 <= NTH && H0 <= NTH, "one thread per staged column and row");
+  __shared__ R lds[9 * C0];
+  __shared__ R ucol[UK == 1 ? 2 * W0 : 1], urow[UK == 1 ? 2 * H0 : 1];
+
+  const int tid = threadIdx.y * BX + threadIdx.x;
+  const uint32_t b = tile_of_block32(blockIdx.x, gridDim.x, a.tiles_x, a.xcd_remap);
+  const uint32_t tyi = fdiv(b, a.tiles_x);
+  const int32_t nx = (int32_t)a.nx, ny = (int32_t)a.ny;
+  const int32_t x0 = (int32_t)(b - tyi * a.tiles_x.d) * TX - RG, y0 = (int32_t)tyi * TY - RG;
+  const size_t pb = (size_t)a.plane * sizeof(R);
+  const Rel2<R> rc = const_rel2<R>(a);
+  const R phi_ref = (R)a.phi_ref;
+  // separable velocity: component c at (x, y) is ((t_c[0] t_c[1+x]) t_c[1+nx+y]) t_c[1+nx+ny]
+  const R* tab = (const R*)a.u_tab;
+  const int32_t tstride = 1 + nx + ny + (int32_t)a.nz;
+  R tz0 = (R)0, tz1 = (R)0;
+  if constexpr (UK == 1) {
+    tz0 = tab[1 + nx + ny];
+    tz1 = tab[tstride + 1 + nx + ny];
+  }
+
+  // collision of one node at periodic image (x, y); (lx, ly) in the widened tile
+  auto collide = [&](R(&f)[9], int32_t x, int32_t y, int lx, int ly) {
+    R ux, uy;
+    if constexpr (UK == 0) {
+      ux = (R)a.u_const[0];
+      uy = (R)a.u_const[1];
+    } else if constexpr (UK == 1) {
+      ux = (ucol[lx] * urow[ly]) * tz0;
+      uy = (ucol[W0 + lx] * urow[H0 + ly]) * tz1;
+    } else {
+      velocity2<R>(a, x, y, ux, uy);
+    }
+    if (a.node_par) collide_d2q9<R>(f, ux, uy, phi_ref, node_rel2<R>(a, (int64_t)y * nx + x));
+    else collide_d2q9<R>(f, ux, uy, phi_ref, rc);
+  };
+
+  // step 1: HBM -> LDS over the whole widened tile
+  {
+    const char* src = (const char*)a.src;
+    R f[K0][9];
+#pragma unroll
+    for (int k = 0; k < K0; ++k) {
+      const int j = tid + k * NTH;
+      if (K0 * NTH > C0 && j >= C0) continue;
+      const int ly = j / W0, lx = j - ly * W0;
+      const int32_t x = wrap_once(x0 + lx, nx), y = wrap_once(y0 + ly, ny);
+      const uint32_t xm = x == 0 ? nx - 1 : x - 1, xp = x + 1 == nx ? 0 : x + 1;
+      const uint32_t r0 = (uint32_t)y * nx, rm = (uint32_t)(y == 0 ? ny - 1 : y - 1) * nx,
+                     rp = (uint32_t)(y + 1 == ny ? 0 : y + 1) * nx;
+      constexpr uint32_t E = sizeof(R);
+      f[k][0] = gld<R>(src, (r0 + x) * E);
+      f[k][1] = gld<R>(src + 1 * pb, (r0 + xm) * E);
+      f[k][2] = gld<R>(src + 2 * pb, (rm + x) * E);
+      f[k][3] = gld<R>(src + 3 * pb, (r0 + xp) * E);
+      f[k][4] = gld<R>(src + 4 * pb, (rp + x) * E);
+      f[k][5] = gld<R>(src + 5 * pb, (rm + xm) * E);
+      f[k][6] = gld<R>(src + 6 * pb, (rm + xp) * E);
+      f[k][7] = gld<R>(src + 7 * pb, (rp + xp) * E);
+      f[k][8] = gld<R>(src + 8 * pb, (rp + xm) * E);
+    }
+    if constexpr (UK == 1) {
+      if (tid < W0) {
+        const int32_t x = wrap_once(x0 + tid, nx);
+        ucol[tid] = tab[0] * tab[1 + x];
+        ucol[W0 + tid] = tab[tstride] * tab[tstride + 1 + x];
+      }
+      if (tid < H0) {
+        const int32_t y = wrap_once(y0 + tid, ny);
+        urow[tid] = tab[1 + nx + y];
+        urow[H0 + tid] = tab[tstride + 1 + nx + y];
+      }
+    }
+    // the staged factors serve step 1 too (the barrier also waits for the
+    // population loads, which the collisions below need anyway)
+    if constexpr (UK == 1) __syncthreads();
+#pragma unroll
+    for (int k = 0; k < K0; ++k) {
+      const int j = tid + k * NTH;
+      if (K0 * NTH > C0 && j >= C0) continue;
+      const int ly = j / W0, lx = j - ly * W0;
+      collide(f[k], wrap_once(x0 + lx, nx), wrap_once(y0 + ly, ny), lx, ly);
+#pragma unroll
+      for (int i = 0; i < 9; ++i) lds[i * C0 + j] = f[k][i];
+    }
+  }
+  __syncthreads();
+
+  // steps 2 .. T-1: in place in LDS over the ring of width T - s
+#pragma unroll
+  for (int s = 2; s < T; ++s) {
+    const int r = T - s, W = TX + 2 * r, H = TY + 2 * r, C = W * H, off = RG - r;
+    R f[K0][9];
+    int at[K0];
+#pragma unroll
+    for (int k = 0; k < K0; ++k) {
+      const int j = tid + k * NTH;
+      at[k] = -1;
+      if (j >= C) continue;
+      const int ly = j / W + off, lx = j % W + off;
+      at[k] = ly * W0 + lx;
+#pragma unroll
+      for (int i = 0; i < 9; ++i) f[k][i] = lds[i * C0 + (ly - kEy9[i]) * W0 + (lx - kEx9[i])];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < K0; ++k) {
+      if (at[k] < 0) continue;
+      const int ly = at[k] / W0, lx = at[k] - ly * W0;
+      collide(f[k], wrap_once(x0 + lx, nx), wrap_once(y0 + ly, ny), lx, ly);
+#pragma unroll
+      for (int i = 0; i < 9; ++i) lds[i * C0 + at[k]] = f[k][i];
+    }
+    __syncthreads();
+  }
+
+  // step T: LDS -> HBM for the tile's own nodes
+  char* dst = (char*)a.dst;
+#pragma unroll
+  for (int k = 0; k < NY; ++k) {
+    const int lx = threadIdx.x + RG, ly = threadIdx.y + k * BY + RG;
+    const int32_t x = x0 + lx, y = y0 + ly;
+    if (x >= nx || y >= ny) continue;
+    R g[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) g[i] = lds[i * C0 + (ly - kEy9[i]) * W0 + (lx - kEx9[i])];
+    collide(g, x, y, lx, ly);
+    const uint32_t off = ((uint32_t)y * nx + x) * (uint32_t)sizeof(R);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) gst<R, true>(dst + i * pb, off, g[i]);
+  }
+}
+
+}  // namespace lbm

@@ -28,6 +28,7 @@
 #include "d3q15.hpp"
 #include "adjoint_d2q9.hpp"
 #include "fp16_d2q9.hpp"
+#include "fused_d2q9.hpp"
 #include "stability.hpp"
 
 using namespace lbm;
@@ -61,14 +62,17 @@ size_t plane_skew() {
 }
 
 // A launch variant of the step kernel: tile shape, store kind, block order,
-// and for the batched persistent launch its number of blocks.
+// for the batched persistent launch its number of blocks, and the number of
+// steps one launch takes (more than one: the LDS-blocked D2Q9 kernel).
 struct Variant {
   int bx, by, ny;
   bool nt;       // non-temporal (streaming) stores
   int xcd;       // block order: 0 hardware, 1 XCD-contiguous ranges, 2 rows interleaved over XCDs
   int grid = 0;  // batched launch: blocks walking the tile list (0: one block per tile)
+  int fuse = 1;  // steps per launch
   bool operator==(const Variant& o) const {
-    return bx == o.bx && by == o.by && ny == o.ny && nt == o.nt && xcd == o.xcd && grid == o.grid;
+    return bx == o.bx && by == o.by && ny == o.ny && nt == o.nt && xcd == o.xcd && grid == o.grid &&
+           fuse == o.fuse;
   }
 };
 
@@ -99,8 +103,10 @@ struct Run {
   double heat[3] = {0, 0, 0};
   double s[15] = {0};
   int64_t steps = 0;
+  int cur = 0;         // population buffer (0/1) that holds the current state
   bool walls = false;
   Variant var{256, 1, 1, true, false};
+  Variant var1{256, 1, 1, true, false};  // one-step launches (the steps a multi-step variant leaves over)
 };
 
 }  // namespace
@@ -110,6 +116,7 @@ struct lbm_cde {
   hipStream_t stream = nullptr;
   hipStream_t capture = nullptr;
   hipGraphExec_t graph[2] = {nullptr, nullptr};
+  bool graph_off = false;  // the runs' steps cannot be replayed from graph[] (odd launch counts)
   std::string err;
   int64_t sample_rows = 0;
   // batched mode: one persistent launch steps every run (same lattice and precision)
@@ -512,7 +519,8 @@ size_t state_size(const Run& r) {
   return r.split ? align_up(pb) + sizeof(float) * r.nodes : pb;
 }
 
-RunArgs make_args(const lbm_cde* h, const Run& r, int parity) {
+RunArgs make_args(const lbm_cde* h, const Run& r, int parity, const Variant* launch = nullptr) {
+  const Variant& var = launch ? *launch : r.var;
   RunArgs a;
   std::memset(&a, 0, sizeof a);
   a.src = r.pop[parity];
@@ -560,17 +568,17 @@ RunArgs make_args(const lbm_cde* h, const Run& r, int parity) {
   a.max_steps = r.d.max_steps;
   a.xref0 = r.d.xref0;
   a.xref_drift = r.d.xref_drift;
-  a.xcd_remap = r.var.xcd;
+  a.xcd_remap = var.xcd;
   // tile counts of the launch's block shape (16-bit runs: the split kernels
   // tile BX x BY nodes; the literal kernel 256 x 1)
-  const int64_t tbx = r.half && !r.split ? 256 : r.var.bx;
-  const int64_t tby = r.half && !r.split ? 1 : (int64_t)r.var.by * (r.half ? 1 : r.var.ny);
+  const int64_t tbx = r.half && !r.split ? 256 : var.bx;
+  const int64_t tby = r.half && !r.split ? 1 : (int64_t)var.by * (r.half ? 1 : var.ny);
   a.tiles_x = make_fastdiv((uint32_t)((r.d.nx + tbx - 1) / tbx));
   a.tiles_y = make_fastdiv((uint32_t)((r.d.ny + tby - 1) / tby));
   a.rows32 = r.d.lattice == LBM_CDE_D2Q9 && !r.half && r.d.bc[0] == LBM_CDE_PERIODIC && !r.node_par &&
              (double)r.plane * r.Q * r.elem < 4294967296.0 && r.d.nx < (1ll << 31) && r.d.ny < (1ll << 31) &&
              (r.d.u_kind != LBM_CDE_U_FIELD || 16.0 * (double)r.nodes < 4294967296.0);
-  if (a.xcd_remap == 2 && tile_rows(r, r.var) % 8 != 0) a.xcd_remap = 0;
+  if (a.xcd_remap == 2 && tile_rows(r, var) % 8 != 0) a.xcd_remap = 0;
   a.active = 1;
   return a;
 }
@@ -709,8 +717,57 @@ const SplitEntry kSplit[] = {SPLIT_ENTRY(64, 4), SPLIT_ENTRY(128, 2), SPLIT_ENTR
                              SPLIT_ENTRY(128, 4), SPLIT_ENTRY(256, 2)};
 
 
+// Several steps per launch (fused_d2q9.hpp): D2Q9 in FP64 or FP32, periodic
+// on both axes, streaming stores; tile BX x (BY * NY) nodes; the velocity
+// kind is a template argument.  A shape whose LDS (nine planes of the tile
+// widened by T - 1 nodes on every side) would exceed the 160 KiB of a CU is
+// not built for that precision.
+template <typename R, int BX, int BY, int NY, int T>
+void launch_fused(const RunArgs a, hipStream_t s) {
+  const int64_t ntx = (a.nx + BX - 1) / BX, nty = (a.ny + BY * NY - 1) / (BY * NY);
+  const dim3 g((unsigned)(ntx * nty)), b(BX, BY);
+  if (a.u_kind == U_CONST) hipLaunchKernelGGL((k_fused_d2q9<R, BX, BY, NY, T, 0>), g, b, 0, s, a);
+  else if (a.u_kind == U_SEPARABLE) hipLaunchKernelGGL((k_fused_d2q9<R, BX, BY, NY, T, 1>), g, b, 0, s, a);
+  else hipLaunchKernelGGL((k_fused_d2q9<R, BX, BY, NY, T, 2>), g, b, 0, s, a);
+}
+
+template <typename R, int BX, int BY, int NY, int T>
+constexpr StepFn fused_fn() {
+  if constexpr (9 * (BX + 2 * (T - 1)) * (BY * NY + 2 * (T - 1)) * sizeof(R) <= 160 * 1024)
+    return launch_fused<R, BX, BY, NY, T>;
+  else
+    return nullptr;
+}
+
+struct FusedEntry {
+  int bx, by, ny, T;
+  StepFn fn[2];  // [double?]
+};
+#define FUSED_ENTRY(BX, BY, NY, T) \
+  FusedEntry { BX, BY, NY, T, {fused_fn<float, BX, BY, NY, T>(), fused_fn<double, BX, BY, NY, T>()} }
+const FusedEntry kFused[] = {FUSED_ENTRY(128, 4, 2, 2), FUSED_ENTRY(128, 4, 2, 3), FUSED_ENTRY(128, 4, 2, 4),
+                             FUSED_ENTRY(128, 4, 2, 5), FUSED_ENTRY(64, 4, 2, 3),  FUSED_ENTRY(64, 4, 2, 4),
+                             FUSED_ENTRY(64, 8, 2, 3),  FUSED_ENTRY(64, 8, 2, 4),  FUSED_ENTRY(64, 8, 2, 5)};
+
+// A run can take T steps per launch when it is D2Q9 in FP64 or FP32,
+// periodic on both axes, each axis spans the tile plus T - 1 nodes on both
+// sides (halo nodes are periodic images taken with one wrap), and byte
+// offsets within a population plane fit 32 bits.
+bool fused_ok(const Run& r, const Variant& v) {
+  return r.d.lattice == LBM_CDE_D2Q9 && !r.half && !r.split && !r.walls && r.d.nz == 1 &&
+         r.d.nx >= (int64_t)v.bx + 2 * (v.fuse - 1) && r.d.ny >= (int64_t)v.by * v.ny + 2 * (v.fuse - 1) &&
+         (double)r.nodes * (double)r.elem < 4294967296.0 && r.d.nx < (1ll << 30) && r.d.ny < (1ll << 30) &&
+         v.grid == 0;
+}
+
 StepFn find_step(const Run& r, const Variant& v) {
   const int p = r.dbl ? 1 : 0, w = r.walls ? 1 : 0;
+  if (v.fuse != 1) {
+    if (v.fuse < 2 || !v.nt || !fused_ok(r, v)) return nullptr;
+    for (const auto& e : kFused)
+      if (e.bx == v.bx && e.by == v.by && e.ny == v.ny && e.T == v.fuse) return e.fn[p];
+    return nullptr;
+  }
   if (r.split) {
     for (const auto& e : kSplit)
       if (e.bx == v.bx && e.by == v.by && v.ny == 1) return e.fn[w][v.nt && !r.walls ? 1 : 0];
@@ -728,20 +785,35 @@ StepFn find_step(const Run& r, const Variant& v) {
   return nullptr;
 }
 
-StepFn pick_step(const lbm_cde* h, const Run& r) {
-  StepFn f = find_step(r, r.var);
-  return f ? f : find_step(r, default_variant(r.d.lattice, r.d.precision));
+// One launch of variant v (validated when it was set) on run r: reads buffer
+// cur, writes the other, advances the run by v.fuse steps.
+void launch_variant(lbm_cde* h, Run& r, const Variant& v, hipStream_t s) {
+  find_step(r, v)(make_args(h, r, r.cur, &v), s);
+  r.cur ^= 1;
+  r.steps += v.fuse;
+}
+
+// Enqueue n steps of run r (fewer where its budget ends first): launches of
+// its variant while they fit, one-step launches for the rest.  With `even`,
+// one multi-step launch is traded for one-step launches where that makes the
+// number of launches even (a captured graph must leave the state in the
+// buffer it started from).  Returns the number of launches.
+int64_t enqueue_run(lbm_cde* h, Run& r, int64_t n, hipStream_t s, bool even = false) {
+  if (r.d.max_steps >= 0) n = std::min<int64_t>(n, std::max<int64_t>(r.d.max_steps - r.steps, 0));
+  const int T = r.var.fuse;
+  int64_t q = T > 1 ? n / T : 0, rest = n - q * T;
+  if (even && T > 1 && q > 0 && ((q + rest) & 1)) {
+    q -= 1;
+    rest += T;
+  }
+  for (int64_t k = 0; k < q; ++k) launch_variant(h, r, r.var, s);
+  const Variant& v1 = T > 1 ? r.var1 : r.var;
+  for (int64_t k = 0; k < rest; ++k) launch_variant(h, r, v1, s);
+  return q + rest;
 }
 
 int launch_steps(lbm_cde* h, hipStream_t s, int64_t n) {
-  for (int64_t t = 0; t < n; ++t) {
-    for (auto& r : h->runs) {
-      if (r.d.max_steps >= 0 && r.steps >= r.d.max_steps) continue;
-      const RunArgs a = make_args(h, r, (int)(r.steps & 1));
-      pick_step(h, r)(a, s);
-      r.steps += 1;
-    }
-  }
+  for (auto& r : h->runs) enqueue_run(h, r, n, s);
   HIP_TRY(h, hipGetLastError());
   return LBM_CDE_OK;
 }
@@ -752,6 +824,7 @@ void drop_graphs(lbm_cde* h) {
       (void)hipGraphExecDestroy(g);
       g = nullptr;
     }
+  h->graph_off = false;
   for (auto* m : {&h->batch_graphs, &h->sample_graphs}) {
     for (auto& kv : *m) (void)hipGraphExecDestroy(kv.second);
     m->clear();
@@ -760,25 +833,26 @@ void drop_graphs(lbm_cde* h) {
   h->adj_graphs.clear();
 }
 
-// Capture kGraphSteps steps starting from parity p on the private stream.
+// Capture kGraphSteps steps of every run, each starting from buffer p, on
+// the private stream.  Callers make sure that every run has kGraphSteps
+// steps of budget left.  A run whose steps take an odd number of launches
+// would end in the other buffer: then no graph is kept (graph_off) and the
+// steps are launched one call at a time.
 int build_graph(lbm_cde* h, int p) {
-  std::vector<int64_t> saved;
+  std::vector<std::pair<int64_t, int>> saved;
   for (auto& r : h->runs) {
-    saved.push_back(r.steps);
-    r.steps = p;  // only the parity matters for the captured launches
+    saved.emplace_back(r.steps, r.cur);
+    r.cur = p;
   }
+  bool even = true;
   HIP_TRY(h, hipStreamBeginCapture(h->capture, hipStreamCaptureModeThreadLocal));
-  for (int t = 0; t < kGraphSteps; ++t)
-    for (auto& r : h->runs) {
-      const RunArgs a = make_args(h, r, (int)(r.steps & 1));
-      pick_step(h, r)(a, h->capture);
-      r.steps += 1;
-    }
+  for (auto& r : h->runs) even = (enqueue_run(h, r, kGraphSteps, h->capture, true) % 2 == 0) && even;
   hipGraph_t g = nullptr;
   hipError_t e = hipStreamEndCapture(h->capture, &g);
-  for (size_t i = 0; i < h->runs.size(); ++i) h->runs[i].steps = saved[i];
+  for (size_t i = 0; i < h->runs.size(); ++i) std::tie(h->runs[i].steps, h->runs[i].cur) = saved[i];
   if (e != hipSuccess) return fail(h, LBM_CDE_EHIP, "graph capture: %s", hipGetErrorString(e));
-  e = hipGraphInstantiate(&h->graph[p], g, nullptr, nullptr, 0);
+  if (even) e = hipGraphInstantiate(&h->graph[p], g, nullptr, nullptr, 0);
+  else h->graph_off = true;
   (void)hipGraphDestroy(g);
   if (e != hipSuccess) return fail(h, LBM_CDE_EHIP, "graph instantiate: %s", hipGetErrorString(e));
   return LBM_CDE_OK;
@@ -798,7 +872,7 @@ void launch_init(const Run& r, const RunArgs& a, const double* phi0, hipStream_t
 }
 
 int reduce_into(lbm_cde* h, Run& r, int kind, double x_ref, double* out_dev) {
-  RunArgs a = make_args(h, r, (int)(r.steps & 1));
+  RunArgs a = make_args(h, r, r.cur);
   if (r.dbl)
     hipLaunchKernelGGL(k_reduce_partial<double>, dim3(RED_BLOCKS), dim3(RED_THREADS), 0, h->stream, a, r.Q, kind,
                        x_ref, r.red_partial);
@@ -909,7 +983,7 @@ const BatchEntry kBatch[] = {BATCH_ENTRY(128, true), BATCH_ENTRY(256, true), BAT
                              BATCH_ENTRY(128, false), BATCH_ENTRY(256, false), BATCH_ENTRY(512, false)};
 
 const BatchEntry* find_batch(const Variant& v) {
-  if (v.by != 1 || v.ny != 1 || v.xcd != 0 || v.grid < 0) return nullptr;
+  if (v.by != 1 || v.ny != 1 || v.xcd != 0 || v.grid < 0 || v.fuse != 1) return nullptr;
   for (const auto& e : kBatch)
     if (e.bx == v.bx && e.nt == v.nt) return &e;
   return nullptr;
@@ -1019,7 +1093,10 @@ int init_runs(lbm_cde* h, const lbm_cde_run_desc* runs, int32_t nruns, const dou
     r.var = default_variant(r.d.lattice, r.d.precision);
     if (r.split && h->env16_set) r.var = h->env16;
     if (h->env_variant && !r.half) r.var = r.d.lattice == LBM_CDE_D3Q15 ? h->env3 : h->env;
-    if (!find_step(r, r.var)) return fail_init(LBM_CDE_EINVAL, "run %d: launch variant not built", i);
+    if (r.var.fuse == 1) r.var1 = r.var;
+    else r.var1 = default_variant(r.d.lattice, r.d.precision);
+    if (!find_step(r, r.var) || !find_step(r, r.var1))
+      return fail_init(LBM_CDE_EINVAL, "run %d: launch variant not built", i);
     // host tables are copied during init; keep no pointer to caller memory
     r.d.u_tables = nullptr;
     r.d.u_field = nullptr;
@@ -1196,8 +1273,10 @@ int capture_batch(lbm_cde* h, int64_t steps, double* hist, unsigned grid, hipGra
 
 void advance_host_clock(lbm_cde* h, int64_t n) {
   h->global_steps += n;
-  for (auto& r : h->runs)
+  for (auto& r : h->runs) {
     r.steps = (r.d.max_steps >= 0 && h->global_steps > r.d.max_steps) ? r.d.max_steps : h->global_steps;
+    r.cur = (int)(r.steps & 1);  // the batched kernels take the buffer from the step's parity
+  }
 }
 
 int batch_step(lbm_cde* h, int64_t n) {
@@ -1246,15 +1325,18 @@ bool cache_lookup(const std::string& key, Variant& v) {
   if (!path) return false;
   FILE* f = std::fopen(path, "r");
   if (!f) return false;
-  char k[256];
-  int bx, by, ny, nt, xcd, grid;
+  char line[512], k[256];
+  int bx, by, ny, nt, xcd, grid, fuse;
   double ms;
   bool found = false;
-  while (std::fscanf(f, "%255s %d %d %d %d %d %d %lf", k, &bx, &by, &ny, &nt, &xcd, &grid, &ms) == 8)
-    if (key == k) {
-      v = Variant{bx, by, ny, nt != 0, xcd, grid};
+  while (std::fgets(line, sizeof line, f)) {
+    fuse = 1;  // lines without the steps-per-launch field are one-step variants
+    if (std::sscanf(line, "%255s %d %d %d %d %d %d %lf %d", k, &bx, &by, &ny, &nt, &xcd, &grid, &ms, &fuse) >= 8 &&
+        key == k) {
+      v = Variant{bx, by, ny, nt != 0, xcd, grid, fuse};
       found = true;  // the last entry wins
     }
+  }
   std::fclose(f);
   return found;
 }
@@ -1263,7 +1345,8 @@ void cache_store(const std::string& key, const Variant& v, double ms) {
   const char* path = std::getenv("LBM_CDE_TUNE_CACHE");
   if (!path) return;
   if (FILE* f = std::fopen(path, "a")) {
-    std::fprintf(f, "%s %d %d %d %d %d %d %.6f\n", key.c_str(), v.bx, v.by, v.ny, (int)v.nt, v.xcd, v.grid, ms);
+    std::fprintf(f, "%s %d %d %d %d %d %d %.6f %d\n", key.c_str(), v.bx, v.by, v.ny, (int)v.nt, v.xcd, v.grid, ms,
+                 v.fuse);
     std::fclose(f);
   }
 }
@@ -1273,10 +1356,7 @@ void cache_store(const std::string& key, const Variant& v, double ms) {
 int time_variant(lbm_cde* h, Run& r, const Variant& v, int trials, double* ms) {
   StepFn fn = find_step(r, v);
   if (!fn) return LBM_CDE_EINVAL;
-  const Variant saved = r.var;
-  r.var = v;
-  const RunArgs a = make_args(h, r, (int)(r.steps & 1));
-  r.var = saved;
+  const RunArgs a = make_args(h, r, r.cur, &v);
   hipEvent_t e0, e1;
   HIP_TRY(h, hipEventCreate(&e0));
   HIP_TRY(h, hipEventCreate(&e1));
@@ -1290,7 +1370,7 @@ int time_variant(lbm_cde* h, Run& r, const Variant& v, int trials, double* ms) {
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   HIP_TRY(h, hipGetLastError());
-  *ms = elapsed / trials;
+  *ms = elapsed / trials / v.fuse;  // per step
   return LBM_CDE_OK;
 }
 
@@ -1335,6 +1415,10 @@ std::vector<Variant> run_candidates(const Run& r) {
       for (const auto& e : kSteps3) add(Variant{e.bx, e.by, e.ny, e.nt, xcd});
     } else {
       for (const auto& e : kSteps) add(Variant{e.bx, e.by, e.ny, e.nt, xcd});
+      for (const auto& e : kFused) {
+        const Variant c{e.bx, e.by, e.ny, true, xcd, 0, e.T};
+        if (find_step(r, c)) add(c);
+      }
     }
   }
   return out;
@@ -1371,6 +1455,7 @@ void variant_out(const Variant& v, int grid, int32_t* out) {
   out[3] = v.nt ? 1 : 0;
   out[4] = v.xcd;
   out[5] = grid;
+  out[6] = v.fuse;
 }
 
 }  // namespace
@@ -1529,20 +1614,20 @@ int lbm_cde_step(lbm_cde_handle h, int64_t n) {
     int parity = -1;
     for (auto& r : h->runs) {
       if (r.d.max_steps >= 0 && r.steps + kGraphSteps > r.d.max_steps) uniform = false;
-      const int p = (int)(r.steps & 1);
+      const int p = r.cur;
       if (parity < 0) parity = p;
       else if (parity != p) uniform = false;
     }
-    if (uniform && parity >= 0) {
-      if (!h->graph[parity]) {
-        const int rc = build_graph(h, parity);
-        if (rc) return rc;
-      }
+    if (uniform && parity >= 0 && !h->graph[parity] && !h->graph_off) {
+      const int rc = build_graph(h, parity);
+      if (rc) return rc;
+    }
+    if (uniform && parity >= 0 && h->graph[parity]) {
       HIP_TRY(h, hipGraphLaunch(h->graph[parity], h->stream));
       for (auto& r : h->runs) r.steps += kGraphSteps;
       done += kGraphSteps;
     } else {
-      const int64_t chunk = std::min<int64_t>(n - done, uniform ? kGraphSteps : 1);
+      const int64_t chunk = std::min<int64_t>(n - done, kGraphSteps);
       const int rc = launch_steps(h, h->stream, chunk);
       if (rc) return rc;
       done += chunk;
@@ -1561,7 +1646,7 @@ int lbm_cde_steps_done(lbm_cde_handle h, int32_t run, int64_t* steps) {
 int lbm_cde_moments(lbm_cde_handle h, int32_t run, double* phi_out) {
   Run* r = get_run(h, run);
   if (!r || !phi_out) return fail(h, LBM_CDE_EINVAL, "moments: bad handle, run or pointer");
-  const RunArgs a = make_args(h, *r, (int)(r->steps & 1));
+  const RunArgs a = make_args(h, *r, r->cur);
   const unsigned blocks = (unsigned)((r->nodes + 255) / 256);
   if (r->dbl) hipLaunchKernelGGL(k_moments<double>, dim3(blocks), dim3(256), 0, h->stream, a, r->Q, phi_out);
   else if (r->half) hipLaunchKernelGGL(k_moments<__half>, dim3(blocks), dim3(256), 0, h->stream, a, r->Q, phi_out);
@@ -1611,7 +1696,7 @@ int lbm_cde_reduce_noalloc(lbm_cde_handle h, int32_t run, int32_t kind, double x
     return fail(h, LBM_CDE_EINVAL,
                 "reduce_noalloc: run %d has %lld nodes; the static scratch holds the partials of at most %lld nodes",
                 run, (long long)r->nodes, (long long)(kScratchPartials * kNodesPerPartial));
-  const RunArgs a = make_args(h, *r, (int)(r->steps & 1));
+  const RunArgs a = make_args(h, *r, r->cur);
   double* partial = h->scratch_dev;  // every partial in [0, nb) is written before it is read
   if (r->dbl)
     hipLaunchKernelGGL(k_reduce_partial<double>, dim3((unsigned)nb), dim3(RED_THREADS), 0, h->stream, a, r->Q, kind,
@@ -1746,12 +1831,15 @@ int lbm_cde_tune(lbm_cde_handle h, int32_t trials) {
   for (auto& r : h->runs) {
     const std::string key = tune_key(r);
     Variant v;
-    if (cache_lookup(key, v) && find_step(r, v)) {
+    Variant v1;
+    if (cache_lookup(key, v) && find_step(r, v) &&
+        (v.fuse == 1 || (cache_lookup(key + "/1", v1) && v1.fuse == 1 && find_step(r, v1)))) {
       r.var = v;
+      r.var1 = v.fuse == 1 ? v : v1;
       continue;
     }
-    double best = 1e300;
-    Variant best_v = r.var;
+    double best = 1e300, best1 = 1e300;
+    Variant best_v = r.var, best_v1 = r.var1;
     for (const Variant& c : run_candidates(r)) {
       double ms = 0.0;
       const int rc = time_variant(h, r, c, trials, &ms);
@@ -1760,9 +1848,15 @@ int lbm_cde_tune(lbm_cde_handle h, int32_t trials) {
         best = ms;
         best_v = c;
       }
+      if (c.fuse == 1 && ms < best1) {
+        best1 = ms;
+        best_v1 = c;
+      }
     }
     r.var = best_v;
+    r.var1 = best_v1;
     cache_store(key, best_v, best);
+    if (best_v.fuse != 1) cache_store(key + "/1", best_v1, best1);
   }
   drop_graphs(h);  // captured graphs hold the previous kernels
   return LBM_CDE_OK;
@@ -1801,14 +1895,16 @@ int lbm_cde_variant_at(lbm_cde_handle h, int32_t run, int32_t index, int32_t* ou
 int lbm_cde_set_variant(lbm_cde_handle h, int32_t run, const int32_t* v) {
   Run* r = get_run(h, run);
   if (!r || !v) return fail(h, LBM_CDE_EINVAL, "set_variant: bad handle, run or pointer");
-  const Variant c{v[0], v[1], v[2], v[3] != 0, v[4], v[5]};
+  const Variant c{v[0], v[1], v[2], v[3] != 0, v[4], v[5], v[6]};
   if (h->batched) return apply_batch_variant(h, c, nullptr);
   if (c.grid != 0 || c.xcd < 0 || c.xcd > 2 || !find_step(*r, c))
-    return fail(h, LBM_CDE_EINVAL, "set_variant: variant %dx%dx%d nt=%d order=%d grid=%d is not built for run %d",
-                c.bx, c.by, c.ny, (int)c.nt, c.xcd, c.grid, run);
+    return fail(h, LBM_CDE_EINVAL,
+                "set_variant: variant %dx%dx%d nt=%d order=%d grid=%d steps=%d is not built for run %d", c.bx, c.by,
+                c.ny, (int)c.nt, c.xcd, c.grid, c.fuse, run);
   if (c.xcd == 2 && tile_rows(*r, c) % 8 != 0)
     return fail(h, LBM_CDE_EINVAL, "set_variant: the row-interleaved order needs a multiple of 8 tile rows");
   r->var = c;
+  if (c.fuse == 1) r->var1 = c;
   drop_graphs(h);
   return LBM_CDE_OK;
 }
@@ -1824,9 +1920,9 @@ int lbm_cde_get_state(lbm_cde_handle h, int32_t run, void* dst) {
   Run* r = get_run(h, run);
   if (!r || !dst) return fail(h, LBM_CDE_EINVAL, "get_state: bad handle, run or pointer");
   const size_t pb = (size_t)r->Q * r->plane * r->elem;
-  HIP_TRY(h, hipMemcpyAsync(dst, r->pop[r->steps & 1], pb, hipMemcpyDeviceToDevice, h->stream));
+  HIP_TRY(h, hipMemcpyAsync(dst, r->pop[r->cur], pb, hipMemcpyDeviceToDevice, h->stream));
   if (r->split)
-    HIP_TRY(h, hipMemcpyAsync((char*)dst + align_up(pb), r->phi[r->steps & 1], sizeof(float) * r->nodes,
+    HIP_TRY(h, hipMemcpyAsync((char*)dst + align_up(pb), r->phi[r->cur], sizeof(float) * r->nodes,
                               hipMemcpyDeviceToDevice, h->stream));
   return LBM_CDE_OK;
 }
@@ -1839,9 +1935,9 @@ int lbm_cde_set_state(lbm_cde_handle h, int32_t run, const void* src, int64_t st
     return fail(h, LBM_CDE_EINVAL, "set_state: step count beyond the run's budget");
   r->steps = steps;
   const size_t pb = (size_t)r->Q * r->plane * r->elem;
-  HIP_TRY(h, hipMemcpyAsync(r->pop[steps & 1], src, pb, hipMemcpyDeviceToDevice, h->stream));
+  HIP_TRY(h, hipMemcpyAsync(r->pop[r->cur], src, pb, hipMemcpyDeviceToDevice, h->stream));
   if (r->split)
-    HIP_TRY(h, hipMemcpyAsync(r->phi[steps & 1], (const char*)src + align_up(pb), sizeof(float) * r->nodes,
+    HIP_TRY(h, hipMemcpyAsync(r->phi[r->cur], (const char*)src + align_up(pb), sizeof(float) * r->nodes,
                               hipMemcpyDeviceToDevice, h->stream));
   return LBM_CDE_OK;
 }

@@ -1,0 +1,214 @@
+"""Several D2Q9 steps per launch (the LDS-blocked kernel) against one-step
+launches and the FP64 oracle.
+
+A multi-step launch computes the intermediate steps of a tile and its halo in
+LDS with the same per-node arithmetic as the one-step kernel, so every result
+must be bitwise that of the run's default (one-step) variant:
+
+* every multi-step variant (steps per launch 2-5, each tile shape, each block
+  order) over call sequences whose counts leave one-step remainders, fill
+  captured graphs (32 steps) and read the state in between; the final state
+  also against the oracle;
+* the velocity as a constant, a separable product (whose factors the later
+  steps of a launch take from LDS) and a per-node field;
+* checkpoint and restart (get_state / set_state) in the middle of multi-step
+  stepping, with the run's step budget ending inside a launch's span;
+* a per-node D field (per-node relaxation parameters) and a per-node velocity
+  field replaced between calls;
+* a handle of two runs of which only one steps several steps per launch, so
+  the runs' buffers drift apart and the graph path is left;
+* grids too small for a tile and its halo, and runs with walls, are refused.
+"""
+import numpy as np
+import pytest
+
+from oracle import lbm as O
+from paper_1404_2363_amd import workloads as W
+from state_views import populations
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": 1e-12, "fp32": 1e-5}
+
+
+def _phi(s, run=0):
+    return s.phi(run).cpu().numpy()
+
+
+def _pops(s, wl, precision):
+    """Stored populations (9, nodes): the state without the padding between planes."""
+    return populations(s.get_state().cpu().numpy(), 9, wl.nodes, precision)[0]
+
+
+def _multi(s, run=0):
+    return [v for v in s.variants(run) if v["steps_per_launch"] > 1]
+
+
+def rel(a, b):
+    return float(np.abs(a - b).max() / np.abs(b).max())
+
+
+@pytest.mark.parametrize("precision,velocity", [("fp64", "separable"), ("fp32", "separable"), ("fp32", "const")])
+def test_every_multi_step_variant(precision, velocity):
+    import dataclasses
+    from paper_1404_2363_amd.solver import Solver
+    seq = [1, 5, 32, 7, 64, 3]
+    wl = W.cellular(nx=203, ny=150, steps=sum(seq), n_hills=4, sigma=7.0)
+    if velocity == "const":
+        wl = dataclasses.replace(wl, u_sep=None, u_const=np.array([0.04, -0.03]))
+    ref = Solver(wl, precision)
+    assert ref.variant()["steps_per_launch"] == 1
+    phis = []
+    for n in seq:
+        ref.step(n)
+        phis.append(_phi(ref))
+    state = _pops(ref, wl, precision)
+    variants = _multi(ref)
+    ref.close()
+    spl = {v["steps_per_launch"] for v in variants}
+    print(f"case multi-step variants 203x150 {precision} {velocity} u: {len(variants)} variants, "
+          f"steps per launch {sorted(spl)}", flush=True)
+    assert spl >= {2, 3, 4, 5} and len(variants) >= 18     # 9 shapes x block orders 0 and 1
+    for v in variants:
+        s = Solver(wl, precision)
+        s.set_variant(v)
+        assert s.variant() == v
+        for n, p in zip(seq, phis):
+            s.step(n)
+            np.testing.assert_array_equal(_phi(s), p, err_msg=str(v))
+        np.testing.assert_array_equal(_pops(s, wl, precision), state, err_msg=str(v))
+        assert s.steps_done() == sum(seq)
+        s.close()
+    oref, _ = O.run_workload(wl, steps=sum(seq))
+    err = rel(phis[-1], oref)
+    print(f"oracle error {err:.2e}", flush=True)
+    assert err <= TOL[precision]
+
+
+def test_checkpoint_restart_and_budget():
+    from paper_1404_2363_amd.solver import Solver
+    wl = W.cellular(nx=160, ny=96, steps=101, n_hills=3, sigma=6.0)
+    ref = Solver(wl, "fp32", max_steps=101)
+    ref.step(200)                       # stops at the budget
+    assert ref.steps_done() == 101
+    end = _phi(ref)
+    ref.close()
+    for T in (3, 4):
+        a = Solver(wl, "fp32", max_steps=101)
+        v = next(v for v in _multi(a) if v["steps_per_launch"] == T and v["block_order"] == 0)
+        print(f"case checkpoint/budget 160x96 fp32 {v}", flush=True)
+        a.set_variant(v)
+        a.step(37)                      # 12 or 9 multi-step launches and a remainder
+        ck, t0 = a.get_state(), a.steps_done()
+        a.step(200)
+        assert a.steps_done() == 101
+        np.testing.assert_array_equal(_phi(a), end)
+        b = Solver(wl, "fp32", max_steps=101)
+        b.set_variant(v)
+        b.set_state(ck, t0)
+        b.step(64)
+        b.step(64)
+        assert b.steps_done() == 101
+        np.testing.assert_array_equal(_phi(b), end)
+        a.close()
+        b.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_per_node_diffusion_field(precision):
+    from paper_1404_2363_amd.solver import Solver
+    nx, ny, steps = 150, 72, 45
+    rng = W.rng_for(93, 17)
+    D = W.dfield_from(*(W.fourier_field(rng, nx, ny, kmax=2) for _ in range(3)))
+    spec = W.GaussianSum(np.array([[nx * 0.4, ny * 0.55]]), np.ones(1), np.array([nx / 9]), (float(nx), float(ny)))
+    wl = W.Workload("dfield_periodic", "d2q9", (nx, ny), ("periodic", "periodic"), steps, spec, D_field=D,
+                    u_const=np.array([0.03, -0.02]))
+    ref = Solver(wl, precision, heat=[1.0, 1.0])
+    ref.step(steps)
+    want = _phi(ref)
+    variants = _multi(ref)
+    ref.close()
+    print(f"case per-node D 150x72 x {steps} {precision}: {len(variants)} multi-step variants", flush=True)
+    for v in variants:
+        if v["block_order"] != 0:
+            continue
+        s = Solver(wl, precision, heat=[1.0, 1.0])
+        s.set_variant(v)
+        s.step(steps)
+        np.testing.assert_array_equal(_phi(s), want, err_msg=str(v))
+        s.close()
+    prob = O.Problem("d2q9", (nx, ny), wl.walls, wl.u(), D, heat_rule=[1.0, 1.0])
+    f = prob.equilibrium(wl.phi0())
+    for _ in range(steps):
+        f = prob.step(f)
+    assert rel(want, O.phi_of(f)) <= TOL[precision]
+
+
+def test_velocity_field_replaced_between_calls():
+    from paper_1404_2363_amd.solver import Solver
+    import torch
+    wl = W.drifting_cellular(nx=140, ny=90, steps=42, n_hills=4, sigma=5.0, U0=0.08, drift=0.7)
+    fields = [torch.tensor(np.asarray(wl.u_schedule(7 * k)), dtype=torch.float64, device="cuda:0") for k in range(6)]
+
+    def run(v):
+        s = Solver(wl, "fp32")
+        if v is not None:
+            s.set_variant(v)
+        for u in fields:
+            s.set_velocity(u)
+            s.step(7)
+        out = _phi(s)
+        s.close()
+        return out
+
+    want = run(None)
+    s = Solver(wl, "fp32")
+    variants = [v for v in _multi(s) if v["block_order"] == 0]
+    s.close()
+    print(f"case velocity field replaced every 7 steps 140x90: {len(variants)} multi-step variants", flush=True)
+    for v in variants:
+        np.testing.assert_array_equal(run(v), want, err_msg=str(v))
+
+
+def test_two_runs_one_multi_step():
+    from paper_1404_2363_amd.solver import Solver
+    wa = W.cellular(nx=180, ny=100, steps=100, n_hills=3, sigma=6.0)
+    wb = W.cellular(nx=96, ny=64, steps=100, n_hills=2, sigma=5.0, seed_id=3)
+    seq = [5, 64, 3, 32]
+    want = []
+    for wl, prec in ((wa, "fp32"), (wb, "fp64")):
+        s = Solver(wl, prec)
+        s.step(sum(seq))
+        want.append(_phi(s))
+        s.close()
+    s = Solver([wa, wb], per_run=[{"precision": "fp32"}, {"precision": "fp64"}])
+    v = next(v for v in _multi(s, 0) if v["steps_per_launch"] == 3 and v["block_order"] == 0)
+    print(f"case two runs, run 0 {v}", flush=True)
+    s.set_variant(v, run=0)
+    for n in seq:
+        s.step(n)
+    assert s.steps_done(0) == s.steps_done(1) == sum(seq)
+    np.testing.assert_array_equal(_phi(s, 0), want[0])
+    np.testing.assert_array_equal(_phi(s, 1), want[1])
+    s.close()
+
+
+def test_refused_where_a_tile_and_its_halo_do_not_fit():
+    from paper_1404_2363_amd import _lib as L
+    from paper_1404_2363_amd.solver import Solver
+    big = Solver(W.cellular(nx=160, ny=96, steps=1, n_hills=2, sigma=5.0), "fp32")
+    v = next(v for v in _multi(big) if v["block"] == (128, 4) and v["steps_per_launch"] == 4)
+    big.close()
+    # 128 + 2 * 3 = 134 columns are needed
+    small = Solver(W.cellular(nx=133, ny=96, steps=1, n_hills=2, sigma=5.0), "fp32")
+    assert all(not (u["block"] == (128, 4) and u["steps_per_launch"] == 4) for u in small.variants())
+    with pytest.raises(L.LbmCdeError) as e:
+        small.set_variant(v)
+    assert e.value.code == L.LBM_CDE_EINVAL
+    small.close()
+    walls = W.taylor_aris_channel(32, 12.0, 1.1, nx=300, steps=1, wall="bounce")
+    s = Solver(walls, "fp32")
+    assert not _multi(s)
+    with pytest.raises(L.LbmCdeError):
+        s.set_variant(v)
+    s.close()
