@@ -291,7 +291,7 @@ int lbm_cde_tune(lbm_cde_handle h, int32_t trials);
 
 /* The launch variant of run `run` into out[0..6] (layout above; out[5] is
  * the launch's actual number of blocks on a batched handle, else 0).  The
- * environment variables LBM_CDE_TILE = "BXxBYxNY", LBM_CDE_TILE3,
+ * environment variables LBM_CDE_TILE = "BXxBYxNY[xSTEPS]", LBM_CDE_TILE3,
  * LBM_CDE_NT, LBM_CDE_XCD, LBM_CDE_TILE16 = "BXxBY[xNT[xORDER]]" and
  * LBM_CDE_BATCH = "BX[xNT[xGRID]]", read by lbm_cde_init(), fix the initial
  * variant of D2Q9 FP64/FP32, D3Q15, FP16_SPLIT runs and batches. */

@@ -928,7 +928,9 @@ void parse_env(lbm_cde* h) {
   if (!t2 && !t3 && !nt && !xcd) return;
   h->env_variant = true;
   int bx, by, ny;
-  if (t2 && std::sscanf(t2, "%dx%dx%d", &bx, &by, &ny) == 3) h->env = Variant{bx, by, ny, false, 0};
+  int fuse = 1;
+  if (t2 && std::sscanf(t2, "%dx%dx%dx%d", &bx, &by, &ny, &fuse) >= 3)
+    h->env = Variant{bx, by, ny, false, 0, 0, fuse};
   if (t3 && std::sscanf(t3, "%dx%dx%d", &bx, &by, &ny) == 3) h->env3 = Variant{bx, by, ny, false, 0};
   h->env.nt = h->env3.nt = nt ? std::atoi(nt) != 0 : false;
   h->env.xcd = h->env3.xcd = xcd ? std::atoi(xcd) : 0;
