@@ -269,8 +269,8 @@ int lbm_cde_set_velocity(lbm_cde_handle h, int32_t run, const double* u);
  * launch over a flat list of block-x-wide row tiles) the number of blocks
  * of that launch (0: one block per tile; otherwise each block walks every
  * grid-th tile), and the number of steps one launch takes.  More than one
- * step per launch is built for D2Q9 FP64/FP32 runs periodic on both axes
- * whose axes span the tile (block x by block y times rows per thread nodes)
+ * step per launch is built for D2Q9 FP64/FP32 MRT-A or MRT-B3 runs periodic
+ * on both axes whose axes span the tile (block x by block y times rows per thread nodes)
  * plus that many steps minus one nodes on each side: the launch keeps the
  * intermediate steps of a tile and its halo in LDS (Eq. 5: a population
  * moves one node per step), so the state crosses HBM once per launch; the

@@ -40,6 +40,11 @@ struct Rel2 {
   R c34, c36, c54, c56;  // coupling coefficients of Eq. (31); zero for the standard S (Eq. 24)
   R nl;                  // 1 for the equilibria with u^2 terms (Eq. 38, 39), else 0
   R c2;                  // m2_eq(phi, 0) / phi: 1 for Eq. (38), else 2
+  // the rows of S divided by the squared norms of the rows of M (Eq. 12):
+  // the collision applies M^-1 = M^T diag(1/|M_k|^2) to S n
+  R k1, k2, k4, k6, k7, k8;
+  R g33, g34, g35, g36, g53, g54, g55, g56;
+  bool lin;  // equilibrium linear in phi and phi u (Eq. 37): no u^2 terms, m2_eq = 2 phi
 };
 
 template <typename R>
@@ -62,6 +67,22 @@ LBM_FORCEINLINE Rel2<R> make_rel2_vals(R axx, R axy, R ayy, R s4, R s6, double s
   r.c56 = modified ? (ayy * (R)0.5 - (R)1) * s6 : (R)0;
   r.nl = (model == LBM_CDE_MRT_B1 || model == LBM_CDE_MRT_B2) ? (R)1 : (R)0;
   r.c2 = model == LBM_CDE_MRT_B1 ? (R)1 : (R)2;
+  r.lin = model == LBM_CDE_MRT_A || model == LBM_CDE_MRT_B3;
+  const R i36 = (R)(1.0 / 36.0), i12 = (R)(1.0 / 12.0), i6 = (R)(1.0 / 6.0), i4 = (R)0.25;
+  r.k1 = r.s1 * i36;
+  r.k2 = r.s2 * i36;
+  r.k4 = r.s4 * i12;
+  r.k6 = r.s6 * i12;
+  r.k7 = r.s7 * i4;
+  r.k8 = r.s8 * i4;
+  r.g33 = r.axx * i6;
+  r.g34 = r.c34 * i6;
+  r.g35 = r.axy * i6;
+  r.g36 = r.c36 * i6;
+  r.g53 = r.axy * i6;
+  r.g54 = r.c54 * i6;
+  r.g55 = r.ayy * i6;
+  r.g56 = r.c56 * i6;
   return r;
 }
 
@@ -86,58 +107,78 @@ LBM_FORCEINLINE Rel2<R> node_rel2(const RunArgs& a, int64_t node) {
 }
 
 // The collision of one node, in place.  phi_ref = 0 for unshifted storage.
-template <typename R>
+// LIN = 1: the equilibrium is linear (r.lin: MRT-A, MRT-B3), LIN = 0: any
+// model through the general formulas, LIN = -1: chosen by r.lin at run time.
+// For a linear equilibrium both forms give the same increments; the linear
+// one skips the u^2 terms, whose coefficients are zero there.
+template <typename R, int LIN = -1>
 LBM_FORCEINLINE void collide_d2q9(R (&f)[9], R ux, R uy, R phi_ref, const Rel2<R>& r) {
-  const R sa = f[1] + f[2] + f[3] + f[4];
-  const R sd = f[5] + f[6] + f[7] + f[8];
-  const R phig = f[0] + sa + sd;
-  const R phi = phig + phi_ref;
-  // moments of the stored populations
-  const R m1 = (R)2 * sd - sa - (R)4 * f[0];
-  const R m2 = (R)4 * f[0] - (R)2 * sa + sd;
-  const R dx13 = f[1] - f[3];
-  const R dx58 = f[5] - f[6] - f[7] + f[8];  // diagonal x-flux
-  const R dy24 = f[2] - f[4];
-  const R dy56 = f[5] + f[6] - f[7] - f[8];  // diagonal y-flux
-  const R m3 = dx13 + dx58;
-  const R m4 = dx58 - (R)2 * dx13;
-  const R m5 = dy24 + dy56;
-  const R m6 = dy56 - (R)2 * dy24;
-  const R m7 = f[1] - f[2] + f[3] - f[4];
-  const R m8 = f[5] - f[6] + f[7] - f[8];
-  // non-equilibrium parts (the u^2 terms only for the MRT-B1/B2 equilibria)
-  const R jx = phi * ux, jy = phi * uy;
-  const R q = r.nl * phi;
-  const R u2 = ux * ux + uy * uy;
-  const R n1 = m1 + (R)2 * phig - (R)3 * q * u2;
-  const R n2 = m2 - r.c2 * phig + (R)3 * q * u2;
-  const R n3 = m3 - jx;
-  const R n4 = m4 + jx;
-  const R n5 = m5 - jy;
-  const R n6 = m6 + jy;
-  // relaxation increments, pre-divided by the squared row norms
-  const R a1 = r.s1 * n1 * (R)(1.0 / 36.0);
-  const R a2 = r.s2 * n2 * (R)(1.0 / 36.0);
-  const R a3 = (r.axx * n3 + r.c34 * n4 + r.axy * n5 + r.c36 * n6) * (R)(1.0 / 6.0);
-  const R a4 = r.s4 * n4 * (R)(1.0 / 12.0);
-  const R a5 = (r.axy * n3 + r.c54 * n4 + r.ayy * n5 + r.c56 * n6) * (R)(1.0 / 6.0);
-  const R a6 = r.s6 * n6 * (R)(1.0 / 12.0);
-  const R a7 = r.s7 * (m7 - q * (ux * ux - uy * uy)) * (R)0.25;
-  const R a8 = r.s8 * (m8 - q * ux * uy) * (R)0.25;
-  // f' = f - M^T a
-  const R ax = -a1 - (R)2 * a2;          // common to the axis populations
-  const R dg = (R)2 * a1 + a2;           // common to the diagonals
-  const R q3 = a3 - (R)2 * a4, q5 = a5 - (R)2 * a6;
-  const R p3 = a3 + a4, p5 = a5 + a6;
-  f[0] -= (R)4 * (a2 - a1);
-  f[1] -= ax + q3 + a7;
-  f[2] -= ax + q5 - a7;
-  f[3] -= ax - q3 + a7;
-  f[4] -= ax - q5 - a7;
-  f[5] -= dg + p3 + p5 + a8;
-  f[6] -= dg - p3 + p5 - a8;
-  f[7] -= dg - p3 - p5 + a8;
-  f[8] -= dg + p3 - p5 - a8;
+  if constexpr (LIN < 0) {
+    if (r.lin) collide_d2q9<R, 1>(f, ux, uy, phi_ref, r);
+    else collide_d2q9<R, 0>(f, ux, uy, phi_ref, r);
+    return;
+  } else {
+    const R sa = f[1] + f[2] + f[3] + f[4];
+    const R sd = f[5] + f[6] + f[7] + f[8];
+    const R phig = f[0] + sa + sd;
+    const R phi = phig + phi_ref;
+    // moments of the stored populations
+    const R m1 = (R)2 * sd - sa - (R)4 * f[0];
+    const R m2 = (R)4 * f[0] - (R)2 * sa + sd;
+    const R dx13 = f[1] - f[3];
+    const R dx58 = f[5] - f[6] - f[7] + f[8];  // diagonal x-flux
+    const R dy24 = f[2] - f[4];
+    const R dy56 = f[5] + f[6] - f[7] - f[8];  // diagonal y-flux
+    const R m3 = dx13 + dx58;
+    const R m4 = dx58 - (R)2 * dx13;
+    const R m5 = dy24 + dy56;
+    const R m6 = dy56 - (R)2 * dy24;
+    const R m7 = f[1] - f[2] + f[3] - f[4];
+    const R m8 = f[5] - f[6] + f[7] - f[8];
+    // non-equilibrium parts (the u^2 terms only for the MRT-B1/B2 equilibria)
+    const R jx = phi * ux, jy = phi * uy;
+    R n1, n2, n7, n8;
+    if constexpr (LIN == 1) {
+      n1 = m1 + (R)2 * phig;
+      n2 = m2 - (R)2 * phig;
+      n7 = m7;
+      n8 = m8;
+    } else {
+      const R q = r.nl * phi;
+      const R u2 = ux * ux + uy * uy;
+      n1 = m1 + (R)2 * phig - (R)3 * q * u2;
+      n2 = m2 - r.c2 * phig + (R)3 * q * u2;
+      n7 = m7 - q * (ux * ux - uy * uy);
+      n8 = m8 - q * ux * uy;
+    }
+    const R n3 = m3 - jx;
+    const R n4 = m4 + jx;
+    const R n5 = m5 - jy;
+    const R n6 = m6 + jy;
+    // relaxation increments S n, divided by the squared row norms
+    const R a1 = r.k1 * n1;
+    const R a2 = r.k2 * n2;
+    const R a3 = r.g33 * n3 + r.g34 * n4 + r.g35 * n5 + r.g36 * n6;
+    const R a4 = r.k4 * n4;
+    const R a5 = r.g53 * n3 + r.g54 * n4 + r.g55 * n5 + r.g56 * n6;
+    const R a6 = r.k6 * n6;
+    const R a7 = r.k7 * n7;
+    const R a8 = r.k8 * n8;
+    // f' = f - M^T a
+    const R ax = -a1 - (R)2 * a2;          // common to the axis populations
+    const R dg = (R)2 * a1 + a2;           // common to the diagonals
+    const R q3 = a3 - (R)2 * a4, q5 = a5 - (R)2 * a6;
+    const R p3 = a3 + a4, p5 = a5 + a6;
+    f[0] -= (R)4 * (a2 - a1);
+    f[1] -= ax + q3 + a7;
+    f[2] -= ax + q5 - a7;
+    f[3] -= ax - q3 + a7;
+    f[4] -= ax - q5 - a7;
+    f[5] -= dg + p3 + p5 + a8;
+    f[6] -= dg - p3 + p5 - a8;
+    f[7] -= dg - p3 - p5 + a8;
+    f[8] -= dg + p3 - p5 - a8;
+  }
 }
 
 // f_eq(phi, u) of the model, in double: m_eq is Eq. (37) for MRT-A and

@@ -12,7 +12,9 @@
 //   step T      pulls from LDS for the tile itself and stores to HBM.
 // Every node's step uses the same pull, velocity, relaxation and collision
 // arithmetic as the one-step kernel (tile_d2q9 without walls), so T steps of
-// this kernel equal T one-step launches bitwise.  HBM sees one read and one
+// this kernel equal T one-step launches bitwise.  It is built for the
+// equilibria linear in phi and phi u (MRT-A, Eq. 37, and MRT-B3), whose
+// collision has no u^2 terms.  HBM sees one read and one
 // write of the state per T steps (72 B per node for FP32, 144 B for FP64)
 // instead of per step; the price is the recomputed rings (the widened tiles'
 // extra collisions) and LDS traffic.  Halo nodes take periodic images, which
@@ -75,8 +77,8 @@ __global__ __launch_bounds__(BX * BY) void k_fused_d2q9(const RunArgs a) {
     } else {
       velocity2<R>(a, x, y, ux, uy);
     }
-    if (a.node_par) collide_d2q9<R>(f, ux, uy, phi_ref, node_rel2<R>(a, (int64_t)y * nx + x));
-    else collide_d2q9<R>(f, ux, uy, phi_ref, rc);
+    if (a.node_par) collide_d2q9<R, 1>(f, ux, uy, phi_ref, node_rel2<R>(a, (int64_t)y * nx + x));
+    else collide_d2q9<R, 1>(f, ux, uy, phi_ref, rc);
   };
 
   // step 1: HBM -> LDS over the whole widened tile

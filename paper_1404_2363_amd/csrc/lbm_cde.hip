@@ -749,12 +749,14 @@ const FusedEntry kFused[] = {FUSED_ENTRY(128, 4, 2, 2), FUSED_ENTRY(128, 4, 2, 3
                              FUSED_ENTRY(128, 4, 2, 5), FUSED_ENTRY(64, 4, 2, 3),  FUSED_ENTRY(64, 4, 2, 4),
                              FUSED_ENTRY(64, 8, 2, 3),  FUSED_ENTRY(64, 8, 2, 4),  FUSED_ENTRY(64, 8, 2, 5)};
 
-// A run can take T steps per launch when it is D2Q9 in FP64 or FP32,
-// periodic on both axes, each axis spans the tile plus T - 1 nodes on both
-// sides (halo nodes are periodic images taken with one wrap), and byte
-// offsets within a population plane fit 32 bits.
+// A run can take T steps per launch when it is D2Q9 in FP64 or FP32 with an
+// equilibrium linear in phi and phi u (MRT-A or MRT-B3), periodic on both
+// axes, each axis spans the tile plus T - 1 nodes on both sides (halo nodes
+// are periodic images taken with one wrap), and byte offsets within a
+// population plane fit 32 bits.
 bool fused_ok(const Run& r, const Variant& v) {
   return r.d.lattice == LBM_CDE_D2Q9 && !r.half && !r.split && !r.walls && r.d.nz == 1 &&
+         (r.d.model == LBM_CDE_MRT_A || r.d.model == LBM_CDE_MRT_B3) &&
          r.d.nx >= (int64_t)v.bx + 2 * (v.fuse - 1) && r.d.ny >= (int64_t)v.by * v.ny + 2 * (v.fuse - 1) &&
          (double)r.nodes * (double)r.elem < 4294967296.0 && r.d.nx < (1ll << 30) && r.d.ny < (1ll << 30) &&
          v.grid == 0;
