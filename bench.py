@@ -13,12 +13,17 @@ the dominant kernel and the FP64 CPU oracle timed on the host cores.
 Timing: after W warm-up steps each variant is timed in 5 blocks of at
 least K steps (a multiple of the library's 32-step captured graph, and at
 least 0.1 s), with HIP events on the stream the library launches on; the
-median per-step time is reported with the minimum and maximum.
+median per-step time is reported with the minimum and maximum.  The tuned
+variant of a run may take several steps per launch (LDS-blocked D2Q9); its
+launch is timed on its own (5 blocks of 40 back-to-back launches, median)
+for the roofline, whose bound is HBM (algorithmic bytes of a launch: the
+state read and written once) or VALU issue (the launch's VALU instructions
+from the committed instruction-count profile), whichever is nearer its peak.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--only NAME]
                        [--quick] [--no-cpu] [--no-tune] [--copy-probe]
 NAME: d2q9_4096_fp32 | d2q9_4096_fp64 | d2q9_4096_fp16 | d3q15_256_fp32 |
-      d3q15_256_fp64 | taylor_aris_batch | adjoint
+      d3q15_256_fp64 | taylor_aris_batch | unsteady | adjoint | adjoint_segment
 """
 import argparse
 import json
@@ -30,6 +35,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E peak
+# VALU issue rate without packed FP32 math (the library is built without it):
+# 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz lane instructions per second
+VALU_PEAK_TINSTR = 256 * 4 * 16 * 2.4e9 / 1e12
 # algorithmic bytes per lattice update: Q populations read + Q written
 BYTES_PER_LU = {("d2q9", "fp64"): 144, ("d2q9", "fp32"): 72, ("d2q9", "fp16"): 44,
                 ("d3q15", "fp64"): 240, ("d3q15", "fp32"): 120}
@@ -46,11 +54,20 @@ def kernel_tag(launch):
     return tag + (f"|steps{launch['steps_per_launch']}" if launch.get("steps_per_launch", 1) > 1 else "")
 
 
-def _profile(name):
+def kernel_name(launch, real):
+    """The step kernel a launch variant of a D2Q9 run stepped alone runs."""
+    T = launch.get("steps_per_launch", 1)
+    if T == 1:
+        return f"k_step_d2q9<{real}>"
+    bx, by = launch["block"]
+    return f"k_fused_d2q9<{real}, {bx}, {by}, {launch['rows_per_thread']}, {T}>"
+
+
+def _profile(name, path="traffic.json"):
     """The committed PMC record of a workload, or None when its kernel
     sources differ from what the counters were taken on."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "traffic.json")
+    path = os.path.join(ROOT, "profiles", path)
     try:
         rec = json.load(open(path))[name]
     except (OSError, KeyError, ValueError):
@@ -69,6 +86,40 @@ def profiled_traffic(name, launch):
     rec = _profile(name)
     k = None if rec is None else rec["kernels"].get(kernel_tag(launch))
     return None if k is None else k["traffic_bytes_per_launch"]
+
+
+def profiled_valu(name, launch):
+    """VALU wave instructions per launch (SQ_INSTS_VALU) from the committed
+    instruction-count profile of this kernel and launch variant, or None when
+    the kernel source or the variant differs from what was counted."""
+    rec = _profile(name, "valu.json")
+    k = None if rec is None else rec["kernels"].get(kernel_tag(launch))
+    return None if k is None else k["valu_wave_instr_per_launch"]
+
+
+def roofline(v, name, real):
+    """The roofline of a run's step kernel: the HBM one (algorithmic bytes of
+    a launch over its measured duration) and, where the kernel's VALU
+    instruction count is profiled, the VALU-issue one (lane instructions of a
+    launch over the same duration); the bound is the one nearer its peak."""
+    launch = v["launch"]
+    hbm = {"bound": "hbm", "achieved": v["achieved_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": v["hbm_frac"]}
+    out = dict(hbm)
+    valu = profiled_valu(name, launch)
+    if valu is not None:
+        t = valu * 64 / (v["ms_per_launch"] * 1e-3) / 1e12
+        alu = {"bound": "alu", "achieved": t, "peak": VALU_PEAK_TINSTR, "unit": "T VALU lane instructions/s",
+               "frac": t / VALU_PEAK_TINSTR, "valu_wave_instructions_per_launch": valu}
+        if alu["frac"] > hbm["frac"]:
+            out = dict(alu)
+            out["hbm"] = hbm
+        else:
+            out["alu"] = alu
+    out.update({"traffic": v.get("traffic"), "kernel": kernel_name(launch, real), "launch": launch,
+                "bytes_per_launch": v["bytes_per_launch"], "ms_per_launch": v["ms_per_launch"],
+                "steps_per_launch": v["steps_per_launch"]})
+    return out
 
 
 def profiled_segment_traffic(K):
@@ -128,6 +179,26 @@ def time_blocks(advance, steps, warmup):
             "wall_s": wall}
 
 
+def time_launch(advance, steps_per_launch, per_block=40):
+    """Average duration of one launch of a run's kernel: ``advance(T)`` with T
+    the variant's steps per launch (below the graph length) enqueues exactly
+    one launch; REPS blocks of ``per_block`` back-to-back launches are timed
+    with HIP events on the library's stream and the median is returned."""
+    import torch
+    advance(steps_per_launch)
+    torch.cuda.synchronize()
+    out = []
+    for _ in range(REPS):
+        start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        start.record()
+        for _ in range(per_block):
+            advance(steps_per_launch)
+        stop.record()
+        torch.cuda.synchronize()
+        out.append(start.elapsed_time(stop) / 1e3 / per_block)
+    return sorted(out)[len(out) // 2]
+
+
 def check_against_default(s, default, steps=GRAPH_STEPS):
     """The tuned variant of a run stepped alone against its default variant
     (which the parity tests compare with the oracle at this grid size): from
@@ -155,18 +226,22 @@ def gpu_variant(wl, precision, steps, warmup, tune=True):
     if tune:
         s.tune(10)
     tm = time_blocks(s.step, steps, warmup)
-    nonfinite = s.nonfinite()
     var = s.variant()
+    T = var.get("steps_per_launch", 1)
+    t_launch = time_launch(s.step, T)
+    nonfinite = s.nonfinite()
     same = check_against_default(s, default) if var != default else True
     s.close()
     t_step = tm["median"]
+    # a launch reads and writes the state once, whatever its number of steps
     bpl = BYTES_PER_LU[(wl.lattice, precision)]
-    gbs = wl.nodes * bpl / t_step / 1e9
+    gbs = wl.nodes * bpl / t_launch / 1e9
     return {"precision": precision, "nodes": wl.nodes, "ms_per_step": t_step * 1e3,
             "ms_per_step_min_max": [tm["min"] * 1e3, tm["max"] * 1e3], "timed_blocks": tm["blocks"],
-            "steps_per_block": tm["steps_per_block"], "mlups": wl.nodes / t_step / 1e6, "achieved_gbs": gbs,
-            "bytes_per_lu": bpl, "hbm_frac": gbs / HBM_PEAK_GBS, "wall_s": tm["wall_s"], "nonfinite": nonfinite,
-            "launch": var, "bitwise_equal_to_default_variant": same}
+            "steps_per_block": tm["steps_per_block"], "mlups": wl.nodes / t_step / 1e6,
+            "steps_per_launch": T, "ms_per_launch": t_launch * 1e3, "bytes_per_launch": wl.nodes * bpl,
+            "achieved_gbs": gbs, "bytes_per_lu": bpl / T, "hbm_frac": gbs / HBM_PEAK_GBS, "wall_s": tm["wall_s"],
+            "nonfinite": nonfinite, "launch": var, "bitwise_equal_to_default_variant": same}
 
 
 def batch_variant(runs, precision, steps, warmup, tune=True):
@@ -458,12 +533,13 @@ def main():
         log(f"unsteady: 4096^2 FP32 with a new velocity field every step, {k} steps")
         out["d2q9_4096_fp32_unsteady_u"] = unsteady_variant("fp32", k, args.warmup)
         log(f"unsteady: {out['d2q9_4096_fp32_unsteady_u']['mlups']:.0f} MLUPS")
-    if (not args.only and not args.quick) or args.only == "adjoint":
+    if (not args.only and not args.quick) or args.only in ("adjoint", "adjoint_segment"):
         log("adjoint: one 2048^2 checkpoint segment of 16 steps (forward recompute + reverse)")
         out["adjoint_segment_2048_fp32"] = adjoint_segment_variant()
         seg = out["adjoint_segment_2048_fp32"]
         seg["traffic"] = profiled_segment_traffic(seg["segment_steps"])
         log(f"adjoint segment: {out['adjoint_segment_2048_fp32']['achieved_gbs']:.0f} GB/s")
+    if (not args.only and not args.quick) or args.only == "adjoint":
         log("adjoint: one 512^2 x 2000-step gradient")
         out["inverse_adjoint_fp32"] = adjoint_variant("fp32")
         log(f"adjoint: {out['inverse_adjoint_fp32']['seconds_per_gradient']:.3f} s per gradient")
@@ -503,11 +579,7 @@ def main():
         "config": {"workload": "D2Q9 modified MRT, 4096x4096 periodic, cellular u (U0=0.05), D eigenvalues "
                                "0.01/0.1 rotated 30 deg, 64 Gaussian hills sigma=32, FP32 shifted storage",
                    "nodes": wl2.nodes},
-        "roofline": {"bound": "hbm", "achieved": main_v["achieved_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": main_v["hbm_frac"],
-                     "traffic": main_v.get("traffic", profiled_traffic("d2q9_4096_fp32", main_v["launch"])),
-                     "kernel": "k_step_d2q9<float>", "launch": main_v["launch"],
-                     "bytes_per_launch": 72 * wl2.nodes},
+        "roofline": roofline(main_v, "d2q9_4096_fp32", "float"),
         "variants": out,
         "cpu_baseline": cpu,
     }

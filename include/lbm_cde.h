@@ -279,9 +279,10 @@ int lbm_cde_set_velocity(lbm_cde_handle h, int32_t run, const double* u);
  * to be valid.  Results are bitwise the same for every variant. */
 
 /* Autotuner: time `trials` launches of every compiled variant (those listed
- * by lbm_cde_variant_at) and keep the one with the least time per step, per
- * run (and the fastest one-step variant for left-over steps), or once for a
- * batched handle.  Each timed launch reads the current state and overwrites
+ * by lbm_cde_variant_at) and keep, per run, the one that takes a 32-step
+ * block (the captured-graph length) in the least time, the steps a
+ * multi-step variant leaves over going to the fastest one-step variant
+ * (kept for them), or once for a batched handle the fastest.  Each timed launch reads the current state and overwrites
  * only the other population buffer, so the simulation state is unchanged.
  * If the environment variable LBM_CDE_TUNE_CACHE names a file, results are
  * looked up there (keyed by GPU architecture, lattice, precision, grid and

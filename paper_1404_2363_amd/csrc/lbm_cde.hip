@@ -1842,19 +1842,29 @@ int lbm_cde_tune(lbm_cde_handle h, int32_t trials) {
       r.var1 = v.fuse == 1 ? v : v1;
       continue;
     }
-    double best = 1e300, best1 = 1e300;
-    Variant best_v = r.var, best_v1 = r.var1;
-    for (const Variant& c : run_candidates(r)) {
-      double ms = 0.0;
-      const int rc = time_variant(h, r, c, trials, &ms);
+    // time every candidate (per step), then rank by the time of a captured
+    // kGraphSteps-step block: a multi-step variant leaves kGraphSteps mod T
+    // steps to the fastest one-step variant
+    const std::vector<Variant> cands = run_candidates(r);
+    std::vector<double> per_step(cands.size());
+    double best1 = 1e300;
+    Variant best_v1 = r.var1;
+    for (size_t i = 0; i < cands.size(); ++i) {
+      const int rc = time_variant(h, r, cands[i], trials, &per_step[i]);
       if (rc) return rc;
-      if (ms < best) {
-        best = ms;
-        best_v = c;
+      if (cands[i].fuse == 1 && per_step[i] < best1) {
+        best1 = per_step[i];
+        best_v1 = cands[i];
       }
-      if (c.fuse == 1 && ms < best1) {
-        best1 = ms;
-        best_v1 = c;
+    }
+    double best = 1e300;
+    Variant best_v = r.var;
+    for (size_t i = 0; i < cands.size(); ++i) {
+      const int T = cands[i].fuse, left = kGraphSteps % T;
+      const double block = per_step[i] * (kGraphSteps - left) + best1 * left;
+      if (block / kGraphSteps < best) {
+        best = block / kGraphSteps;
+        best_v = cands[i];
       }
     }
     r.var = best_v;
