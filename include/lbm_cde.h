@@ -275,8 +275,10 @@ int lbm_cde_set_velocity(lbm_cde_handle h, int32_t run, const double* u);
  * intermediate steps of a tile and its halo in LDS (Eq. 5: a population
  * moves one node per step), so the state crosses HBM once per launch; the
  * steps left over when a call's count is not a multiple go one per launch.
- * A batched handle has one variant for all its runs; the run index only has
- * to be valid.  Results are bitwise the same for every variant. */
+ * A run that can take several steps per launch starts with 4 (64 x 16
+ * tiles in FP32, 64 x 8 in FP64), any other with one.  A batched handle has
+ * one variant for all its runs; the run index only has to be valid.  Results
+ * are bitwise the same for every variant. */
 
 /* Autotuner: time `trials` launches of every compiled variant (those listed
  * by lbm_cde_variant_at) and keep, per run, the one that takes a 32-step

@@ -1095,6 +1095,12 @@ int init_runs(lbm_cde* h, const lbm_cde_run_desc* runs, int32_t nruns, const dou
     r.walls = false;
     for (int a = 0; a < r.dim; ++a) r.walls |= r.d.bc[a] != LBM_CDE_PERIODIC;
     r.var = default_variant(r.d.lattice, r.d.precision);
+    {
+      // runs that can take several steps per launch do so by default (64 x 16
+      // tiles, 4 steps in FP32; 64 x 8, 4 steps, XCD-contiguous order in FP64)
+      const Variant multi = r.dbl ? Variant{64, 4, 2, true, 1, 0, 4} : Variant{64, 8, 2, true, 0, 0, 4};
+      if (r.d.lattice == LBM_CDE_D2Q9 && !r.half && find_step(r, multi)) r.var = multi;
+    }
     if (r.split && h->env16_set) r.var = h->env16;
     if (h->env_variant && !r.half) r.var = r.d.lattice == LBM_CDE_D3Q15 ? h->env3 : h->env;
     if (r.var.fuse == 1) r.var1 = r.var;

@@ -40,6 +40,12 @@ def _pops(s, wl, precision):
     return populations(s.get_state().cpu().numpy(), 9, wl.nodes, precision)[0]
 
 
+def _one_step(s, run=0):
+    """The one-step variant with 256 x 1 tiles and streaming stores in hardware order."""
+    return next(v for v in s.variants(run) if v["steps_per_launch"] == 1 and v["block"] == (256, 1)
+                and v["rows_per_thread"] == 1 and v["nt_stores"] and v["block_order"] == 0)
+
+
 def _multi(s, run=0):
     return [v for v in s.variants(run) if v["steps_per_launch"] > 1]
 
@@ -57,7 +63,8 @@ def test_every_multi_step_variant(precision, velocity):
     if velocity == "const":
         wl = dataclasses.replace(wl, u_sep=None, u_const=np.array([0.04, -0.03]))
     ref = Solver(wl, precision)
-    assert ref.variant()["steps_per_launch"] == 1
+    assert ref.variant()["steps_per_launch"] == 4          # the default for such runs
+    ref.set_variant(_one_step(ref))
     phis = []
     for n in seq:
         ref.step(n)
@@ -89,6 +96,7 @@ def test_checkpoint_restart_and_budget():
     from paper_1404_2363_amd.solver import Solver
     wl = W.cellular(nx=160, ny=96, steps=101, n_hills=3, sigma=6.0)
     ref = Solver(wl, "fp32", max_steps=101)
+    ref.set_variant(_one_step(ref))
     ref.step(200)                       # stops at the budget
     assert ref.steps_done() == 101
     end = _phi(ref)
@@ -124,6 +132,7 @@ def test_per_node_diffusion_field(precision):
     wl = W.Workload("dfield_periodic", "d2q9", (nx, ny), ("periodic", "periodic"), steps, spec, D_field=D,
                     u_const=np.array([0.03, -0.02]))
     ref = Solver(wl, precision, heat=[1.0, 1.0])
+    ref.set_variant(_one_step(ref))
     ref.step(steps)
     want = _phi(ref)
     variants = _multi(ref)
@@ -152,8 +161,7 @@ def test_velocity_field_replaced_between_calls():
 
     def run(v):
         s = Solver(wl, "fp32")
-        if v is not None:
-            s.set_variant(v)
+        s.set_variant(v if v is not None else _one_step(s))
         for u in fields:
             s.set_velocity(u)
             s.step(7)
@@ -178,6 +186,7 @@ def test_two_runs_one_multi_step():
     want = []
     for wl, prec in ((wa, "fp32"), (wb, "fp64")):
         s = Solver(wl, prec)
+        s.set_variant(_one_step(s))
         s.step(sum(seq))
         want.append(_phi(s))
         s.close()
@@ -185,6 +194,7 @@ def test_two_runs_one_multi_step():
     v = next(v for v in _multi(s, 0) if v["steps_per_launch"] == 3 and v["block_order"] == 0)
     print(f"case two runs, run 0 {v}", flush=True)
     s.set_variant(v, run=0)
+    s.set_variant(_one_step(s, 1), run=1)
     for n in seq:
         s.step(n)
     assert s.steps_done(0) == s.steps_done(1) == sum(seq)
