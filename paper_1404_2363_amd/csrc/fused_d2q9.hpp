@@ -17,8 +17,13 @@
 // collision has no u^2 terms.  HBM sees one read and one
 // write of the state per T steps (72 B per node for FP32, 144 B for FP64)
 // instead of per step; the price is the recomputed rings (the widened tiles'
-// extra collisions) and LDS traffic.  Halo nodes take periodic images, which
-// needs nx >= TX + 2(T-1) and ny >= TY + 2(T-1) (one wrap per coordinate).
+// extra collisions) and LDS traffic.  x is periodic: halo nodes take periodic
+// images, which needs nx >= TX + 2(T-1) (one wrap per coordinate).  y is
+// periodic the same way (ny >= TY + 2(T-1)) or, with WY, bounded by walls:
+// rows beyond a wall are not computed, and a population whose source lies
+// beyond it takes the wall rule's source (the node itself or its neighbour
+// along or inside the wall, all within one node: row_source_d2q9), from LDS
+// in steps 2..T as from memory in step 1.
 //
 // UK selects the velocity: 0 constant, 1 separable (a product of per-axis
 // factors: the block stages the widened tile's column and row factors in LDS
@@ -37,8 +42,17 @@ __device__ constexpr int kEy9[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
 
 LBM_FORCEINLINE int32_t wrap_once(int32_t v, int32_t n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
 
+// Source of population I (velocity (EX, EY)) at row y: (population, row,
+// x shift) under the run's y boundary (walls), as in the one-step kernel.
+template <int I>
+LBM_FORCEINLINE void wall_source(const RunArgs& a, int32_t y, int32_t ny, int& pop, int32_t& sy, int& dx) {
+  constexpr int EX = I == 1 || I == 5 || I == 8 ? 1 : (I == 3 || I == 6 || I == 7 ? -1 : 0);
+  constexpr int EY = I == 2 || I == 5 || I == 6 ? 1 : (I == 4 || I == 7 || I == 8 ? -1 : 0);
+  row_source_d2q9<EX, EY>(a, y, ny, pop, sy, dx);
+}
+
 // Block (BX, BY) threads; output tile BX x (BY * NY); T steps per launch.
-template <typename R, int BX, int BY, int NY, int T, int UK>
+template <typename R, int BX, int BY, int NY, int T, int UK, bool WY>
 __global__ __launch_bounds__(BX * BY) void k_fused_d2q9(const RunArgs a) {
   static_assert(T >= 2, "one step per launch is k_step_d2q9");
   constexpr int NTH = BX * BY, TX = BX, TY = BY * NY, RG = T - 1;
@@ -65,6 +79,36 @@ __global__ __launch_bounds__(BX * BY) void k_fused_d2q9(const RunArgs a) {
     tz1 = tab[tstride + 1 + nx + ny];
   }
 
+  // row of the widened tile -> row of the grid (periodic image; with walls the
+  // row itself, which may lie beyond a wall and is then skipped)
+  auto grid_row = [&](int ly) -> int32_t { return WY ? y0 + ly : wrap_once(y0 + ly, ny); };
+  auto outside = [&](int32_t y) { return WY && (y < 0 || y >= ny); };
+  // LDS gather of the nine populations of local node (lx, ly), grid row y
+  auto gather = [&](R(&f)[9], int lx, int ly, int32_t y) {
+    if constexpr (!WY) {
+#pragma unroll
+      for (int i = 0; i < 9; ++i) f[i] = lds[i * C0 + (ly - kEy9[i]) * W0 + (lx - kEx9[i])];
+    } else {
+#define LBM_FUSED_WALL_PULL(I)                                     \
+  {                                                                \
+    int pop, dx;                                                   \
+    int32_t sy;                                                    \
+    wall_source<I>(a, y, ny, pop, sy, dx);                         \
+    f[I] = lds[pop * C0 + (ly + (sy - y)) * W0 + (lx + dx)];       \
+  }
+      LBM_FUSED_WALL_PULL(0)
+      LBM_FUSED_WALL_PULL(1)
+      LBM_FUSED_WALL_PULL(2)
+      LBM_FUSED_WALL_PULL(3)
+      LBM_FUSED_WALL_PULL(4)
+      LBM_FUSED_WALL_PULL(5)
+      LBM_FUSED_WALL_PULL(6)
+      LBM_FUSED_WALL_PULL(7)
+      LBM_FUSED_WALL_PULL(8)
+#undef LBM_FUSED_WALL_PULL
+    }
+  };
+
   // collision of one node at periodic image (x, y); (lx, ly) in the widened tile
   auto collide = [&](R(&f)[9], int32_t x, int32_t y, int lx, int ly) {
     R ux, uy;
@@ -85,25 +129,47 @@ __global__ __launch_bounds__(BX * BY) void k_fused_d2q9(const RunArgs a) {
   {
     const char* src = (const char*)a.src;
     R f[K0][9];
+    constexpr uint32_t E = sizeof(R);
 #pragma unroll
     for (int k = 0; k < K0; ++k) {
       const int j = tid + k * NTH;
       if (K0 * NTH > C0 && j >= C0) continue;
       const int ly = j / W0, lx = j - ly * W0;
-      const int32_t x = wrap_once(x0 + lx, nx), y = wrap_once(y0 + ly, ny);
+      const int32_t x = wrap_once(x0 + lx, nx), y = grid_row(ly);
+      if (outside(y)) continue;
       const uint32_t xm = x == 0 ? nx - 1 : x - 1, xp = x + 1 == nx ? 0 : x + 1;
-      const uint32_t r0 = (uint32_t)y * nx, rm = (uint32_t)(y == 0 ? ny - 1 : y - 1) * nx,
-                     rp = (uint32_t)(y + 1 == ny ? 0 : y + 1) * nx;
-      constexpr uint32_t E = sizeof(R);
-      f[k][0] = gld<R>(src, (r0 + x) * E);
-      f[k][1] = gld<R>(src + 1 * pb, (r0 + xm) * E);
-      f[k][2] = gld<R>(src + 2 * pb, (rm + x) * E);
-      f[k][3] = gld<R>(src + 3 * pb, (r0 + xp) * E);
-      f[k][4] = gld<R>(src + 4 * pb, (rp + x) * E);
-      f[k][5] = gld<R>(src + 5 * pb, (rm + xm) * E);
-      f[k][6] = gld<R>(src + 6 * pb, (rm + xp) * E);
-      f[k][7] = gld<R>(src + 7 * pb, (rp + xp) * E);
-      f[k][8] = gld<R>(src + 8 * pb, (rp + xm) * E);
+      if constexpr (!WY) {
+        const uint32_t r0 = (uint32_t)y * nx, rm = (uint32_t)(y == 0 ? ny - 1 : y - 1) * nx,
+                       rp = (uint32_t)(y + 1 == ny ? 0 : y + 1) * nx;
+        f[k][0] = gld<R>(src, (r0 + x) * E);
+        f[k][1] = gld<R>(src + 1 * pb, (r0 + xm) * E);
+        f[k][2] = gld<R>(src + 2 * pb, (rm + x) * E);
+        f[k][3] = gld<R>(src + 3 * pb, (r0 + xp) * E);
+        f[k][4] = gld<R>(src + 4 * pb, (rp + x) * E);
+        f[k][5] = gld<R>(src + 5 * pb, (rm + xm) * E);
+        f[k][6] = gld<R>(src + 6 * pb, (rm + xp) * E);
+        f[k][7] = gld<R>(src + 7 * pb, (rp + xp) * E);
+        f[k][8] = gld<R>(src + 8 * pb, (rp + xm) * E);
+      } else {
+#define LBM_FUSED_WALL_LOAD(I)                                                                  \
+  {                                                                                             \
+    int pop, dx;                                                                                \
+    int32_t sy;                                                                                 \
+    wall_source<I>(a, y, ny, pop, sy, dx);                                                      \
+    const uint32_t sx = dx < 0 ? xm : (dx > 0 ? xp : (uint32_t)x);                              \
+    f[k][I] = gld<R>(src + (size_t)pop * pb, ((uint32_t)sy * nx + sx) * E);                       \
+  }
+        LBM_FUSED_WALL_LOAD(0)
+        LBM_FUSED_WALL_LOAD(1)
+        LBM_FUSED_WALL_LOAD(2)
+        LBM_FUSED_WALL_LOAD(3)
+        LBM_FUSED_WALL_LOAD(4)
+        LBM_FUSED_WALL_LOAD(5)
+        LBM_FUSED_WALL_LOAD(6)
+        LBM_FUSED_WALL_LOAD(7)
+        LBM_FUSED_WALL_LOAD(8)
+#undef LBM_FUSED_WALL_LOAD
+      }
     }
     if constexpr (UK == 1) {
       if (tid < W0) {
@@ -112,7 +178,8 @@ __global__ __launch_bounds__(BX * BY) void k_fused_d2q9(const RunArgs a) {
         ucol[W0 + tid] = tab[tstride] * tab[tstride + 1 + x];
       }
       if (tid < H0) {
-        const int32_t y = wrap_once(y0 + tid, ny);
+        // rows beyond a wall are never collided; clamp to stay inside the table
+        const int32_t yy = grid_row(tid), y = WY ? (yy < 0 ? 0 : (yy >= ny ? ny - 1 : yy)) : yy;
         urow[tid] = tab[1 + nx + y];
         urow[H0 + tid] = tab[tstride + 1 + nx + y];
       }
@@ -125,7 +192,9 @@ __global__ __launch_bounds__(BX * BY) void k_fused_d2q9(const RunArgs a) {
       const int j = tid + k * NTH;
       if (K0 * NTH > C0 && j >= C0) continue;
       const int ly = j / W0, lx = j - ly * W0;
-      collide(f[k], wrap_once(x0 + lx, nx), wrap_once(y0 + ly, ny), lx, ly);
+      const int32_t y = grid_row(ly);
+      if (outside(y)) continue;
+      collide(f[k], wrap_once(x0 + lx, nx), y, lx, ly);
 #pragma unroll
       for (int i = 0; i < 9; ++i) lds[i * C0 + j] = f[k][i];
     }
@@ -144,16 +213,17 @@ __global__ __launch_bounds__(BX * BY) void k_fused_d2q9(const RunArgs a) {
       at[k] = -1;
       if (j >= C) continue;
       const int ly = j / W + off, lx = j % W + off;
+      const int32_t y = grid_row(ly);
+      if (outside(y)) continue;
       at[k] = ly * W0 + lx;
-#pragma unroll
-      for (int i = 0; i < 9; ++i) f[k][i] = lds[i * C0 + (ly - kEy9[i]) * W0 + (lx - kEx9[i])];
+      gather(f[k], lx, ly, y);
     }
     __syncthreads();
 #pragma unroll
     for (int k = 0; k < K0; ++k) {
       if (at[k] < 0) continue;
       const int ly = at[k] / W0, lx = at[k] - ly * W0;
-      collide(f[k], wrap_once(x0 + lx, nx), wrap_once(y0 + ly, ny), lx, ly);
+      collide(f[k], wrap_once(x0 + lx, nx), grid_row(ly), lx, ly);
 #pragma unroll
       for (int i = 0; i < 9; ++i) lds[i * C0 + at[k]] = f[k][i];
     }
@@ -168,8 +238,7 @@ __global__ __launch_bounds__(BX * BY) void k_fused_d2q9(const RunArgs a) {
     const int32_t x = x0 + lx, y = y0 + ly;
     if (x >= nx || y >= ny) continue;
     R g[9];
-#pragma unroll
-    for (int i = 0; i < 9; ++i) g[i] = lds[i * C0 + (ly - kEy9[i]) * W0 + (lx - kEx9[i])];
+    gather(g, lx, ly, y);
     collide(g, x, y, lx, ly);
     const uint32_t off = ((uint32_t)y * nx + x) * (uint32_t)sizeof(R);
 #pragma unroll

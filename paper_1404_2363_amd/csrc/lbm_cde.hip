@@ -726,9 +726,16 @@ template <typename R, int BX, int BY, int NY, int T>
 void launch_fused(const RunArgs a, hipStream_t s) {
   const int64_t ntx = (a.nx + BX - 1) / BX, nty = (a.ny + BY * NY - 1) / (BY * NY);
   const dim3 g((unsigned)(ntx * nty)), b(BX, BY);
-  if (a.u_kind == U_CONST) hipLaunchKernelGGL((k_fused_d2q9<R, BX, BY, NY, T, 0>), g, b, 0, s, a);
-  else if (a.u_kind == U_SEPARABLE) hipLaunchKernelGGL((k_fused_d2q9<R, BX, BY, NY, T, 1>), g, b, 0, s, a);
-  else hipLaunchKernelGGL((k_fused_d2q9<R, BX, BY, NY, T, 2>), g, b, 0, s, a);
+  if (a.bc[1] != LBM_CDE_PERIODIC) {  // walls in y (velocity constant or separable)
+    if (a.u_kind == U_CONST) hipLaunchKernelGGL((k_fused_d2q9<R, BX, BY, NY, T, 0, true>), g, b, 0, s, a);
+    else hipLaunchKernelGGL((k_fused_d2q9<R, BX, BY, NY, T, 1, true>), g, b, 0, s, a);
+  } else if (a.u_kind == U_CONST) {
+    hipLaunchKernelGGL((k_fused_d2q9<R, BX, BY, NY, T, 0, false>), g, b, 0, s, a);
+  } else if (a.u_kind == U_SEPARABLE) {
+    hipLaunchKernelGGL((k_fused_d2q9<R, BX, BY, NY, T, 1, false>), g, b, 0, s, a);
+  } else {
+    hipLaunchKernelGGL((k_fused_d2q9<R, BX, BY, NY, T, 2, false>), g, b, 0, s, a);
+  }
 }
 
 template <typename R, int BX, int BY, int NY, int T>
@@ -750,14 +757,16 @@ const FusedEntry kFused[] = {FUSED_ENTRY(128, 4, 2, 2), FUSED_ENTRY(128, 4, 2, 3
                              FUSED_ENTRY(64, 8, 2, 3),  FUSED_ENTRY(64, 8, 2, 4),  FUSED_ENTRY(64, 8, 2, 5)};
 
 // A run can take T steps per launch when it is D2Q9 in FP64 or FP32 with an
-// equilibrium linear in phi and phi u (MRT-A or MRT-B3), periodic on both
-// axes, each axis spans the tile plus T - 1 nodes on both sides (halo nodes
-// are periodic images taken with one wrap), and byte offsets within a
-// population plane fit 32 bits.
+// equilibrium linear in phi and phi u (MRT-A or MRT-B3), periodic in x, each
+// periodic axis spans the tile plus T - 1 nodes on both sides (halo nodes are
+// periodic images taken with one wrap), a run with walls in y has a constant
+// or separable velocity, and byte offsets within a population plane fit 32
+// bits.
 bool fused_ok(const Run& r, const Variant& v) {
-  return r.d.lattice == LBM_CDE_D2Q9 && !r.half && !r.split && !r.walls && r.d.nz == 1 &&
-         (r.d.model == LBM_CDE_MRT_A || r.d.model == LBM_CDE_MRT_B3) &&
-         r.d.nx >= (int64_t)v.bx + 2 * (v.fuse - 1) && r.d.ny >= (int64_t)v.by * v.ny + 2 * (v.fuse - 1) &&
+  const bool wy = r.d.bc[1] != LBM_CDE_PERIODIC;
+  return r.d.lattice == LBM_CDE_D2Q9 && !r.half && !r.split && r.d.bc[0] == LBM_CDE_PERIODIC && r.d.nz == 1 &&
+         (r.d.model == LBM_CDE_MRT_A || r.d.model == LBM_CDE_MRT_B3) && !(wy && r.d.u_kind == LBM_CDE_U_FIELD) &&
+         r.d.nx >= (int64_t)v.bx + 2 * (v.fuse - 1) && (wy || r.d.ny >= (int64_t)v.by * v.ny + 2 * (v.fuse - 1)) &&
          (double)r.nodes * (double)r.elem < 4294967296.0 && r.d.nx < (1ll << 30) && r.d.ny < (1ll << 30) &&
          v.grid == 0;
 }

@@ -17,7 +17,10 @@ must be bitwise that of the run's default (one-step) variant:
   field replaced between calls;
 * a handle of two runs of which only one steps several steps per launch, so
   the runs' buffers drift apart and the graph path is left;
-* grids too small for a tile and its halo, and runs with walls, are refused.
+* walls in y (bounce-back, halfway mirror, the paper's on-node mirror) on a
+  channel whose height is no multiple of the tile height;
+* grids too small for a tile and its halo, walls in x, and a per-node
+  velocity field with walls, are refused.
 """
 import numpy as np
 import pytest
@@ -203,6 +206,42 @@ def test_two_runs_one_multi_step():
     s.close()
 
 
+@pytest.mark.parametrize("wall", ["bounce", "specular", "node"])
+def test_walls_in_y(wall):
+    """A plane Poiseuille channel (x periodic, walls in y, separable velocity):
+    every multi-step variant against one-step launches, and the oracle.  Tiles
+    overhang the walls (ny = 37 is no multiple of the tile height); rows beyond
+    a wall are skipped and pulls across it take the wall rule's source."""
+    import dataclasses
+    from paper_1404_2363_amd.solver import Solver
+    wl = W.taylor_aris_channel(37, 12.0, 0.9, nx=150, steps=45, wall="specular")
+    wl.walls = ("periodic", wall)
+    for precision in ("fp64", "fp32"):
+        ref = Solver(wl, precision)
+        assert ref.variant()["steps_per_launch"] == 4
+        ref.set_variant(_one_step(ref))
+        seq = [3, 32, 10]
+        phis = []
+        for n in seq:
+            ref.step(n)
+            phis.append(_phi(ref))
+        variants = _multi(ref)
+        ref.close()
+        print(f"case channel 150x37 walls {wall} {precision}: {len(variants)} multi-step variants", flush=True)
+        assert len(variants) >= 18
+        for v in variants:
+            s = Solver(wl, precision)
+            s.set_variant(v)
+            for n, p in zip(seq, phis):
+                s.step(n)
+                np.testing.assert_array_equal(_phi(s), p, err_msg=str(v))
+            s.close()
+        oref, _ = O.run_workload(wl, steps=sum(seq))
+        err = rel(phis[-1], oref)
+        print(f"oracle error {err:.2e}", flush=True)
+        assert err <= TOL[precision]
+
+
 def test_refused_where_a_tile_and_its_halo_do_not_fit():
     from paper_1404_2363_amd import _lib as L
     from paper_1404_2363_amd.solver import Solver
@@ -216,9 +255,16 @@ def test_refused_where_a_tile_and_its_halo_do_not_fit():
         small.set_variant(v)
     assert e.value.code == L.LBM_CDE_EINVAL
     small.close()
+    # walls in x (only y may have walls), and a per-node velocity field with walls in y
     walls = W.taylor_aris_channel(32, 12.0, 1.1, nx=300, steps=1, wall="bounce")
+    walls.walls = ("bounce", "periodic")
     s = Solver(walls, "fp32")
     assert not _multi(s)
     with pytest.raises(L.LbmCdeError):
         s.set_variant(v)
+    s.close()
+    fld = W.taylor_aris_channel(32, 12.0, 1.1, nx=300, steps=1, wall="bounce")
+    fld.u_field, fld.u_sep = fld.u(), None
+    s = Solver(fld, "fp32")
+    assert not _multi(s)
     s.close()
