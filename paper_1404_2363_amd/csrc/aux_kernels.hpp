@@ -230,8 +230,17 @@ __global__ __launch_bounds__(RED_THREADS) void k_batch_xmom_final(const double* 
 }
 
 // Advance the device step clock (clock[0]: steps, clock[1]: history rows).
-__global__ void k_tick(int64_t* __restrict__ clock, int which) {
-  if (threadIdx.x == 0) clock[which] += 1;
+// Batch clock: [0] steps, [1] history rows, [2] population buffer of the
+// next launch.  which = 0: one step (flips the buffer); 1: one history row;
+// 2: a launch of n steps (flips the buffer).
+__global__ void k_tick(int64_t* __restrict__ clock, int which, int n) {
+  if (threadIdx.x != 0) return;
+  if (which == 1) {
+    clock[1] += 1;
+  } else {
+    clock[0] += which == 0 ? 1 : n;
+    clock[2] ^= 1;
+  }
 }
 
 // Point a velocity slot at a field (a kernel, so that it is ordered on the

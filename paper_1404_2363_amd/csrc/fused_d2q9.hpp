@@ -51,9 +51,10 @@ LBM_FORCEINLINE void wall_source(const RunArgs& a, int32_t y, int32_t ny, int& p
   row_source_d2q9<EX, EY>(a, y, ny, pop, sy, dx);
 }
 
-// Block (BX, BY) threads; output tile BX x (BY * NY); T steps per launch.
+// T steps of output tile (txi, tyi) of the run described by a; block (BX,
+// BY) threads, tile BX x (BY * NY).
 template <typename R, int BX, int BY, int NY, int T, int UK, bool WY>
-__global__ __launch_bounds__(BX * BY) void k_fused_d2q9(const RunArgs a) {
+LBM_FORCEINLINE void fused_tile(const RunArgs& a, uint32_t txi, uint32_t tyi) {
   static_assert(T >= 2, "one step per launch is k_step_d2q9");
   constexpr int NTH = BX * BY, TX = BX, TY = BY * NY, RG = T - 1;
   constexpr int W0 = TX + 2 * RG, H0 = TY + 2 * RG, C0 = W0 * H0;
@@ -63,10 +64,8 @@ __global__ __launch_bounds__(BX * BY) void k_fused_d2q9(const RunArgs a) {
   __shared__ R ucol[UK == 1 ? 2 * W0 : 1], urow[UK == 1 ? 2 * H0 : 1];
 
   const int tid = threadIdx.y * BX + threadIdx.x;
-  const uint32_t b = tile_of_block32(blockIdx.x, gridDim.x, a.tiles_x, a.xcd_remap);
-  const uint32_t tyi = fdiv(b, a.tiles_x);
   const int32_t nx = (int32_t)a.nx, ny = (int32_t)a.ny;
-  const int32_t x0 = (int32_t)(b - tyi * a.tiles_x.d) * TX - RG, y0 = (int32_t)tyi * TY - RG;
+  const int32_t x0 = (int32_t)txi * TX - RG, y0 = (int32_t)tyi * TY - RG;
   const size_t pb = (size_t)a.plane * sizeof(R);
   const Rel2<R> rc = const_rel2<R>(a);
   const R phi_ref = (R)a.phi_ref;
@@ -244,6 +243,87 @@ __global__ __launch_bounds__(BX * BY) void k_fused_d2q9(const RunArgs a) {
 #pragma unroll
     for (int i = 0; i < 9; ++i) gst<R, true>(dst + i * pb, off, g[i]);
   }
+}
+
+// One run: one block per tile, in the chosen block order.
+template <typename R, int BX, int BY, int NY, int T, int UK, bool WY>
+__global__ __launch_bounds__(BX * BY) void k_fused_d2q9(const RunArgs a) {
+  const uint32_t b = tile_of_block32(blockIdx.x, gridDim.x, a.tiles_x, a.xcd_remap);
+  const uint32_t tyi = fdiv(b, a.tiles_x);
+  fused_tile<R, BX, BY, NY, T, UK, WY>(a, b - tyi * a.tiles_x.d, tyi);
+}
+
+// The arguments of one step of a batched run (its compact record), for the
+// multi-step tile: what fused_tile reads, in the one-run kernel's form.
+template <typename R>
+LBM_FORCEINLINE RunArgs batch_run_args(const BatchRun& br, int par) {
+  RunArgs a;
+  a.src = br.pop[par];
+  a.dst = (void*)br.pop[par ^ 1];
+  a.nx = br.nx;
+  a.ny = br.ny;
+  a.nz = 1;
+  a.plane = br.pb / (uint32_t)sizeof(R);
+  a.bc[0] = LBM_CDE_PERIODIC;
+  a.bc[1] = br.bc_y;
+  a.bc[2] = LBM_CDE_PERIODIC;
+  a.model = br.model;
+  a.u_kind = br.u_kind;
+  a.u_const[0] = br.u_const[0];
+  a.u_const[1] = br.u_const[1];
+  a.u_tab = br.u_tab;
+  a.node_par = nullptr;
+  a.phi_ref = br.phi_ref;
+  a.s[1] = br.s1;
+  a.s[2] = br.s2;
+  a.s[7] = br.s7;
+  a.s[8] = br.s8;
+  a.A[0][0] = br.axx;
+  a.A[0][1] = br.axy;
+  a.A[1][1] = br.ayy;
+  a.heat[0] = br.s4;
+  a.heat[1] = br.s6;
+  return a;
+}
+
+// T steps of every active run of a batch (runs periodic in x, walls or not
+// in y, constant or separable velocity) in one launch: block b takes tile b
+// of a flat list of BX x (BY * NY) tiles over the runs (in order of
+// decreasing budget; blocks past the active runs' tiles exit, and the host
+// launches this kernel only while no run's budget ends inside the launch).
+// The buffer parity is clock[2], which every launch of a batched kernel
+// flips (the one-step kernel's parity, t & 1, equals it between launches of
+// this kernel taken in pairs).
+template <typename R, int BX, int BY, int NY, int T, int UK, bool WY>
+__global__ __launch_bounds__(BX * BY) void k_batch_fused_d2q9(const BatchRun* __restrict__ runs,
+                                                             const uint32_t* __restrict__ tile_start, int nruns,
+                                                             const int64_t* __restrict__ clock) {
+  const uint32_t t = blockIdx.x;
+  // active runs: a prefix of the list (runs are stored by decreasing budget)
+  const int64_t t_global = clock[0];
+  int na;
+  {
+    int l = 0, h = nruns;
+    while (l < h) {
+      const int mid = (l + h) / 2;
+      const int64_t ms = runs[mid].max_steps;
+      if (ms >= 0 && t_global >= ms) h = mid;
+      else l = mid + 1;
+    }
+    na = l;
+  }
+  if (na == 0 || t >= tile_start[na]) return;
+  int lo = 0, hi = na - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) / 2;
+    if (tile_start[mid] <= t) lo = mid;
+    else hi = mid - 1;
+  }
+  const BatchRun& br = runs[lo];
+  const RunArgs a = batch_run_args<R>(br, (int)(clock[2] & 1));
+  const uint32_t ntx = (br.nx + BX - 1) / BX, local = t - tile_start[lo];
+  const uint32_t tyi = local / ntx;
+  fused_tile<R, BX, BY, NY, T, UK, WY>(a, local - tyi * ntx, tyi);
 }
 
 }  // namespace lbm

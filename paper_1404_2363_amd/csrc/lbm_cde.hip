@@ -141,6 +141,13 @@ struct lbm_cde {
   std::map<std::tuple<int32_t, int32_t, const void*, const void*, const void*, const void*, int>, hipGraphExec_t>
       adj_graphs;
   std::vector<int64_t> batch_prefix;  // tile-list prefix, in batch order (host copy)
+  // several steps per launch for the whole batch (fuse > 1), used for every
+  // kGraphSteps block in which no run's budget ends; batch_var steps the rest
+  Variant batch_fuse{64, 8, 2, true, 0, 0, 1};
+  uint32_t* dev_tiles_f = nullptr;     // tile starts of the multi-step launch, batch order
+  std::vector<int64_t> batch_prefix_f; // host copy
+  std::map<unsigned, hipGraphExec_t> batch_fgraphs;
+  std::map<uint64_t, hipGraphExec_t> sample_fgraphs;
   int64_t sample_every = 0;
   double* sample_hist = nullptr;
   bool env_variant = false;   // LBM_CDE_TILE / _NT / _XCD override every run
@@ -596,9 +603,9 @@ bool batch_eligible(const lbm_cde_run_desc* runs, int32_t nruns) {
 
 size_t batch_bytes(int32_t nruns) {
   return align_up(sizeof(RunArgs) * nruns) + align_up(sizeof(int64_t) * (nruns + 1)) +
-         align_up(sizeof(int32_t) * nruns) + align_up(2 * sizeof(int64_t)) +
+         align_up(sizeof(int32_t) * nruns) + align_up(3 * sizeof(int64_t)) +
          align_up(sizeof(double) * 3 * kBatchRedBlocks * nruns) + align_up(sizeof(BatchRun) * nruns) +
-         align_up(sizeof(uint32_t) * (nruns + 1));
+         2 * align_up(sizeof(uint32_t) * (nruns + 1));
 }
 
 // ---- kernel dispatch ------------------------------------------------------
@@ -836,10 +843,12 @@ void drop_graphs(lbm_cde* h) {
       g = nullptr;
     }
   h->graph_off = false;
-  for (auto* m : {&h->batch_graphs, &h->sample_graphs}) {
+  for (auto* m : {&h->batch_graphs, &h->sample_graphs, &h->batch_fgraphs}) {
     for (auto& kv : *m) (void)hipGraphExecDestroy(kv.second);
     m->clear();
   }
+  for (auto& kv : h->sample_fgraphs) (void)hipGraphExecDestroy(kv.second);
+  h->sample_fgraphs.clear();
   for (auto& kv : h->adj_graphs) (void)hipGraphExecDestroy(kv.second);
   h->adj_graphs.clear();
 }
@@ -1020,6 +1029,19 @@ std::vector<Variant> batch_candidates() {
   return out;
 }
 
+BatchFn find_batch_fused(const lbm_cde* h, const Variant& v);
+
+// The multi-step launches every run of the batch allows.
+std::vector<Variant> batch_fused_candidates(const lbm_cde* h);
+
+// Every candidate of a batched handle: the one-step launches, then the
+// multi-step ones.
+std::vector<Variant> batch_all_candidates(const lbm_cde* h) {
+  std::vector<Variant> out = batch_candidates();
+  for (const Variant& c : batch_fused_candidates(h)) out.push_back(c);
+  return out;
+}
+
 // Make v the batched launch variant: the flat tile list (runs in order of
 // decreasing step budget, ceil(nx / bx) tiles per row) is rewritten in the
 // workspace and the captured graphs are dropped.  tiles_out, if given,
@@ -1084,6 +1106,128 @@ int apply_batch_variant(lbm_cde* h, const Variant& v, std::vector<int64_t>* tile
   h->batch_prefix = tiles;
   if (tiles_out) *tiles_out = tiles;
   return LBM_CDE_OK;
+}
+
+// Several steps per launch for a whole batch (k_batch_fused_d2q9): every run
+// periodic in x, of a linear equilibrium, without per-node fields, all with
+// the same velocity kind (constant or separable) and all with walls in y or
+// none; T divides kGraphSteps an even number of times, so that a captured
+// block of multi-step launches leaves the state in the buffer that the
+// step count's parity names.
+template <typename R, int BX, int BY, int NY, int T>
+void launch_batch_fused(const lbm_cde* h, hipStream_t s, unsigned grid) {
+  const Run& r0 = h->runs[0];
+  const int nr = (int)h->runs.size();
+  const dim3 g(grid), b(BX, BY);
+  if (r0.d.bc[1] != LBM_CDE_PERIODIC) {
+    if (r0.d.u_kind == LBM_CDE_U_CONST)
+      hipLaunchKernelGGL((k_batch_fused_d2q9<R, BX, BY, NY, T, 0, true>), g, b, 0, s, h->dev_brun, h->dev_tiles_f,
+                         nr, h->dev_clock);
+    else
+      hipLaunchKernelGGL((k_batch_fused_d2q9<R, BX, BY, NY, T, 1, true>), g, b, 0, s, h->dev_brun, h->dev_tiles_f,
+                         nr, h->dev_clock);
+  } else if (r0.d.u_kind == LBM_CDE_U_CONST) {
+    hipLaunchKernelGGL((k_batch_fused_d2q9<R, BX, BY, NY, T, 0, false>), g, b, 0, s, h->dev_brun, h->dev_tiles_f, nr,
+                       h->dev_clock);
+  } else {
+    hipLaunchKernelGGL((k_batch_fused_d2q9<R, BX, BY, NY, T, 1, false>), g, b, 0, s, h->dev_brun, h->dev_tiles_f, nr,
+                       h->dev_clock);
+  }
+}
+
+template <typename R, int BX, int BY, int NY, int T>
+constexpr BatchFn batch_fused_fn() {
+  if constexpr (9 * (BX + 2 * (T - 1)) * (BY * NY + 2 * (T - 1)) * sizeof(R) <= 160 * 1024)
+    return launch_batch_fused<R, BX, BY, NY, T>;
+  else
+    return nullptr;
+}
+
+struct BatchFusedEntry {
+  int bx, by, ny, T;
+  BatchFn fn[2];  // [double?]
+};
+#define BATCH_FUSED_ENTRY(BX, BY, NY, T)                                                           \
+  BatchFusedEntry {                                                                                \
+    BX, BY, NY, T, {batch_fused_fn<float, BX, BY, NY, T>(), batch_fused_fn<double, BX, BY, NY, T>()} \
+  }
+const BatchFusedEntry kBatchFused[] = {BATCH_FUSED_ENTRY(64, 8, 2, 4), BATCH_FUSED_ENTRY(64, 4, 2, 4),
+                                       BATCH_FUSED_ENTRY(128, 4, 2, 4), BATCH_FUSED_ENTRY(64, 8, 2, 2)};
+
+// The multi-step batched launch of variant v, or null where it is not built
+// or some run does not allow it.
+BatchFn find_batch_fused(const lbm_cde* h, const Variant& v) {
+  if (!h->batch_lean || v.fuse < 2 || (kGraphSteps / v.fuse) % 2 != 0 || kGraphSteps % v.fuse != 0 || !v.nt ||
+      v.xcd != 0 || v.grid != 0 || h->runs.empty())
+    return nullptr;
+  const Run& r0 = h->runs[0];
+  for (const Run& r : h->runs)
+    if (!fused_ok(r, v) || r.node_par || r.d.u_kind == LBM_CDE_U_FIELD || r.d.u_kind != r0.d.u_kind ||
+        (r.d.bc[1] == LBM_CDE_PERIODIC) != (r0.d.bc[1] == LBM_CDE_PERIODIC) || r.dbl != r0.dbl)
+      return nullptr;
+  for (const auto& e : kBatchFused)
+    if (e.bx == v.bx && e.by == v.by && e.ny == v.ny && e.T == v.fuse) return e.fn[r0.dbl ? 1 : 0];
+  return nullptr;
+}
+
+std::vector<Variant> batch_fused_candidates(const lbm_cde* h) {
+  std::vector<Variant> out;
+  for (const auto& e : kBatchFused) {
+    const Variant c{e.bx, e.by, e.ny, true, 0, 0, e.T};
+    if (find_batch_fused(h, c)) out.push_back(c);
+  }
+  return out;
+}
+
+// Make v the multi-step batched launch (v.fuse > 1; validated by the caller
+// with find_batch_fused) or switch it off (v.fuse == 1): the flat list of
+// BX x (BY * NY) tiles over the runs, in batch order, goes to the workspace.
+int apply_batch_fused(lbm_cde* h, const Variant& v) {
+  if (v.fuse > 1) {
+    const int32_t nruns = (int32_t)h->runs.size();
+    std::vector<int64_t> tiles(1, 0);
+    const int64_t th = (int64_t)v.by * v.ny;
+    for (int32_t k = 0; k < nruns; ++k) {
+      const Run& r = h->runs[h->batch_order[k]];
+      tiles.push_back(tiles.back() + (r.d.nx + v.bx - 1) / v.bx * ((r.d.ny + th - 1) / th));
+    }
+    if (tiles.back() >= ((int64_t)1 << 31)) return fail(h, LBM_CDE_EINVAL, "batch: too many tiles");
+    std::vector<uint32_t> t32(nruns + 1);
+    for (int32_t k = 0; k <= nruns; ++k) t32[k] = (uint32_t)tiles[k];
+    HIP_TRY(h, hipMemcpyAsync(h->dev_tiles_f, t32.data(), sizeof(uint32_t) * (nruns + 1), hipMemcpyHostToDevice,
+                              h->stream));
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    h->batch_prefix_f = tiles;
+  }
+  drop_graphs(h);
+  h->batch_fuse = v;
+  return LBM_CDE_OK;
+}
+
+// Launch grid of the multi-step batched launch from step t on: the tiles of
+// the runs still active, rounded up to a power of two (blocks past them exit).
+unsigned batch_fgrid_at(const lbm_cde* h, int64_t t) {
+  int64_t active = 0;
+  for (size_t k = 0; k < h->batch_order.size(); ++k) {
+    const int64_t ms = h->runs[h->batch_order[k]].d.max_steps;
+    if (ms >= 0 && t >= ms) break;
+    active = h->batch_prefix_f[k + 1];
+  }
+  const int64_t total = h->batch_prefix_f.back();
+  int64_t g = 64;
+  while (g < active && g < total) g *= 2;
+  return (unsigned)std::max<int64_t>(1, std::min(g, total));
+}
+
+// Whether steps t .. t + n of a batch may take the multi-step launch: it is
+// on, and no run's budget ends strictly inside the span.
+bool batch_fused_span(const lbm_cde* h, int64_t t, int64_t n) {
+  if (h->batch_fuse.fuse < 2 || n < 2 * h->batch_fuse.fuse) return false;
+  for (const Run& r : h->runs) {
+    const int64_t ms = r.d.max_steps;
+    if (ms >= 0 && ms > t && ms < t + n) return false;
+  }
+  return true;
 }
 
 // Per-run set-up of lbm_cde_init (errors go to the thread's init error text).
@@ -1196,12 +1340,14 @@ int init_runs(lbm_cde* h, const lbm_cde_run_desc* runs, int32_t nruns, const dou
     h->dev_order = (int32_t*)p;
     p += align_up(sizeof(int32_t) * nruns);
     h->dev_clock = (int64_t*)p;
-    p += align_up(2 * sizeof(int64_t));
+    p += align_up(3 * sizeof(int64_t));
     h->batch_partial = (double*)p;
     p += align_up(sizeof(double) * 3 * kBatchRedBlocks * nruns);
     h->dev_brun = (BatchRun*)p;
     p += align_up(sizeof(BatchRun) * nruns);
     h->dev_tiles32 = (uint32_t*)p;
+    p += align_up(sizeof(uint32_t) * (nruns + 1));
+    h->dev_tiles_f = (uint32_t*)p;
     std::vector<RunArgs> args;
     h->batch_lean = true;
     for (auto& r : h->runs) {
@@ -1222,7 +1368,7 @@ int init_runs(lbm_cde* h, const lbm_cde_run_desc* runs, int32_t nruns, const dou
     hipStream_t s = h->stream;
     HIP_TRY(nullptr, hipMemcpyAsync(h->dev_runs, args.data(), sizeof(RunArgs) * nruns, hipMemcpyHostToDevice, s));
     HIP_TRY(nullptr, hipMemcpyAsync(h->dev_order, order.data(), sizeof(int32_t) * nruns, hipMemcpyHostToDevice, s));
-    HIP_TRY(nullptr, hipMemsetAsync(h->dev_clock, 0, 2 * sizeof(int64_t), s));
+    HIP_TRY(nullptr, hipMemsetAsync(h->dev_clock, 0, 3 * sizeof(int64_t), s));
     HIP_TRY(nullptr, hipStreamSynchronize(s));
     h->batched = true;
     Variant bv = h->batch_var;
@@ -1230,6 +1376,15 @@ int init_runs(lbm_cde* h, const lbm_cde_run_desc* runs, int32_t nruns, const dou
     if (const char* e = std::getenv("LBM_CDE_BATCH"))  // "BX[xNT[xGRID]]" fixes the batched launch variant
       if (std::sscanf(e, "%dx%dx%d", &bx, &nt, &grid) >= 1) bv = Variant{bx, 1, 1, nt != 0, 0, grid};
     if (apply_batch_variant(h, bv, nullptr)) return fail_init(LBM_CDE_EINVAL, "init: %s", h->err.c_str());
+    // several steps per launch by default where every run allows it (not
+    // when LBM_CDE_BATCH fixes the one-step launch); LBM_CDE_BATCH_FUSE =
+    // "BXxBYxNYxT" fixes the multi-step one
+    Variant fv = h->runs[0].dbl ? Variant{64, 4, 2, true, 0, 0, 4} : Variant{64, 8, 2, true, 0, 0, 4};
+    int fbx, fby, fny, ft;
+    if (const char* e = std::getenv("LBM_CDE_BATCH_FUSE"))
+      if (std::sscanf(e, "%dx%dx%dx%d", &fbx, &fby, &fny, &ft) == 4) fv = Variant{fbx, fby, fny, true, 0, 0, ft};
+    if (!std::getenv("LBM_CDE_BATCH") && find_batch_fused(h, fv) && apply_batch_fused(h, fv))
+      return fail_init(LBM_CDE_EINVAL, "init: %s", h->err.c_str());
   }
   HIP_TRY(nullptr, hipStreamCreateWithFlags(&h->capture, hipStreamNonBlocking));
   return LBM_CDE_OK;
@@ -1257,7 +1412,7 @@ unsigned batch_grid_at(const lbm_cde* h, int64_t t) {
 // One batched step: the persistent kernel, then the clock tick.
 void launch_batch_step(lbm_cde* h, hipStream_t s, unsigned grid) {
   find_batch(h->batch_var)->fn[h->runs[0].dbl ? 1 : 0](h, s, grid);
-  hipLaunchKernelGGL(k_tick, dim3(1), dim3(64), 0, s, h->dev_clock, 0);
+  hipLaunchKernelGGL(k_tick, dim3(1), dim3(64), 0, s, h->dev_clock, 0, 1);
 }
 
 // Sample the x-moments of every run into hist[row], then advance the row clock.
@@ -1272,14 +1427,26 @@ void launch_batch_sample(lbm_cde* h, hipStream_t s, double* hist) {
                        h->dev_runs, Q, h->dev_clock, h->batch_partial);
   hipLaunchKernelGGL(k_batch_xmom_final, dim3(nr), dim3(RED_THREADS), 0, s, h->batch_partial, kBatchRedBlocks, nr,
                      h->dev_clock, hist);
-  hipLaunchKernelGGL(k_tick, dim3(1), dim3(64), 0, s, h->dev_clock, 1);
+  hipLaunchKernelGGL(k_tick, dim3(1), dim3(64), 0, s, h->dev_clock, 1, 1);
 }
 
 // Capture `steps` batched steps of the given grid (and, with hist, one
-// sample) as a graph.
-int capture_batch(lbm_cde* h, int64_t steps, double* hist, unsigned grid, hipGraphExec_t* out) {
+// sample) as a graph.  With gridf > 0 the steps go in pairs of multi-step
+// launches of that grid as far as they fit, the rest one per launch.
+int capture_batch(lbm_cde* h, int64_t steps, double* hist, unsigned grid, hipGraphExec_t* out, unsigned gridf = 0) {
   HIP_TRY(h, hipStreamBeginCapture(h->capture, hipStreamCaptureModeThreadLocal));
-  for (int64_t t = 0; t < steps; ++t) launch_batch_step(h, h->capture, grid);
+  int64_t one = steps;
+  if (gridf > 0) {
+    const int T = h->batch_fuse.fuse;
+    const int64_t q = steps / (2 * T) * 2;
+    const BatchFn fn = find_batch_fused(h, h->batch_fuse);
+    for (int64_t k = 0; k < q; ++k) {
+      fn(h, h->capture, gridf);
+      hipLaunchKernelGGL(k_tick, dim3(1), dim3(64), 0, h->capture, h->dev_clock, 2, T);
+    }
+    one = steps - q * T;
+  }
+  for (int64_t t = 0; t < one; ++t) launch_batch_step(h, h->capture, grid);
   if (hist) launch_batch_sample(h, h->capture, hist);
   hipGraph_t g = nullptr;
   hipError_t e = hipStreamEndCapture(h->capture, &g);
@@ -1303,11 +1470,15 @@ int batch_step(lbm_cde* h, int64_t n) {
   while (done < n) {
     const unsigned grid = batch_grid_at(h, h->global_steps);
     if (n - done >= kGraphSteps) {
-      hipGraphExec_t& g = h->batch_graphs[grid];
+      const bool fused = batch_fused_span(h, h->global_steps, kGraphSteps);
+      const unsigned gridf = fused ? batch_fgrid_at(h, h->global_steps) : 0;
+      auto& graphs = fused ? h->batch_fgraphs : h->batch_graphs;
+      const unsigned key = fused ? gridf : grid;
+      hipGraphExec_t& g = graphs[key];
       if (!g) {
-        const int rc = capture_batch(h, kGraphSteps, nullptr, grid, &g);
+        const int rc = capture_batch(h, kGraphSteps, nullptr, grid, &g, gridf);
         if (rc) {
-          h->batch_graphs.erase(grid);
+          graphs.erase(key);
           return rc;
         }
       }
@@ -1393,17 +1564,18 @@ int time_variant(lbm_cde* h, Run& r, const Variant& v, int trials, double* ms) {
   return LBM_CDE_OK;
 }
 
-// Time `trials` launches of the batched step kernel without advancing the
-// clock: each reads the current buffers and writes the other ones, so the
-// state of every run is unchanged.
-int time_batch(lbm_cde* h, int trials, double* ms) {
-  const BatchFn fn = find_batch(h->batch_var)->fn[h->runs[0].dbl ? 1 : 0];
+// Time `trials` launches of the batched step kernel (or of the multi-step
+// one, per step) without advancing the clock: each reads the current buffers
+// and writes the other ones, so the state of every run is unchanged.
+int time_batch(lbm_cde* h, int trials, double* ms, const Variant* fused = nullptr) {
+  const BatchFn fn = fused ? find_batch_fused(h, *fused) : find_batch(h->batch_var)->fn[h->runs[0].dbl ? 1 : 0];
+  const unsigned grid = fused ? (unsigned)h->batch_prefix_f.back() : h->batch_grid;
   hipEvent_t e0, e1;
   HIP_TRY(h, hipEventCreate(&e0));
   HIP_TRY(h, hipEventCreate(&e1));
-  fn(h, h->stream, h->batch_grid);  // warm-up
+  fn(h, h->stream, grid);  // warm-up
   HIP_TRY(h, hipEventRecord(e0, h->stream));
-  for (int t = 0; t < trials; ++t) fn(h, h->stream, h->batch_grid);
+  for (int t = 0; t < trials; ++t) fn(h, h->stream, grid);
   HIP_TRY(h, hipEventRecord(e1, h->stream));
   HIP_TRY(h, hipEventSynchronize(e1));
   float elapsed = 0.f;
@@ -1411,7 +1583,7 @@ int time_batch(lbm_cde* h, int trials, double* ms) {
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   HIP_TRY(h, hipGetLastError());
-  *ms = elapsed / trials;
+  *ms = elapsed / trials / (fused ? fused->fuse : 1);  // per step
   return LBM_CDE_OK;
 }
 
@@ -1743,16 +1915,24 @@ int lbm_cde_run_sampled(lbm_cde_handle h, int64_t n, int64_t every, double* hist
     if (h->sample_every != every || h->sample_hist != hist) {
       for (auto& kv : h->sample_graphs) (void)hipGraphExecDestroy(kv.second);
       h->sample_graphs.clear();
+      for (auto& kv : h->sample_fgraphs) (void)hipGraphExecDestroy(kv.second);
+      h->sample_fgraphs.clear();
       h->sample_every = every;
       h->sample_hist = hist;
     }
     for (int64_t k = 0; k < rows; ++k) {
       const unsigned grid = batch_grid_at(h, h->global_steps);
-      hipGraphExec_t& g = h->sample_graphs[grid];
+      const bool fused = batch_fused_span(h, h->global_steps, every);
+      const unsigned gridf = fused ? batch_fgrid_at(h, h->global_steps) : 0;
+      hipGraphExec_t* gp;
+      if (fused) gp = &h->sample_fgraphs[((uint64_t)gridf << 32) | grid];
+      else gp = &h->sample_graphs[grid];
+      hipGraphExec_t& g = *gp;
       if (!g) {
-        const int rc = capture_batch(h, every, hist, grid, &g);
+        const int rc = capture_batch(h, every, hist, grid, &g, gridf);
         if (rc) {
-          h->sample_graphs.erase(grid);
+          if (fused) h->sample_fgraphs.erase(((uint64_t)gridf << 32) | grid);
+          else h->sample_graphs.erase(grid);
           return rc;
         }
       }
@@ -1830,14 +2010,40 @@ int lbm_cde_tune(lbm_cde_handle h, int32_t trials) {
   if (trials < 1) return fail(h, LBM_CDE_EINVAL, "tune: trials must be >= 1");
   if (h->batched) {
     const std::string key = batch_tune_key(h);
-    Variant v;
-    if (cache_lookup(key, v) && find_batch(v)) return apply_batch_variant(h, v, nullptr);
-    double best = 1e300;
-    Variant best_v = h->batch_var;
+    const Variant off{64, 8, 2, true, 0, 0, 1};
+    Variant v, v1;
+    if (cache_lookup(key, v)) {
+      if (v.fuse == 1 && find_batch(v)) {
+        const int rc = apply_batch_variant(h, v, nullptr);
+        return rc ? rc : apply_batch_fused(h, off);
+      }
+      if (v.fuse > 1 && cache_lookup(key + "/1", v1) && find_batch(v1) && find_batch_fused(h, v)) {
+        const int rc = apply_batch_variant(h, v1, nullptr);
+        return rc ? rc : apply_batch_fused(h, v);
+      }
+    }
+    // one-step launches (kept for the blocks in which a budget ends), then
+    // the multi-step ones, per step
+    double best1 = 1e300;
+    Variant best_v1 = h->batch_var;
     for (const Variant& c : batch_candidates()) {
       double ms = 0.0;
       int rc = apply_batch_variant(h, c, nullptr);
       if (!rc) rc = time_batch(h, trials, &ms);
+      if (rc) return rc;
+      if (ms < best1) {
+        best1 = ms;
+        best_v1 = c;
+      }
+    }
+    int rc = apply_batch_variant(h, best_v1, nullptr);
+    if (rc) return rc;
+    double best = best1;
+    Variant best_v = best_v1;
+    for (const Variant& c : batch_fused_candidates(h)) {
+      double ms = 0.0;
+      rc = apply_batch_fused(h, c);
+      if (!rc) rc = time_batch(h, trials, &ms, &c);
       if (rc) return rc;
       if (ms < best) {
         best = ms;
@@ -1845,7 +2051,8 @@ int lbm_cde_tune(lbm_cde_handle h, int32_t trials) {
       }
     }
     cache_store(key, best_v, best);
-    return apply_batch_variant(h, best_v, nullptr);
+    if (best_v.fuse > 1) cache_store(key + "/1", best_v1, best1);
+    return apply_batch_fused(h, best_v.fuse > 1 ? best_v : off);
   }
   for (auto& r : h->runs) {
     const std::string key = tune_key(r);
@@ -1895,7 +2102,8 @@ int lbm_cde_get_variant(lbm_cde_handle h, int32_t run, int32_t* out) {
   Run* r = get_run(h, run);
   if (!r || !out) return fail(h, LBM_CDE_EINVAL, "get_variant: bad handle, run or pointer");
   if (h->batched) {
-    variant_out(h->batch_var, h->batch_grid, out);
+    if (h->batch_fuse.fuse > 1) variant_out(h->batch_fuse, (int)h->batch_prefix_f.back(), out);
+    else variant_out(h->batch_var, h->batch_grid, out);
     return LBM_CDE_OK;
   }
   Variant v = r->var;
@@ -1907,14 +2115,14 @@ int lbm_cde_get_variant(lbm_cde_handle h, int32_t run, int32_t* out) {
 int lbm_cde_variant_count(lbm_cde_handle h, int32_t run, int32_t* count) {
   Run* r = get_run(h, run);
   if (!r || !count) return fail(h, LBM_CDE_EINVAL, "variant_count: bad handle, run or pointer");
-  *count = (int32_t)(h->batched ? batch_candidates().size() : run_candidates(*r).size());
+  *count = (int32_t)(h->batched ? batch_all_candidates(h).size() : run_candidates(*r).size());
   return LBM_CDE_OK;
 }
 
 int lbm_cde_variant_at(lbm_cde_handle h, int32_t run, int32_t index, int32_t* out) {
   Run* r = get_run(h, run);
   if (!r || !out) return fail(h, LBM_CDE_EINVAL, "variant_at: bad handle, run or pointer");
-  const std::vector<Variant> c = h->batched ? batch_candidates() : run_candidates(*r);
+  const std::vector<Variant> c = h->batched ? batch_all_candidates(h) : run_candidates(*r);
   if (index < 0 || index >= (int32_t)c.size())
     return fail(h, LBM_CDE_EINVAL, "variant_at: index %d outside [0, %zu)", index, c.size());
   variant_out(c[index], c[index].grid, out);
@@ -1925,7 +2133,16 @@ int lbm_cde_set_variant(lbm_cde_handle h, int32_t run, const int32_t* v) {
   Run* r = get_run(h, run);
   if (!r || !v) return fail(h, LBM_CDE_EINVAL, "set_variant: bad handle, run or pointer");
   const Variant c{v[0], v[1], v[2], v[3] != 0, v[4], v[5], v[6]};
-  if (h->batched) return apply_batch_variant(h, c, nullptr);
+  if (h->batched) {
+    if (c.fuse > 1) {
+      if (!find_batch_fused(h, c))
+        return fail(h, LBM_CDE_EINVAL, "set_variant: %dx%dx%d with %d steps per launch is not built for this batch",
+                    c.bx, c.by, c.ny, c.fuse);
+      return apply_batch_fused(h, c);
+    }
+    const int rc = apply_batch_variant(h, c, nullptr);
+    return rc ? rc : apply_batch_fused(h, Variant{64, 8, 2, true, 0, 0, 1});
+  }
   if (c.grid != 0 || c.xcd < 0 || c.xcd > 2 || !find_step(*r, c))
     return fail(h, LBM_CDE_EINVAL,
                 "set_variant: variant %dx%dx%d nt=%d order=%d grid=%d steps=%d is not built for run %d", c.bx, c.by,

@@ -17,6 +17,9 @@ must be bitwise that of the run's default (one-step) variant:
   field replaced between calls;
 * a handle of two runs of which only one steps several steps per launch, so
   the runs' buffers drift apart and the graph path is left;
+* a batch of channels in one multi-step launch over all their tiles, with
+  budgets ending inside and at the end of 32-step blocks (one step per launch
+  there), against one-step batched launches (states and sampled histories);
 * walls in y (bounce-back, halfway mirror, the paper's on-node mirror) on a
   channel whose height is no multiple of the tile height;
 * grids too small for a tile and its halo, walls in x, and a per-node
@@ -240,6 +243,95 @@ def test_walls_in_y(wall):
         err = rel(phis[-1], oref)
         print(f"oracle error {err:.2e}", flush=True)
         assert err <= TOL[precision]
+
+
+FBATCH = [  # (h, Pe, tau, nx, max_steps, wall): budgets inside and at the end of 32-step blocks
+    (12, 20.0, 0.8, 300, -1, "specular"),
+    (20, 8.0, 1.4, 150, 45, "bounce"),
+    (7, 40.0, 0.6, 400, -1, "node"),
+    (16, 12.0, 1.1, 200, 64, "specular"),
+    (9, 5.0, 1.9, 160, 17, "bounce"),
+]
+
+
+def _fbatch(precision):
+    from paper_1404_2363_amd.solver import Solver
+    wls, per = [], []
+    for h, Pe, tau, nx, budget, wall in FBATCH:
+        wl = W.taylor_aris_channel(h, Pe, tau, nx=nx, wall="specular", steps=40)
+        wl.walls = ("periodic", wall)
+        wls.append(wl)
+        per.append({"max_steps": budget, "heat": [1 / tau, 1 / tau], "xref0": wl.meta["x0"],
+                    "xref_drift": wl.meta["U_node_mean"]})
+    return wls, per, (lambda: Solver(wls, precision, per_run=per))
+
+
+def _batch_one_step(s):
+    return next(v for v in s.variants() if v["steps_per_launch"] == 1 and v["block"] == (256, 1)
+                and v["nt_stores"] and v["grid"] == 0)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_batch_multi_step(precision):
+    """A batch of channels (walls in y of all three kinds, budgets ending inside
+    and at the end of 32-step blocks): the multi-step batched launch, the
+    default here, and every other multi-step candidate equal one-step batched
+    launches bitwise after every call; each run equals the oracle at its own
+    budget."""
+    wls, per, make = _fbatch(precision)
+    seq = [5, 64, 3, 32, 40]
+    ref = make()
+    default = ref.variant()
+    assert default["steps_per_launch"] == 4
+    multi = [v for v in ref.variants() if v["steps_per_launch"] > 1]
+    ref.set_variant(_batch_one_step(ref))
+    assert ref.variant()["steps_per_launch"] == 1
+    want = []
+    for n in seq:
+        ref.step(n)
+        want.append([_phi(ref, i) for i in range(len(wls))])
+    done = [ref.steps_done(i) for i in range(len(wls))]
+    ref.close()
+    print(f"case batch multi-step {precision}: default {default}, {len(multi)} multi-step candidates", flush=True)
+    assert len(multi) >= 3
+    for v in multi:
+        s = make()
+        s.set_variant(v)
+        assert s.variant()["steps_per_launch"] == v["steps_per_launch"]
+        for k, n in enumerate(seq):
+            s.step(n)
+            for i in range(len(wls)):
+                np.testing.assert_array_equal(_phi(s, i), want[k][i], err_msg=f"{v} call {k} run {i}")
+        assert [s.steps_done(i) for i in range(len(wls))] == done
+        s.close()
+    for i, (wl, p) in enumerate(zip(wls, per)):
+        steps = sum(seq) if p["max_steps"] < 0 else p["max_steps"]
+        r, _ = O.run_workload(wl, steps=steps, heat_rule=p["heat"])
+        assert rel(want[-1][i], r) <= TOL[precision], i
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_batch_multi_step_sampled_history(precision):
+    """In-graph x-moment sampling with multi-step launches (samples every 20
+    steps: four-step pairs and one-step launches, and one step per launch in
+    the spans where a budget ends; then every 40: multi-step only) equals the
+    one-step batch bitwise, history and states."""
+    import torch
+    wls, per, make = _fbatch(precision)
+    out = []
+    for multi in (True, False):
+        s = make()
+        if not multi:
+            s.set_variant(_batch_one_step(s))
+        hist = torch.zeros((9, len(wls), 3), dtype=torch.float64, device="cuda:0")
+        s.run_sampled(100, 20, hist)
+        s.run_sampled(80, 40, hist)
+        assert s.samples_written() == 7
+        out.append((hist.cpu().numpy(), [_phi(s, i) for i in range(len(wls))]))
+        s.close()
+    np.testing.assert_array_equal(out[0][0], out[1][0])
+    for i in range(len(wls)):
+        np.testing.assert_array_equal(out[0][1][i], out[1][1][i])
 
 
 def test_refused_where_a_tile_and_its_halo_do_not_fit():
