@@ -122,19 +122,36 @@ def roofline(v, name, real):
     return out
 
 
-def profiled_segment_traffic(K):
-    """HBM bytes of one adjoint checkpoint segment of K steps from the
-    per-kernel counters: K - 1 recomputed steps that store their state, one
-    that does not, and the first, K - 2 middle and last reverse steps."""
+def profiled_segment_traffic(K, T=4):
+    """HBM bytes of one FP32 adjoint checkpoint segment of K steps launched as
+    segment_plan_bytes describes, from the per-kernel counters: multi-step
+    forward and reverse launches (each averaged over its dispatches), the
+    first reverse step, and the one-step launches of the left-over steps."""
     rec = _profile("adjoint_segment_2048_fp32")
     if rec is None:
         return None
     t = {k: v["traffic_bytes_per_launch"] for k, v in rec["kernels"].items()}
-    need = ("forward_v", "forward_v_last", "reverse_first", "reverse", "reverse_last")
-    if any(n not in t for n in need):
+    out, k = 0.0, 0
+    try:
+        while k < K:
+            if k + T <= K:
+                out += t["forward_multi"]
+                k += T
+            else:
+                out += t["forward_v"] if k + 1 < K else t["forward_v_last"]
+                k += 1
+        out += t["reverse_first"]
+        k = K - 2
+        while k >= 0:
+            if k - T + 1 >= 0:
+                out += t["reverse_multi_fold"] if k - T + 1 == 0 else t["reverse_multi"]
+                k -= T
+            else:
+                out += t["reverse_last"] if k == 0 else t["reverse"]
+                k -= 1
+    except KeyError:
         return None
-    return ((K - 1) * t["forward_v"] + t["forward_v_last"] + t["reverse_first"] + (K - 2) * t["reverse"]
-            + t["reverse_last"])
+    return out
 
 
 def log(msg):
@@ -371,7 +388,8 @@ def adjoint_all_ics_variant(precision="fp32"):
 def adjoint_segment_variant(n=2048, K=16, precision="fp32"):
     """One checkpoint segment of the adjoint on an n^2 grid with a per-node D
     field (FP32): K forward steps recomputed from the checkpoint, then K
-    reverse steps.  Algorithmic bytes per node: a recomputed step reads 36
+    reverse steps, several per launch (segment_plan_bytes).  Algorithmic
+    bytes per node of one step per launch: a recomputed step reads 36
     (populations) + 12 (per-node flux block A) and writes 36 (populations,
     not for the last step) + 8 (v); a reverse step gathers 36 (mu), reads 8
     (v) + 12 (A), writes 36 (mu) and moves the gradient: 12 (FP32 partial
@@ -413,14 +431,47 @@ def adjoint_segment_variant(n=2048, K=16, precision="fp32"):
     finite = bool(torch.isfinite(grad).all())
     s.close()
     nodes = n * n
-    fwd = (K - 1) * 92 + 56
-    rev = K * 92 + 12 + (K - 2) * 24 + 60 + 8
-    byts = nodes * (fwd + rev)
+    one_step = (K - 1) * 92 + 56 + K * 92 + 12 + (K - 2) * 24 + 60 + 8
+    plan = segment_plan_bytes(K, 4)
+    byts = nodes * plan
     return {"precision": precision, "nodes": nodes, "segment_steps": K, "seconds_per_segment": t,
             "forward_plus_reverse_mlups": nodes * K / t / 1e6,
             "bytes_per_node": {"forward_step": 92, "reverse_step_first": 104, "reverse_step": 116,
-                               "reverse_step_last": 152, "segment": fwd + rev},
-            "achieved_gbs": byts / t / 1e9, "hbm_frac": byts / t / 1e9 / HBM_PEAK_GBS, "finite": finite}
+                               "reverse_step_last": 152, "segment_one_step_per_launch": one_step,
+                               "segment": plan},
+            "steps_per_launch": 4, "achieved_gbs": byts / t / 1e9, "hbm_frac": byts / t / 1e9 / HBM_PEAK_GBS,
+            "finite": finite}
+
+
+def segment_plan_bytes(K, T):
+    """Algorithmic bytes per node of one FP32 checkpoint segment as the
+    library launches it on a periodic grid that spans its tiles: forward
+    chunks of T steps from the checkpoint (state read 36 and, except at the
+    segment's end, written 36, flux block 12, v 8 per step), the rest one step
+    per launch (92, the last 56); the first reverse step one per launch (104 +
+    the 8-byte injection), reverse chunks of T steps down to the start (mu 36
+    + 36, v 8 per step, flux block 12, FP32 partial read and written 24, or
+    partial read 12 and FP64 gradient read and written 48 for the chunk that
+    ends at the segment's start), the left-over steps one per launch (116,
+    the segment's first step 152)."""
+    out, k = 0, 0
+    while k < K:                                        # forward
+        if k + T <= K:
+            out += 36 + 12 + 8 * T + (36 if k + T < K else 0)
+            k += T
+        else:
+            out += 92 if k + 1 < K else 56
+            k += 1
+    out += 104 + 8                                      # first reverse step, with the injection
+    k = K - 2
+    while k >= 0:                                       # reverse
+        if k - T + 1 >= 0:
+            out += 72 + 8 * T + 12 + (12 + 48 if k - T + 1 == 0 else 24)
+            k -= T
+        else:
+            out += 152 if k == 0 else 116
+            k -= 1
+    return out
 
 
 def copy_probe():

@@ -91,6 +91,50 @@ LBM_FORCEINLINE void adjoint_v(const R (&f)[9], R ux, R uy, R phi_ref, const Rel
   vy = n5 + (R)0.5 * r.s6 * n6;
 }
 
+// The reverse step at one node: from the gathered adjoint populations l
+// (lambda_{t+1} at the node, injection included), the forward step's v, the
+// velocity and the relaxation rates, the outgoing mu_t (m) and the gradient
+// contributions g_c (xx, yy, xy; before the 1/kappa factor).
+template <typename R>
+LBM_FORCEINLINE void adjoint_node(const R (&l)[9], R vx, R vy, R ux, R uy, const Rel2<R>& r, R (&m)[9], R (&gc)[3]) {
+  // w = M^-T lambda (moments of lambda over the squared row norms)
+  const R sa = l[1] + l[2] + l[3] + l[4], sd = l[5] + l[6] + l[7] + l[8];
+  const R w1 = ((R)2 * sd - sa - (R)4 * l[0]) * (R)(1.0 / 36.0);
+  const R w2 = ((R)4 * l[0] - (R)2 * sa + sd) * (R)(1.0 / 36.0);
+  const R lx13 = l[1] - l[3], lx58 = l[5] - l[6] - l[7] + l[8];
+  const R ly24 = l[2] - l[4], ly56 = l[5] + l[6] - l[7] - l[8];
+  const R w3 = (lx13 + lx58) * (R)(1.0 / 6.0), w4 = (lx58 - (R)2 * lx13) * (R)(1.0 / 12.0);
+  const R w5 = (ly24 + ly56) * (R)(1.0 / 6.0), w6 = (ly56 - (R)2 * ly24) * (R)(1.0 / 12.0);
+  const R w7 = (l[1] - l[2] + l[3] - l[4]) * (R)0.25, w8 = (l[5] - l[6] + l[7] - l[8]) * (R)0.25;
+
+  // gradient with respect to the D components (xx, yy, xy) of this node
+  const R awx = r.axx * w3 + r.axy * w5, awy = r.axy * w3 + r.ayy * w5;
+  const R avx = r.axx * vx + r.axy * vy, avy = r.axy * vx + r.ayy * vy;
+  gc[0] = awx * avx;
+  gc[1] = awy * avy;
+  gc[2] = awx * avy + awy * avx;
+
+  // z = S^T w (Eq. 31 transposed)
+  const R z1 = r.s1 * w1, z2 = r.s2 * w2;
+  const R z3 = r.axx * w3 + r.axy * w5, z5 = r.axy * w3 + r.ayy * w5;
+  const R z4 = r.s4 * w4 + r.c34 * w3 + r.c54 * w5;
+  const R z6 = r.s6 * w6 + r.c36 * w3 + r.c56 * w5;
+  const R z7 = r.s7 * w7, z8 = r.s8 * w8;
+  const R ez = (R)2 * (z2 - z1) + ux * (z3 - z4) + uy * (z5 - z6);   // E^T z
+  // mu = lambda - M^T z + E^T z (every population)
+  const R ax = -z1 - (R)2 * z2, dg = (R)2 * z1 + z2;
+  const R q3 = z3 - (R)2 * z4, q5 = z5 - (R)2 * z6, p3 = z3 + z4, p5 = z5 + z6;
+  m[0] = l[0] - (R)4 * (z2 - z1) + ez;
+  m[1] = l[1] - (ax + q3 + z7) + ez;
+  m[2] = l[2] - (ax + q5 - z7) + ez;
+  m[3] = l[3] - (ax - q3 + z7) + ez;
+  m[4] = l[4] - (ax - q5 - z7) + ez;
+  m[5] = l[5] - (dg + p3 + p5 + z8) + ez;
+  m[6] = l[6] - (dg - p3 + p5 - z8) + ez;
+  m[7] = l[7] - (dg - p3 - p5 + z8) + ez;
+  m[8] = l[8] - (dg + p3 - p5 - z8) + ez;
+}
+
 // One forward step of the segment recomputation (256-wide row tiles): the
 // pull step of k_step_d2q9 from a.src to a.dst (when STORE; the same
 // arithmetic, so the states are bitwise those of the run), plus v of every
@@ -224,42 +268,8 @@ __global__ __launch_bounds__(512) void k_adjoint_d2q9(const RunArgs a, const R* 
 #pragma unroll
     for (int i = 0; i < 9; ++i) l[i] += g;
   }
-
-  // w = M^-T lambda (moments of lambda over the squared row norms)
-  const R sa = l[1] + l[2] + l[3] + l[4], sd = l[5] + l[6] + l[7] + l[8];
-  const R w1 = ((R)2 * sd - sa - (R)4 * l[0]) * (R)(1.0 / 36.0);
-  const R w2 = ((R)4 * l[0] - (R)2 * sa + sd) * (R)(1.0 / 36.0);
-  const R lx13 = l[1] - l[3], lx58 = l[5] - l[6] - l[7] + l[8];
-  const R ly24 = l[2] - l[4], ly56 = l[5] + l[6] - l[7] - l[8];
-  const R w3 = (lx13 + lx58) * (R)(1.0 / 6.0), w4 = (lx58 - (R)2 * lx13) * (R)(1.0 / 12.0);
-  const R w5 = (ly24 + ly56) * (R)(1.0 / 6.0), w6 = (ly56 - (R)2 * ly24) * (R)(1.0 / 12.0);
-  const R w7 = (l[1] - l[2] + l[3] - l[4]) * (R)0.25, w8 = (l[5] - l[6] + l[7] - l[8]) * (R)0.25;
-
-  // gradient with respect to the D components (xx, yy, xy) of this node
-  const R awx = r.axx * w3 + r.axy * w5, awy = r.axy * w3 + r.ayy * w5;
-  const R avx = r.axx * vx + r.axy * vy, avy = r.axy * vx + r.ayy * vy;
-  const R gc[3] = {awx * avx, awy * avy, awx * avy + awy * avx};
-
-  // z = S^T w (Eq. 31 transposed)
-  const R z1 = r.s1 * w1, z2 = r.s2 * w2;
-  const R z3 = r.axx * w3 + r.axy * w5, z5 = r.axy * w3 + r.ayy * w5;
-  const R z4 = r.s4 * w4 + r.c34 * w3 + r.c54 * w5;
-  const R z6 = r.s6 * w6 + r.c36 * w3 + r.c56 * w5;
-  const R z7 = r.s7 * w7, z8 = r.s8 * w8;
-  const R ez = (R)2 * (z2 - z1) + ux * (z3 - z4) + uy * (z5 - z6);   // E^T z
-  // mu = lambda - M^T z + E^T z (every population)
-  const R ax = -z1 - (R)2 * z2, dg = (R)2 * z1 + z2;
-  const R q3 = z3 - (R)2 * z4, q5 = z5 - (R)2 * z6, p3 = z3 + z4, p5 = z5 + z6;
-  R m[9];
-  m[0] = l[0] - (R)4 * (z2 - z1) + ez;
-  m[1] = l[1] - (ax + q3 + z7) + ez;
-  m[2] = l[2] - (ax + q5 - z7) + ez;
-  m[3] = l[3] - (ax - q3 + z7) + ez;
-  m[4] = l[4] - (ax - q5 - z7) + ez;
-  m[5] = l[5] - (dg + p3 + p5 + z8) + ez;
-  m[6] = l[6] - (dg - p3 + p5 - z8) + ez;
-  m[7] = l[7] - (dg - p3 - p5 + z8) + ez;
-  m[8] = l[8] - (dg + p3 - p5 - z8) + ez;
+  R m[9], gc[3];
+  adjoint_node<R>(l, vx, vy, ux, uy, r, m, gc);
   double gout[3];
   float pout[3];
 #pragma unroll

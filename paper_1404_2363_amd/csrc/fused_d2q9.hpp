@@ -32,6 +32,7 @@
 // plane are 32-bit (nodes * sizeof(R) < 2^32).
 #pragma once
 
+#include "adjoint_d2q9.hpp"
 #include "d2q9.hpp"
 
 namespace lbm {
@@ -52,9 +53,14 @@ LBM_FORCEINLINE void wall_source(const RunArgs& a, int32_t y, int32_t ny, int& p
 }
 
 // T steps of output tile (txi, tyi) of the run described by a; block (BX,
-// BY) threads, tile BX x (BY * NY).
-template <typename R, int BX, int BY, int NY, int T, int UK, bool WY>
-LBM_FORCEINLINE void fused_tile(const RunArgs& a, uint32_t txi, uint32_t tyi) {
+// BY) threads, tile BX x (BY * NY).  With VOUT (the adjoint's forward
+// recomputation) every step also stores v = (n3 + s4 n4 / 2, n5 + s6 n6 / 2)
+// of the tile's own nodes (adjoint_v; two planes of nx ny values at
+// vout + s * vstep bytes for the launch's step s), and the final state goes to
+// memory only with store_end.
+template <typename R, int BX, int BY, int NY, int T, int UK, bool WY, bool VOUT = false>
+LBM_FORCEINLINE void fused_tile(const RunArgs& a, uint32_t txi, uint32_t tyi, char* vout = nullptr,
+                                int64_t vstep = 0, bool store_end = true) {
   static_assert(T >= 2, "one step per launch is k_step_d2q9");
   constexpr int NTH = BX * BY, TX = BX, TY = BY * NY, RG = T - 1;
   constexpr int W0 = TX + 2 * RG, H0 = TY + 2 * RG, C0 = W0 * H0;
@@ -108,8 +114,21 @@ LBM_FORCEINLINE void fused_tile(const RunArgs& a, uint32_t txi, uint32_t tyi) {
     }
   };
 
-  // collision of one node at periodic image (x, y); (lx, ly) in the widened tile
-  auto collide = [&](R(&f)[9], int32_t x, int32_t y, int lx, int ly) {
+  // v of one node of the tile itself at the launch's step st
+  auto store_v = [&](const R(&f)[9], R ux, R uy, const Rel2<R>& rel, int32_t x, int32_t y, int lx, int ly, int st) {
+    if constexpr (VOUT) {
+      if (lx < RG || lx >= RG + TX || ly < RG || ly >= RG + TY || x0 + lx >= nx || y0 + ly >= ny) return;
+      R vx, vy;
+      adjoint_v<R>(f, ux, uy, phi_ref, rel, vx, vy);
+      const uint32_t o = ((uint32_t)y * nx + x) * (uint32_t)sizeof(R);
+      char* vb = vout + st * vstep;
+      gst<R, true>(vb, o, vx);
+      gst<R, true>(vb + (size_t)nx * ny * sizeof(R), o, vy);
+    }
+  };
+  // collision of one node at periodic image (x, y); (lx, ly) in the widened
+  // tile; st = the launch's step
+  auto collide = [&](R(&f)[9], int32_t x, int32_t y, int lx, int ly, int st = 0) {
     R ux, uy;
     if constexpr (UK == 0) {
       ux = (R)a.u_const[0];
@@ -120,8 +139,14 @@ LBM_FORCEINLINE void fused_tile(const RunArgs& a, uint32_t txi, uint32_t tyi) {
     } else {
       velocity2<R>(a, x, y, ux, uy);
     }
-    if (a.node_par) collide_d2q9<R, 1>(f, ux, uy, phi_ref, node_rel2<R>(a, (int64_t)y * nx + x));
-    else collide_d2q9<R, 1>(f, ux, uy, phi_ref, rc);
+    if (a.node_par) {
+      const Rel2<R> rn = node_rel2<R>(a, (int64_t)y * nx + x);
+      store_v(f, ux, uy, rn, x, y, lx, ly, st);
+      collide_d2q9<R, 1>(f, ux, uy, phi_ref, rn);
+    } else {
+      store_v(f, ux, uy, rc, x, y, lx, ly, st);
+      collide_d2q9<R, 1>(f, ux, uy, phi_ref, rc);
+    }
   };
 
   // step 1: HBM -> LDS over the whole widened tile
@@ -193,7 +218,7 @@ LBM_FORCEINLINE void fused_tile(const RunArgs& a, uint32_t txi, uint32_t tyi) {
       const int ly = j / W0, lx = j - ly * W0;
       const int32_t y = grid_row(ly);
       if (outside(y)) continue;
-      collide(f[k], wrap_once(x0 + lx, nx), y, lx, ly);
+      collide(f[k], wrap_once(x0 + lx, nx), y, lx, ly, 0);
 #pragma unroll
       for (int i = 0; i < 9; ++i) lds[i * C0 + j] = f[k][i];
     }
@@ -222,7 +247,7 @@ LBM_FORCEINLINE void fused_tile(const RunArgs& a, uint32_t txi, uint32_t tyi) {
     for (int k = 0; k < K0; ++k) {
       if (at[k] < 0) continue;
       const int ly = at[k] / W0, lx = at[k] - ly * W0;
-      collide(f[k], wrap_once(x0 + lx, nx), grid_row(ly), lx, ly);
+      collide(f[k], wrap_once(x0 + lx, nx), grid_row(ly), lx, ly, s - 1);
 #pragma unroll
       for (int i = 0; i < 9; ++i) lds[i * C0 + at[k]] = f[k][i];
     }
@@ -238,7 +263,8 @@ LBM_FORCEINLINE void fused_tile(const RunArgs& a, uint32_t txi, uint32_t tyi) {
     if (x >= nx || y >= ny) continue;
     R g[9];
     gather(g, lx, ly, y);
-    collide(g, x, y, lx, ly);
+    collide(g, x, y, lx, ly, T - 1);
+    if (VOUT && !store_end) continue;
     const uint32_t off = ((uint32_t)y * nx + x) * (uint32_t)sizeof(R);
 #pragma unroll
     for (int i = 0; i < 9; ++i) gst<R, true>(dst + i * pb, off, g[i]);

@@ -29,6 +29,7 @@
 #include "adjoint_d2q9.hpp"
 #include "fp16_d2q9.hpp"
 #include "fused_d2q9.hpp"
+#include "adjoint_fused_d2q9.hpp"
 #include "stability.hpp"
 
 using namespace lbm;
@@ -1737,6 +1738,35 @@ void launch_step_v(const Run& r, const RunArgs& a, void* v, bool store, hipStrea
   }
 }
 
+// Several steps per launch in a checkpoint segment (adjoint_fused_d2q9.hpp):
+// the forward recomputation with v, and the reverse sweep.
+template <typename R, int BX, int BY, int NY, int T>
+void launch_fused_v(const RunArgs& a, char* vout, int64_t vstep, bool store, hipStream_t s) {
+  const unsigned blocks = (unsigned)(((a.nx + BX - 1) / BX) * ((a.ny + BY * NY - 1) / (BY * NY)));
+  const dim3 g(blocks), b(BX, BY);
+  if (a.u_kind == U_CONST)
+    hipLaunchKernelGGL((k_fused_v_d2q9<R, BX, BY, NY, T, 0>), g, b, 0, s, a, vout, vstep, (int)store);
+  else if (a.u_kind == U_SEPARABLE)
+    hipLaunchKernelGGL((k_fused_v_d2q9<R, BX, BY, NY, T, 1>), g, b, 0, s, a, vout, vstep, (int)store);
+  else
+    hipLaunchKernelGGL((k_fused_v_d2q9<R, BX, BY, NY, T, 2>), g, b, 0, s, a, vout, vstep, (int)store);
+}
+
+template <typename R, int BX, int BY, int NY, int T>
+void launch_fused_adj(const RunArgs& a, const char* v_hi, int64_t vstep, const void* mu_in, void* mu_out,
+                      double* grad, float* part, double inv_kappa, bool fold, hipStream_t s) {
+  const unsigned blocks = (unsigned)(((a.nx + BX - 1) / BX) * ((a.ny + BY * NY - 1) / (BY * NY)));
+  hipLaunchKernelGGL((k_fused_adj_d2q9<R, BX, BY, NY, T>), dim3(blocks), dim3(BX, BY), 0, s, a, v_hi, vstep,
+                     (const R*)mu_in, (R*)mu_out, grad, part, inv_kappa, (int)fold);
+}
+
+// The shape of the multi-step adjoint launches: FP32 64 x 16 tiles with 4
+// steps, FP64 64 x 8 tiles with 3 (the reverse kernel adds the tile's
+// running gradient sums to the LDS of the forward one).
+Variant adjoint_multi_variant(const Run& r) {
+  return r.dbl ? Variant{64, 4, 2, true, 0, 0, 3} : Variant{64, 8, 2, true, 0, 0, 4};
+}
+
 // Scratch of a segment of K steps: two ping-pong states, v of every step
 // ([K][2][N] in the storage precision) and the FP32 gradient partial [3][N].
 struct SegLayout {
@@ -2209,43 +2239,103 @@ int lbm_cde_adjoint_segment(lbm_cde_handle h, int32_t run, const void* ckpt, int
   char* P[2] = {segc, segc + L.state};
   float* part = (float*)(segc + L.part);
   const int K = nsteps;
-  // forward step k of the recomputation (from the checkpoint for k = 0),
-  // keeping v of each step (the last step needs no state)
-  auto fwd = [&](int k, hipStream_t s) {
+  const double inv_kappa = 1.0 / r->kappa;
+  // Launch plans.  A run periodic on both axes that spans the tile takes
+  // several steps per launch (unless a snapshot falls inside the segment, or
+  // LBM_CDE_ADJ_FUSED=0): forward chunks of T steps from the checkpoint, the
+  // remaining steps one per launch; after the first reverse step (the one
+  // that takes the injection, one per launch), reverse chunks of T steps down
+  // to the segment's start, the rest one per launch.
+  bool mid_inj = false;
+  if (inj)
+    for (int k = 0; k + 1 < K; ++k) mid_inj = mid_inj || inj[k];
+  const Variant av = adjoint_multi_variant(*r);
+  bool multi = K >= 2 && !mid_inj && !r->walls && fused_ok(*r, av);
+  if (const char* e = std::getenv("LBM_CDE_ADJ_FUSED")) multi = multi && std::atoi(e) != 0;
+  const int TA = multi ? av.fuse : 1;
+  std::vector<std::pair<int, int>> fw, rv;  // (first / highest step, steps)
+  for (int k = 0; k < K;) {
+    const int n = k + TA <= K ? TA : 1;
+    fw.emplace_back(k, n);
+    k += n;
+  }
+  for (int k = K - 2; k >= 0;) {
+    const int n = k - TA + 1 >= 0 ? TA : 1;
+    rv.emplace_back(k, n);
+    k -= n;
+  }
+  // forward launch: steps k .. k+n-1 from src into dst, v of every step
+  // (the segment's last step stores no state)
+  auto fwd = [&](int k, int n, const void* src, void* dst, hipStream_t s) {
     RunArgs a = make_args(h, *r, 0);
-    a.src = k == 0 ? ckpt : P[k & 1];
-    a.dst = P[(k + 1) & 1];
-    void* v = segc + L.v + (size_t)k * L.v_step;
-    if (r->dbl) launch_step_v<double>(*r, a, v, k + 1 < K, s);
-    else launch_step_v<float>(*r, a, v, k + 1 < K, s);
+    a.src = src;
+    a.dst = dst;
+    char* v = segc + L.v + (size_t)k * L.v_step;
+    const bool store = k + n < K;
+    if (n == 1) {
+      if (r->dbl) launch_step_v<double>(*r, a, v, store, s);
+      else launch_step_v<float>(*r, a, v, store, s);
+    } else if (r->dbl) {
+      launch_fused_v<double, 64, 4, 2, 3>(a, v, (int64_t)L.v_step, store, s);
+    } else {
+      launch_fused_v<float, 64, 8, 2, 4>(a, v, (int64_t)L.v_step, store, s);
+    }
   };
-  // reverse step k: mu_{t+1} (cur) -> mu_t (nxt).  FP32 storage gathers the
-  // segment's gradient in the FP32 partial and folds it into the FP64 output
-  // in the last reverse step.
-  auto rev = [&](int k, void* cur, void* nxt, const double* injk, hipStream_t s) {
+  // reverse launch: steps k, k-1, .., k-n+1: mu_{k+1} (cur) -> mu_{k-n+1}
+  // (nxt).  FP32 storage gathers the segment's gradient in the FP32 partial
+  // (set by the first reverse step) and folds it into the FP64 output in the
+  // last reverse step.
+  auto rev = [&](int k, int n, void* cur, void* nxt, const double* injk, hipStream_t s) {
     const RunArgs a = make_args(h, *r, 0);
-    const AdjBufs b{segc + L.v + (size_t)k * L.v_step, cur, injk, nxt, grad, part};
-    int gmode = GRAD_F64;
-    if (!r->dbl && K >= 2) gmode = k == K - 1 ? GRAD_F32_SET : (k == 0 ? GRAD_F32_FOLD : GRAD_F32_ADD);
-    if (r->dbl) launch_adjoint<double>(h, *r, a, b, gmode, 1.0 / r->kappa, s);
-    else launch_adjoint<float>(h, *r, a, b, gmode, 1.0 / r->kappa, s);
+    if (n == 1) {
+      const AdjBufs b{segc + L.v + (size_t)k * L.v_step, cur, injk, nxt, grad, part};
+      int gmode = GRAD_F64;
+      if (!r->dbl && K >= 2) gmode = k == K - 1 ? GRAD_F32_SET : (k == 0 ? GRAD_F32_FOLD : GRAD_F32_ADD);
+      if (r->dbl) launch_adjoint<double>(h, *r, a, b, gmode, inv_kappa, s);
+      else launch_adjoint<float>(h, *r, a, b, gmode, inv_kappa, s);
+    } else {
+      const char* v_hi = segc + L.v + (size_t)k * L.v_step;
+      const bool fold = k - n + 1 == 0;
+      if (r->dbl)
+        launch_fused_adj<double, 64, 4, 2, 3>(a, v_hi, (int64_t)L.v_step, cur, nxt, grad, part, inv_kappa, fold, s);
+      else
+        launch_fused_adj<float, 64, 8, 2, 4>(a, v_hi, (int64_t)L.v_step, cur, nxt, grad, part, inv_kappa, fold, s);
+    }
+  };
+  // the forward launches after the first, from buffer P[1]
+  auto fwd_rest = [&](hipStream_t s) {
+    int p = 1;
+    for (size_t j = 1; j < fw.size(); ++j) {
+      fwd(fw[j].first, fw[j].second, P[p], P[p ^ 1], s);
+      p ^= 1;
+    }
+  };
+  // the reverse launches after the first, mu_{K-1} in mu_tmp; the result ends in mu
+  auto rev_rest = [&](hipStream_t s) -> void* {
+    void* cur = mu_tmp;
+    void* nxt = mu;
+    for (const auto& c : rv) {
+      rev(c.first, c.second, cur, nxt, nullptr, s);
+      std::swap(cur, nxt);
+    }
+    return cur;
   };
   const size_t sb = (size_t)r->Q * r->plane * r->elem;
   // Graphs: with K >= 2 and no injection before the segment's last step,
-  // everything but the first forward step (which reads the caller's
+  // everything but the first forward launch (which reads the caller's
   // checkpoint) and the first reverse step (which reads the injection) has
   // the same arguments in every call with the same K and buffers: those two
   // are launched directly and the rest replayed from two captured graphs.
-  bool graphs = K >= 2;
-  if (inj)
-    for (int k = 0; k + 1 < K; ++k) graphs = graphs && !inj[k];
+  bool graphs = K >= 2 && !mid_inj;
   if (const char* e = std::getenv("LBM_CDE_ADJ_GRAPHS")) graphs = graphs && std::atoi(e) != 0;
   if (!graphs) {
-    for (int k = 0; k < K; ++k) fwd(k, h->stream);
-    void* cur = mu;
-    void* nxt = mu_tmp;
-    for (int k = K - 1; k >= 0; --k) {
-      rev(k, cur, nxt, inj ? inj[k] : nullptr, h->stream);
+    fwd(fw[0].first, fw[0].second, ckpt, P[1], h->stream);
+    fwd_rest(h->stream);
+    rev(K - 1, 1, mu, mu_tmp, inj ? inj[K - 1] : nullptr, h->stream);
+    void* cur = mu_tmp;
+    void* nxt = mu;
+    for (const auto& c : rv) {
+      rev(c.first, c.second, cur, nxt, inj ? inj[c.first] : nullptr, h->stream);
       std::swap(cur, nxt);
     }
     if (cur != mu) HIP_TRY(h, hipMemcpyAsync(mu, cur, sb, hipMemcpyDeviceToDevice, h->stream));
@@ -2254,7 +2344,7 @@ int lbm_cde_adjoint_segment(lbm_cde_handle h, int32_t run, const void* ckpt, int
   }
   auto graph = [&](int which, auto body) -> hipGraphExec_t {
     const auto key = std::make_tuple(run, K, (const void*)seg, (const void*)mu, (const void*)mu_tmp,
-                                     (const void*)grad, which);
+                                     (const void*)grad, which + 2 * TA);
     auto it = h->adj_graphs.find(key);
     if (it != h->adj_graphs.end()) return it->second;
     if (h->adj_graphs.size() >= kMaxAdjGraphs) {  // callers that change buffers every call
@@ -2271,22 +2361,15 @@ int lbm_cde_adjoint_segment(lbm_cde_handle h, int32_t run, const void* ckpt, int
     if (g) (void)hipGraphDestroy(g);
     return x;
   };
-  hipGraphExec_t ga = graph(0, [&](hipStream_t s) {
-    for (int k = 1; k < K; ++k) fwd(k, s);
-  });
+  hipGraphExec_t ga = graph(0, [&](hipStream_t s) { fwd_rest(s); });
   hipGraphExec_t gb = graph(1, [&](hipStream_t s) {
-    void* cur = mu_tmp;
-    void* nxt = mu;
-    for (int k = K - 2; k >= 0; --k) {
-      rev(k, cur, nxt, nullptr, s);
-      std::swap(cur, nxt);
-    }
+    void* cur = rev_rest(s);
     if (cur != mu) (void)hipMemcpyAsync(mu, cur, sb, hipMemcpyDeviceToDevice, s);
   });
   if (!ga || !gb) return fail(h, LBM_CDE_EHIP, "adjoint_segment: graph capture failed");
-  fwd(0, h->stream);
+  fwd(fw[0].first, fw[0].second, ckpt, P[1], h->stream);
   HIP_TRY(h, hipGraphLaunch(ga, h->stream));
-  rev(K - 1, mu, mu_tmp, inj ? inj[K - 1] : nullptr, h->stream);
+  rev(K - 1, 1, mu, mu_tmp, inj ? inj[K - 1] : nullptr, h->stream);
   HIP_TRY(h, hipGraphLaunch(gb, h->stream));
   HIP_TRY(h, hipGetLastError());
   return LBM_CDE_OK;

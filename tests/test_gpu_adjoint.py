@@ -6,7 +6,8 @@ adjoint and against central finite differences.
   periodic and with walls, with checkpoint segments that do and do not divide
   the run length, with snapshots inside segments and at segment ends only.
   Bounds: 1e-10 (FP64) and 1e-4 (FP32) of max |grad|.
-* Segments replayed from captured graphs equal step-by-step launches bitwise.
+* Segments replayed from captured graphs equal step-by-step launches bitwise,
+  and so do segments taking several steps per launch.
 * Finite differences: on the inverse-problem workload (512^2, smooth random
   D field, 10 Gaussian initial conditions, 2000 steps, snapshots every 200,
   checkpoints every 100) the FP32 adjoint gradient agrees with central
@@ -93,6 +94,45 @@ def test_segment_graphs_equal_direct_launches(precision, monkeypatch):
         np.testing.assert_array_equal(out[0][0], out[1][0])
         np.testing.assert_array_equal(out[0][1], out[1][1])
         assert np.abs(out[0][0]).max() > 0
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("fp32", 1e-4)])
+def test_multi_step_segments_equal_one_step(precision, tol, monkeypatch):
+    """On a periodic grid that spans the tiles, the segment's recomputation
+    and reverse sweep take several steps per launch (forward chunks and
+    reverse chunks of 4 steps in FP32, 3 in FP64; the first reverse step and
+    the left-over steps one per launch): gradients bitwise those of one step
+    per launch, with and without the captured graphs, for checkpoint
+    intervals that leave remainders; the gradient against the oracle."""
+    import torch
+    from paper_1404_2363_amd.adjoint import RolloutSpec, misfit
+    nx, ny, steps, snap = 150, 72, 120, 40
+    wl, d_trial, phi0, obs = _setup(nx, ny, steps, snap)
+    dev = "cuda:0"
+    ob = torch.tensor(np.stack(obs), dtype=torch.float64, device=dev)
+    for ckpt in (20, 23, 7):
+        out = []
+        for fused, graphs in (("1", "1"), ("1", "0"), ("0", "1")):
+            monkeypatch.setenv("LBM_CDE_ADJ_FUSED", fused)
+            monkeypatch.setenv("LBM_CDE_ADJ_GRAPHS", graphs)
+            print(f"case adjoint multi-step={fused} graphs={graphs} {precision} ckpt {ckpt}", flush=True)
+            D = torch.tensor(d_trial, dtype=torch.float64, device=dev, requires_grad=True)
+            p0 = torch.tensor(phi0, dtype=torch.float64, device=dev, requires_grad=True)
+            J = misfit(D, p0, ob, RolloutSpec(wl, steps, snap, ckpt, precision, (1.0, 1.0)))
+            J.backward()
+            out.append((D.grad.cpu().numpy(), p0.grad.cpu().numpy(), float(J.detach())))
+        for o in out[1:]:
+            np.testing.assert_array_equal(o[0], out[0][0])
+            np.testing.assert_array_equal(o[1], out[0][1])
+    monkeypatch.delenv("LBM_CDE_ADJ_FUSED")
+    monkeypatch.delenv("LBM_CDE_ADJ_GRAPHS")
+    J_ref, g_ref, dphi_ref = O.misfit_gradient(O.Problem("d2q9", (nx, ny), wl.walls, wl.u(), d_trial,
+                                                         heat_rule=[1.0, 1.0]), phi0, obs, snap, return_dphi0=True)
+    g = out[0][0]
+    err = float(np.abs(g - g_ref).max() / np.abs(g_ref).max())
+    print(f"oracle gradient error {err:.2e}", flush=True)
+    assert err <= tol
+    assert np.abs(out[0][1] - dphi_ref).max() <= tol * np.abs(dphi_ref).max()
 
 
 def test_adjoint_rejects_adaptive_heat_rates():
