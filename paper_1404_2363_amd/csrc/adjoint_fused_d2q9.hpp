@@ -28,17 +28,17 @@ namespace lbm {
 // Forward recomputation: T steps of the run from a.src, v of every step into
 // vout (step s of the launch at vout + s * vstep bytes, planes [2][nx ny]),
 // the end state into a.dst when store_end.
-template <typename R, int BX, int BY, int NY, int T, int UK>
+template <typename R, int BX, int BY, int NY, int T, int UK, bool NP>
 __global__ __launch_bounds__(BX * BY) void k_fused_v_d2q9(const RunArgs a, char* vout, int64_t vstep, int store_end) {
   const uint32_t ntx = ((uint32_t)a.nx + BX - 1) / BX, tyi = blockIdx.x / ntx;
-  fused_tile<R, BX, BY, NY, T, UK, false, true>(a, blockIdx.x - tyi * ntx, tyi, vout, vstep, store_end != 0);
+  fused_tile<R, BX, BY, NY, T, UK, false, true, NP>(a, blockIdx.x - tyi * ntx, tyi, vout, vstep, store_end != 0);
 }
 
 // Reverse steps k_hi, k_hi - 1, ..., k_hi - T + 1 of a segment: mu_in =
 // mu_{k_hi + 1}, v of step k_hi - s at v_hi - s * vstep bytes, mu_out =
 // mu_{k_hi - T + 1}; grad (FP64 [3][N]) and part (FP32 [3][N]) as described
 // above (fold: the launch ends with the segment's first step, FP32 only).
-template <typename R, int BX, int BY, int NY, int T>
+template <typename R, int BX, int BY, int NY, int T, bool NP>
 __global__ __launch_bounds__(BX * BY) void k_fused_adj_d2q9(const RunArgs a, const char* __restrict__ v_hi,
                                                            int64_t vstep, const R* __restrict__ mu_in,
                                                            R* __restrict__ mu_out, double* __restrict__ grad,
@@ -80,7 +80,7 @@ __global__ __launch_bounds__(BX * BY) void k_fused_adj_d2q9(const RunArgs a, con
     const R vx = gld<R>(vb, o), vy = gld<R>(vb + (size_t)N * E, o);
     R ux, uy;
     velocity2<R>(a, x, y, ux, uy);
-    if (a.node_par) adjoint_node<R>(l, vx, vy, ux, uy, node_rel2<R>(a, (int64_t)y * nx + x), m, gc);
+    if constexpr (NP) adjoint_node<R>(l, vx, vy, ux, uy, node_rel2<R>(a, (int64_t)y * nx + x), m, gc);
     else adjoint_node<R>(l, vx, vy, ux, uy, rc, m, gc);
   };
   auto add = [&](int lx, int ly, const R(&gc)[3]) {

@@ -58,7 +58,7 @@ LBM_FORCEINLINE void wall_source(const RunArgs& a, int32_t y, int32_t ny, int& p
 // of the tile's own nodes (adjoint_v; two planes of nx ny values at
 // vout + s * vstep bytes for the launch's step s), and the final state goes to
 // memory only with store_end.
-template <typename R, int BX, int BY, int NY, int T, int UK, bool WY, bool VOUT = false>
+template <typename R, int BX, int BY, int NY, int T, int UK, bool WY, bool VOUT = false, bool NP = false>
 LBM_FORCEINLINE void fused_tile(const RunArgs& a, uint32_t txi, uint32_t tyi, char* vout = nullptr,
                                 int64_t vstep = 0, bool store_end = true) {
   static_assert(T >= 2, "one step per launch is k_step_d2q9");
@@ -139,7 +139,7 @@ LBM_FORCEINLINE void fused_tile(const RunArgs& a, uint32_t txi, uint32_t tyi, ch
     } else {
       velocity2<R>(a, x, y, ux, uy);
     }
-    if (a.node_par) {
+    if constexpr (NP) {  // per-node relaxation parameters (a D field)
       const Rel2<R> rn = node_rel2<R>(a, (int64_t)y * nx + x);
       store_v(f, ux, uy, rn, x, y, lx, ly, st);
       collide_d2q9<R, 1>(f, ux, uy, phi_ref, rn);
@@ -271,12 +271,14 @@ LBM_FORCEINLINE void fused_tile(const RunArgs& a, uint32_t txi, uint32_t tyi, ch
   }
 }
 
-// One run: one block per tile, in the chosen block order.
-template <typename R, int BX, int BY, int NY, int T, int UK, bool WY>
+// One run: one block per tile, in the chosen block order.  NP: the run has
+// per-node relaxation parameters (a D field; the branch is resolved at compile
+// time, so runs without them pay nothing for it).
+template <typename R, int BX, int BY, int NY, int T, int UK, bool WY, bool NP>
 __global__ __launch_bounds__(BX * BY) void k_fused_d2q9(const RunArgs a) {
   const uint32_t b = tile_of_block32(blockIdx.x, gridDim.x, a.tiles_x, a.xcd_remap);
   const uint32_t tyi = fdiv(b, a.tiles_x);
-  fused_tile<R, BX, BY, NY, T, UK, WY>(a, b - tyi * a.tiles_x.d, tyi);
+  fused_tile<R, BX, BY, NY, T, UK, WY, false, NP>(a, b - tyi * a.tiles_x.d, tyi);
 }
 
 // The arguments of one step of a batched run (its compact record), for the

@@ -734,15 +734,18 @@ template <typename R, int BX, int BY, int NY, int T>
 void launch_fused(const RunArgs a, hipStream_t s) {
   const int64_t ntx = (a.nx + BX - 1) / BX, nty = (a.ny + BY * NY - 1) / (BY * NY);
   const dim3 g((unsigned)(ntx * nty)), b(BX, BY);
-  if (a.bc[1] != LBM_CDE_PERIODIC) {  // walls in y (velocity constant or separable)
-    if (a.u_kind == U_CONST) hipLaunchKernelGGL((k_fused_d2q9<R, BX, BY, NY, T, 0, true>), g, b, 0, s, a);
-    else hipLaunchKernelGGL((k_fused_d2q9<R, BX, BY, NY, T, 1, true>), g, b, 0, s, a);
+  if (a.node_par) {  // a D field (periodic, velocity constant or separable: fused_ok)
+    if (a.u_kind == U_CONST) hipLaunchKernelGGL((k_fused_d2q9<R, BX, BY, NY, T, 0, false, true>), g, b, 0, s, a);
+    else hipLaunchKernelGGL((k_fused_d2q9<R, BX, BY, NY, T, 1, false, true>), g, b, 0, s, a);
+  } else if (a.bc[1] != LBM_CDE_PERIODIC) {  // walls in y (velocity constant or separable)
+    if (a.u_kind == U_CONST) hipLaunchKernelGGL((k_fused_d2q9<R, BX, BY, NY, T, 0, true, false>), g, b, 0, s, a);
+    else hipLaunchKernelGGL((k_fused_d2q9<R, BX, BY, NY, T, 1, true, false>), g, b, 0, s, a);
   } else if (a.u_kind == U_CONST) {
-    hipLaunchKernelGGL((k_fused_d2q9<R, BX, BY, NY, T, 0, false>), g, b, 0, s, a);
+    hipLaunchKernelGGL((k_fused_d2q9<R, BX, BY, NY, T, 0, false, false>), g, b, 0, s, a);
   } else if (a.u_kind == U_SEPARABLE) {
-    hipLaunchKernelGGL((k_fused_d2q9<R, BX, BY, NY, T, 1, false>), g, b, 0, s, a);
+    hipLaunchKernelGGL((k_fused_d2q9<R, BX, BY, NY, T, 1, false, false>), g, b, 0, s, a);
   } else {
-    hipLaunchKernelGGL((k_fused_d2q9<R, BX, BY, NY, T, 2, false>), g, b, 0, s, a);
+    hipLaunchKernelGGL((k_fused_d2q9<R, BX, BY, NY, T, 2, false, false>), g, b, 0, s, a);
   }
 }
 
@@ -767,13 +770,14 @@ const FusedEntry kFused[] = {FUSED_ENTRY(128, 4, 2, 2), FUSED_ENTRY(128, 4, 2, 3
 // A run can take T steps per launch when it is D2Q9 in FP64 or FP32 with an
 // equilibrium linear in phi and phi u (MRT-A or MRT-B3), periodic in x, each
 // periodic axis spans the tile plus T - 1 nodes on both sides (halo nodes are
-// periodic images taken with one wrap), a run with walls in y has a constant
-// or separable velocity, and byte offsets within a population plane fit 32
-// bits.
+// periodic images taken with one wrap), a run with walls in y or a D field
+// (per-node rates, periodic only) has a constant or separable velocity, and
+// byte offsets within a population plane fit 32 bits.
 bool fused_ok(const Run& r, const Variant& v) {
   const bool wy = r.d.bc[1] != LBM_CDE_PERIODIC;
   return r.d.lattice == LBM_CDE_D2Q9 && !r.half && !r.split && r.d.bc[0] == LBM_CDE_PERIODIC && r.d.nz == 1 &&
          (r.d.model == LBM_CDE_MRT_A || r.d.model == LBM_CDE_MRT_B3) && !(wy && r.d.u_kind == LBM_CDE_U_FIELD) &&
+         !(r.node_par && (wy || r.d.u_kind == LBM_CDE_U_FIELD)) &&
          r.d.nx >= (int64_t)v.bx + 2 * (v.fuse - 1) && (wy || r.d.ny >= (int64_t)v.by * v.ny + 2 * (v.fuse - 1)) &&
          (double)r.nodes * (double)r.elem < 4294967296.0 && r.d.nx < (1ll << 30) && r.d.ny < (1ll << 30) &&
          v.grid == 0;
@@ -1744,20 +1748,30 @@ template <typename R, int BX, int BY, int NY, int T>
 void launch_fused_v(const RunArgs& a, char* vout, int64_t vstep, bool store, hipStream_t s) {
   const unsigned blocks = (unsigned)(((a.nx + BX - 1) / BX) * ((a.ny + BY * NY - 1) / (BY * NY)));
   const dim3 g(blocks), b(BX, BY);
-  if (a.u_kind == U_CONST)
-    hipLaunchKernelGGL((k_fused_v_d2q9<R, BX, BY, NY, T, 0>), g, b, 0, s, a, vout, vstep, (int)store);
-  else if (a.u_kind == U_SEPARABLE)
-    hipLaunchKernelGGL((k_fused_v_d2q9<R, BX, BY, NY, T, 1>), g, b, 0, s, a, vout, vstep, (int)store);
-  else
-    hipLaunchKernelGGL((k_fused_v_d2q9<R, BX, BY, NY, T, 2>), g, b, 0, s, a, vout, vstep, (int)store);
+  if (a.node_par) {  // velocity constant or separable (fused_ok)
+    if (a.u_kind == U_CONST)
+      hipLaunchKernelGGL((k_fused_v_d2q9<R, BX, BY, NY, T, 0, true>), g, b, 0, s, a, vout, vstep, (int)store);
+    else
+      hipLaunchKernelGGL((k_fused_v_d2q9<R, BX, BY, NY, T, 1, true>), g, b, 0, s, a, vout, vstep, (int)store);
+  } else if (a.u_kind == U_CONST) {
+    hipLaunchKernelGGL((k_fused_v_d2q9<R, BX, BY, NY, T, 0, false>), g, b, 0, s, a, vout, vstep, (int)store);
+  } else if (a.u_kind == U_SEPARABLE) {
+    hipLaunchKernelGGL((k_fused_v_d2q9<R, BX, BY, NY, T, 1, false>), g, b, 0, s, a, vout, vstep, (int)store);
+  } else {
+    hipLaunchKernelGGL((k_fused_v_d2q9<R, BX, BY, NY, T, 2, false>), g, b, 0, s, a, vout, vstep, (int)store);
+  }
 }
 
 template <typename R, int BX, int BY, int NY, int T>
 void launch_fused_adj(const RunArgs& a, const char* v_hi, int64_t vstep, const void* mu_in, void* mu_out,
                       double* grad, float* part, double inv_kappa, bool fold, hipStream_t s) {
   const unsigned blocks = (unsigned)(((a.nx + BX - 1) / BX) * ((a.ny + BY * NY - 1) / (BY * NY)));
-  hipLaunchKernelGGL((k_fused_adj_d2q9<R, BX, BY, NY, T>), dim3(blocks), dim3(BX, BY), 0, s, a, v_hi, vstep,
-                     (const R*)mu_in, (R*)mu_out, grad, part, inv_kappa, (int)fold);
+  if (a.node_par)
+    hipLaunchKernelGGL((k_fused_adj_d2q9<R, BX, BY, NY, T, true>), dim3(blocks), dim3(BX, BY), 0, s, a, v_hi, vstep,
+                       (const R*)mu_in, (R*)mu_out, grad, part, inv_kappa, (int)fold);
+  else
+    hipLaunchKernelGGL((k_fused_adj_d2q9<R, BX, BY, NY, T, false>), dim3(blocks), dim3(BX, BY), 0, s, a, v_hi,
+                       vstep, (const R*)mu_in, (R*)mu_out, grad, part, inv_kappa, (int)fold);
 }
 
 // The shape of the multi-step adjoint launches: FP32 64 x 16 tiles with 4
