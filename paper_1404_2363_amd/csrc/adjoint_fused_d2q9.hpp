@@ -65,7 +65,7 @@ __global__ __launch_bounds__(BX * BY) void k_fused_adj_d2q9(const RunArgs a, con
     const int ly = j / TX, lx = j - ly * TX;
     const int32_t x = x0 + RG + lx, y = y0 + RG + ly;
     if (x >= nx || y >= ny) continue;
-    const uint32_t n = (uint32_t)y * nx + x;
+    const uint32_t n = __umul24((uint32_t)y, (uint32_t)nx) + x;
 #pragma unroll
     for (int c = 0; c < 3; ++c) acc[c * NI + j] = F64 ? (Acc)grad[c * N + n] : (Acc)part[c * N + n];
   }
@@ -76,7 +76,7 @@ __global__ __launch_bounds__(BX * BY) void k_fused_adj_d2q9(const RunArgs a, con
   // reverse step s of the launch at grid node (x, y), local (lx, ly)
   auto step = [&](R(&l)[9], int32_t x, int32_t y, int s, R(&m)[9], R(&gc)[3]) {
     const char* vb = v_hi - s * vstep;
-    const uint32_t o = ((uint32_t)y * nx + x) * E;
+    const uint32_t o = (__umul24((uint32_t)y, (uint32_t)nx) + x) * E;
     const R vx = gld<R>(vb, o), vy = gld<R>(vb + (size_t)N * E, o);
     R ux, uy;
     velocity2<R>(a, x, y, ux, uy);
@@ -101,6 +101,7 @@ __global__ __launch_bounds__(BX * BY) void k_fused_adj_d2q9(const RunArgs a, con
   // step 0 of the launch: mu from memory over the widened tile
   {
     const char* mb = (const char*)mu_in;
+    const uint32_t rlast = (uint32_t)(ny - 1) * (uint32_t)nx;  // offset of the last row
     R f[K0][9];
 #pragma unroll
     for (int k = 0; k < K0; ++k) {
@@ -109,8 +110,8 @@ __global__ __launch_bounds__(BX * BY) void k_fused_adj_d2q9(const RunArgs a, con
       const int ly = j / W0, lx = j - ly * W0;
       const int32_t x = wrap_once(x0 + lx, nx), y = wrap_once(y0 + ly, ny);
       const uint32_t xm = x == 0 ? nx - 1 : x - 1, xp = x + 1 == nx ? 0 : x + 1;
-      const uint32_t r0 = (uint32_t)y * nx, rm = (uint32_t)(y == 0 ? ny - 1 : y - 1) * nx,
-                     rp = (uint32_t)(y + 1 == ny ? 0 : y + 1) * nx;
+      const uint32_t r0 = __umul24((uint32_t)y, (uint32_t)nx), rm = y == 0 ? rlast : r0 - nx,
+                     rp = y + 1 == ny ? 0u : r0 + nx;
       // population (ex, ey) from its push destination (x + ex, y + ey)
       f[k][0] = gld<R>(mb, (r0 + x) * E);
       f[k][1] = gld<R>(mb + 1 * pb, (r0 + xp) * E);
@@ -175,7 +176,7 @@ __global__ __launch_bounds__(BX * BY) void k_fused_adj_d2q9(const RunArgs a, con
     R l[9], m[9], gc[3];
     gather(l, lx, ly);
     step(l, x, y, T - 1, m, gc);
-    const uint32_t n = (uint32_t)y * nx + x;
+    const uint32_t n = __umul24((uint32_t)y, (uint32_t)nx) + x;
 #pragma unroll
     for (int i = 0; i < 9; ++i) gst<R, true>(ob + i * pb, n * E, m[i]);
     const int ii = (ly - RG) * TX + (lx - RG);

@@ -34,6 +34,25 @@ inline FastDiv make_fastdiv(uint32_t d) {
 // Velocity description in the precision R of the arithmetic.
 enum UKind : int32_t { U_CONST = 0, U_SEPARABLE = 1, U_FIELD = 2 };
 
+// Compiled for the host and the device alike.
+#define LBM_HD __host__ __device__ __forceinline__
+
+// Relaxation coefficients of the D2Q9 collision (Eq. 31) in the precision R
+// of the arithmetic; make_rel2_vals computes them.
+template <typename R>
+struct Rel2 {
+  R s1, s2, s7, s8, s4, s6;
+  R axx, axy, ayy;
+  R c34, c36, c54, c56;  // coupling coefficients of Eq. (31); zero for the standard S (Eq. 24)
+  R nl;                  // 1 for the equilibria with u^2 terms (Eq. 38, 39), else 0
+  R c2;                  // m2_eq(phi, 0) / phi: 1 for Eq. (38), else 2
+  // the rows of S divided by the squared norms of the rows of M (Eq. 12):
+  // the collision applies M^-1 = M^T diag(1/|M_k|^2) to S n
+  R k1, k2, k4, k6, k7, k8;
+  R g33, g34, g35, g36, g53, g54, g55, g56;
+  bool lin;  // equilibrium linear in phi and phi u (Eq. 37): no u^2 terms, m2_eq = 2 phi
+};
+
 // Everything one kernel launch needs about one run.  Passed by value as a
 // kernel argument (and stored in device memory for batched launches).
 struct RunArgs {
@@ -60,6 +79,11 @@ struct RunArgs {
   double s[15];             // s[k] by moment index (flux-row entries unused)
   double A[3][3];           // flux block s_ab
   double heat[3];           // s4, s6, s8
+  // the D2Q9 collision's coefficients for the constant rates above, rounded
+  // on the host by the kernels' own formulas (make_rel2_vals), so that a
+  // block reads them instead of deriving them again
+  Rel2<float> relf;
+  Rel2<double> reld;
   // FP16 split storage (MRT-A, constant D), rounded once on the host: the
   // rows of (I - S) times the storage scale over |M_k|^2 (see
   // collide_neq_d2q9) and 1/scale

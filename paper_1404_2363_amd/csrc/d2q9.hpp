@@ -34,22 +34,8 @@
 namespace lbm {
 
 template <typename R>
-struct Rel2 {
-  R s1, s2, s7, s8, s4, s6;
-  R axx, axy, ayy;
-  R c34, c36, c54, c56;  // coupling coefficients of Eq. (31); zero for the standard S (Eq. 24)
-  R nl;                  // 1 for the equilibria with u^2 terms (Eq. 38, 39), else 0
-  R c2;                  // m2_eq(phi, 0) / phi: 1 for Eq. (38), else 2
-  // the rows of S divided by the squared norms of the rows of M (Eq. 12):
-  // the collision applies M^-1 = M^T diag(1/|M_k|^2) to S n
-  R k1, k2, k4, k6, k7, k8;
-  R g33, g34, g35, g36, g53, g54, g55, g56;
-  bool lin;  // equilibrium linear in phi and phi u (Eq. 37): no u^2 terms, m2_eq = 2 phi
-};
-
-template <typename R>
-LBM_FORCEINLINE Rel2<R> make_rel2_vals(R axx, R axy, R ayy, R s4, R s6, double s1, double s2, double s7, double s8,
-                                       int model) {
+LBM_HD Rel2<R> make_rel2_vals(R axx, R axy, R ayy, R s4, R s6, double s1, double s2, double s7, double s8,
+                              int model) {
   Rel2<R> r;
   r.s1 = (R)s1;
   r.s2 = (R)s2;
@@ -91,9 +77,19 @@ LBM_FORCEINLINE Rel2<R> make_rel2(R axx, R axy, R ayy, R s4, R s6, const RunArgs
   return make_rel2_vals<R>(axx, axy, ayy, s4, s6, a.s[1], a.s[2], a.s[7], a.s[8], a.model);
 }
 
+// The coefficients of a run's constant rates (host: filling RunArgs::relf
+// and reld; device: runs described by a compact batch record).
+template <typename R>
+LBM_HD Rel2<R> rel2_of_rates(const RunArgs& a) {
+  return make_rel2_vals<R>((R)a.A[0][0], (R)a.A[0][1], (R)a.A[1][1], (R)a.heat[0], (R)a.heat[1], a.s[1], a.s[2],
+                           a.s[7], a.s[8], a.model);
+}
+
+// The coefficients of the run's constant rates, as the host rounded them.
 template <typename R>
 LBM_FORCEINLINE Rel2<R> const_rel2(const RunArgs& a) {
-  return make_rel2<R>((R)a.A[0][0], (R)a.A[0][1], (R)a.A[1][1], (R)a.heat[0], (R)a.heat[1], a);
+  if constexpr (sizeof(R) == sizeof(float)) return a.relf;
+  else return a.reld;
 }
 
 // Per-node relaxation parameters (D field): axx, axy, ayy, s4, s6 planes; the

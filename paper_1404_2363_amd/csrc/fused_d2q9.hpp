@@ -29,7 +29,8 @@
 // factors: the block stages the widened tile's column and row factors in LDS
 // once and multiplies them in the one-step kernel's order), 2 a per-node
 // field (read from memory at every step).  Byte offsets within a population
-// plane are 32-bit (nodes * sizeof(R) < 2^32).
+// plane are 32-bit (nodes * sizeof(R) < 2^32), node coordinates below 2^24
+// (row offsets are 24-bit products).
 #pragma once
 
 #include "adjoint_d2q9.hpp"
@@ -41,7 +42,11 @@ namespace lbm {
 __device__ constexpr int kEx9[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
 __device__ constexpr int kEy9[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
 
-LBM_FORCEINLINE int32_t wrap_once(int32_t v, int32_t n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
+// v mod n for v in [-n, 2n): of v, v + n and v - n the one in [0, n) is the
+// smallest as an unsigned number (the others are n or more, or negative).
+LBM_FORCEINLINE int32_t wrap_once(int32_t v, int32_t n) {
+  return (int32_t)min(min((uint32_t)v, (uint32_t)(v + n)), (uint32_t)(v - n));
+}
 
 // Source of population I (velocity (EX, EY)) at row y: (population, row,
 // x shift) under the run's y boundary (walls), as in the one-step kernel.
@@ -70,6 +75,10 @@ LBM_FORCEINLINE void fused_tile(const RunArgs& a, uint32_t txi, uint32_t tyi, ch
   __shared__ R ucol[UK == 1 ? 2 * W0 : 1], urow[UK == 1 ? 2 * H0 : 1];
 
   const int tid = threadIdx.y * BX + threadIdx.x;
+  // the launch's block is BX x BY: the slots below that every thread fills
+  // then need no guard, and a slot's collision waits only for its own loads
+  // (a guarded slot before it would make the wait cover every load issued)
+  if (tid >= NTH) __builtin_unreachable();
   const int32_t nx = (int32_t)a.nx, ny = (int32_t)a.ny;
   const int32_t x0 = (int32_t)txi * TX - RG, y0 = (int32_t)tyi * TY - RG;
   const size_t pb = (size_t)a.plane * sizeof(R);
@@ -78,8 +87,10 @@ LBM_FORCEINLINE void fused_tile(const RunArgs& a, uint32_t txi, uint32_t tyi, ch
   // separable velocity: component c at (x, y) is ((t_c[0] t_c[1+x]) t_c[1+nx+y]) t_c[1+nx+ny]
   const R* tab = (const R*)a.u_tab;
   const int32_t tstride = 1 + nx + ny + (int32_t)a.nz;
-  R tz0 = (R)0, tz1 = (R)0;
-  if constexpr (UK == 1) {
+  R ta0 = (R)0, ta1 = (R)0, tz0 = (R)0, tz1 = (R)0;
+  if constexpr (UK == 1) {  // read here, before any store, as scalars
+    ta0 = tab[0];
+    ta1 = tab[tstride];
     tz0 = tab[1 + nx + ny];
     tz1 = tab[tstride + 1 + nx + ny];
   }
@@ -120,7 +131,7 @@ LBM_FORCEINLINE void fused_tile(const RunArgs& a, uint32_t txi, uint32_t tyi, ch
       if (lx < RG || lx >= RG + TX || ly < RG || ly >= RG + TY || x0 + lx >= nx || y0 + ly >= ny) return;
       R vx, vy;
       adjoint_v<R>(f, ux, uy, phi_ref, rel, vx, vy);
-      const uint32_t o = ((uint32_t)y * nx + x) * (uint32_t)sizeof(R);
+      const uint32_t o = (__umul24((uint32_t)y, (uint32_t)nx) + x) * (uint32_t)sizeof(R);
       char* vb = vout + st * vstep;
       gst<R, true>(vb, o, vx);
       gst<R, true>(vb + (size_t)nx * ny * sizeof(R), o, vy);
@@ -128,7 +139,7 @@ LBM_FORCEINLINE void fused_tile(const RunArgs& a, uint32_t txi, uint32_t tyi, ch
   };
   // collision of one node at periodic image (x, y); (lx, ly) in the widened
   // tile; st = the launch's step
-  auto collide = [&](R(&f)[9], int32_t x, int32_t y, int lx, int ly, int st = 0) {
+  auto collide = [&](R(&f)[9], int32_t x, int32_t y, int lx, int ly, int st) {
     R ux, uy;
     if constexpr (UK == 0) {
       ux = (R)a.u_const[0];
@@ -151,29 +162,55 @@ LBM_FORCEINLINE void fused_tile(const RunArgs& a, uint32_t txi, uint32_t tyi, ch
 
   // step 1: HBM -> LDS over the whole widened tile
   {
-    const char* src = (const char*)a.src;
+    // the nine source planes as scalar base addresses (as the destination
+    // planes of the last step, below)
+    const char* spl[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      spl[i] = (const char*)a.src + i * pb;
+      asm volatile("" : "+s"(spl[i]));
+    }
+    const uint32_t rlast = (uint32_t)(ny - 1) * (uint32_t)nx;  // offset of the last row
     R f[K0][9];
     constexpr uint32_t E = sizeof(R);
-#pragma unroll
-    for (int k = 0; k < K0; ++k) {
+    // separable velocity: the widened tile's column and row factors are read
+    // before the populations and staged in LDS after them, so that the
+    // barrier which publishes them waits for these few loads only
+    R sc0 = (R)0, sc1 = (R)0, sr0 = (R)0, sr1 = (R)0;
+    if constexpr (UK == 1) {
+      if (tid < W0) {
+        const int32_t x = wrap_once(x0 + tid, nx);
+        sc0 = tab[1 + x];
+        sc1 = tab[tstride + 1 + x];
+      }
+      if (tid < H0) {
+        // rows beyond a wall are never collided; clamp to stay inside the table
+        const int32_t yy = grid_row(tid), y = WY ? (yy < 0 ? 0 : (yy >= ny ? ny - 1 : yy)) : yy;
+        sr0 = tab[1 + nx + y];
+        sr1 = tab[tstride + 1 + nx + y];
+      }
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    // the loads of slot k (node tid + k NTH of the widened tile)
+    auto load_slot = [&](const int k) {
       const int j = tid + k * NTH;
-      if (K0 * NTH > C0 && j >= C0) continue;
+      if (K0 * NTH > C0 && j >= C0) return;
       const int ly = j / W0, lx = j - ly * W0;
       const int32_t x = wrap_once(x0 + lx, nx), y = grid_row(ly);
-      if (outside(y)) continue;
+      if (outside(y)) return;
       const uint32_t xm = x == 0 ? nx - 1 : x - 1, xp = x + 1 == nx ? 0 : x + 1;
       if constexpr (!WY) {
-        const uint32_t r0 = (uint32_t)y * nx, rm = (uint32_t)(y == 0 ? ny - 1 : y - 1) * nx,
-                       rp = (uint32_t)(y + 1 == ny ? 0 : y + 1) * nx;
-        f[k][0] = gld<R>(src, (r0 + x) * E);
-        f[k][1] = gld<R>(src + 1 * pb, (r0 + xm) * E);
-        f[k][2] = gld<R>(src + 2 * pb, (rm + x) * E);
-        f[k][3] = gld<R>(src + 3 * pb, (r0 + xp) * E);
-        f[k][4] = gld<R>(src + 4 * pb, (rp + x) * E);
-        f[k][5] = gld<R>(src + 5 * pb, (rm + xm) * E);
-        f[k][6] = gld<R>(src + 6 * pb, (rm + xp) * E);
-        f[k][7] = gld<R>(src + 7 * pb, (rp + xp) * E);
-        f[k][8] = gld<R>(src + 8 * pb, (rp + xm) * E);
+        const uint32_t r0 = __umul24((uint32_t)y, (uint32_t)nx), rm = y == 0 ? rlast : r0 - nx,
+                       rp = y + 1 == ny ? 0u : r0 + nx;
+        f[k][0] = gld<R>(spl[0], (r0 + x) * E);
+        f[k][1] = gld<R>(spl[1], (r0 + xm) * E);
+        f[k][2] = gld<R>(spl[2], (rm + x) * E);
+        f[k][3] = gld<R>(spl[3], (r0 + xp) * E);
+        f[k][4] = gld<R>(spl[4], (rp + x) * E);
+        f[k][5] = gld<R>(spl[5], (rm + xm) * E);
+        f[k][6] = gld<R>(spl[6], (rm + xp) * E);
+        f[k][7] = gld<R>(spl[7], (rp + xp) * E);
+        f[k][8] = gld<R>(spl[8], (rp + xm) * E);
       } else {
 #define LBM_FUSED_WALL_LOAD(I)                                                                  \
   {                                                                                             \
@@ -181,7 +218,8 @@ LBM_FORCEINLINE void fused_tile(const RunArgs& a, uint32_t txi, uint32_t tyi, ch
     int32_t sy;                                                                                 \
     wall_source<I>(a, y, ny, pop, sy, dx);                                                      \
     const uint32_t sx = dx < 0 ? xm : (dx > 0 ? xp : (uint32_t)x);                              \
-    f[k][I] = gld<R>(src + (size_t)pop * pb, ((uint32_t)sy * nx + sx) * E);                       \
+    const uint32_t so = (__umul24((uint32_t)sy, (uint32_t)nx) + sx) * E;                        \
+    f[k][I] = gld<R>((const char*)a.src + (size_t)pop * pb, so);                                \
   }
         LBM_FUSED_WALL_LOAD(0)
         LBM_FUSED_WALL_LOAD(1)
@@ -194,23 +232,30 @@ LBM_FORCEINLINE void fused_tile(const RunArgs& a, uint32_t txi, uint32_t tyi, ch
         LBM_FUSED_WALL_LOAD(8)
 #undef LBM_FUSED_WALL_LOAD
       }
+    };
+    // Issue order: the slot that only some threads fill first, then the full
+    // slots in order, each kept together (sched_barrier), so that the wait
+    // before slot k's collision covers only the loads issued up to slot k:
+    // slot 0 collides while the later slots' loads are still in flight.
+    constexpr int KF = C0 / NTH;  // slots that every thread fills
+    if constexpr (K0 > KF) load_slot(KF);
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int k = 0; k < KF; ++k) {
+      load_slot(k);
+      __builtin_amdgcn_sched_barrier(0);
     }
     if constexpr (UK == 1) {
       if (tid < W0) {
-        const int32_t x = wrap_once(x0 + tid, nx);
-        ucol[tid] = tab[0] * tab[1 + x];
-        ucol[W0 + tid] = tab[tstride] * tab[tstride + 1 + x];
+        ucol[tid] = ta0 * sc0;
+        ucol[W0 + tid] = ta1 * sc1;
       }
       if (tid < H0) {
-        // rows beyond a wall are never collided; clamp to stay inside the table
-        const int32_t yy = grid_row(tid), y = WY ? (yy < 0 ? 0 : (yy >= ny ? ny - 1 : yy)) : yy;
-        urow[tid] = tab[1 + nx + y];
-        urow[H0 + tid] = tab[tstride + 1 + nx + y];
+        urow[tid] = sr0;
+        urow[H0 + tid] = sr1;
       }
+      __syncthreads();
     }
-    // the staged factors serve step 1 too (the barrier also waits for the
-    // population loads, which the collisions below need anyway)
-    if constexpr (UK == 1) __syncthreads();
 #pragma unroll
     for (int k = 0; k < K0; ++k) {
       const int j = tid + k * NTH;
@@ -221,6 +266,7 @@ LBM_FORCEINLINE void fused_tile(const RunArgs& a, uint32_t txi, uint32_t tyi, ch
       collide(f[k], wrap_once(x0 + lx, nx), y, lx, ly, 0);
 #pragma unroll
       for (int i = 0; i < 9; ++i) lds[i * C0 + j] = f[k][i];
+      __builtin_amdgcn_sched_barrier(0);
     }
   }
   __syncthreads();
@@ -255,7 +301,15 @@ LBM_FORCEINLINE void fused_tile(const RunArgs& a, uint32_t txi, uint32_t tyi, ch
   }
 
   // step T: LDS -> HBM for the tile's own nodes
-  char* dst = (char*)a.dst;
+  // the nine destination planes as scalar base addresses (the empty asm keeps
+  // each in scalar registers and out of the per-node address arithmetic, so
+  // a store takes the base-plus-32-bit-offset form with no vector add)
+  char* dpl[9];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    dpl[i] = (char*)a.dst + i * pb;
+    asm volatile("" : "+s"(dpl[i]));
+  }
 #pragma unroll
   for (int k = 0; k < NY; ++k) {
     const int lx = threadIdx.x + RG, ly = threadIdx.y + k * BY + RG;
@@ -265,9 +319,9 @@ LBM_FORCEINLINE void fused_tile(const RunArgs& a, uint32_t txi, uint32_t tyi, ch
     gather(g, lx, ly, y);
     collide(g, x, y, lx, ly, T - 1);
     if (VOUT && !store_end) continue;
-    const uint32_t off = ((uint32_t)y * nx + x) * (uint32_t)sizeof(R);
+    const uint32_t off = (__umul24((uint32_t)y, (uint32_t)nx) + x) * (uint32_t)sizeof(R);
 #pragma unroll
-    for (int i = 0; i < 9; ++i) gst<R, true>(dst + i * pb, off, g[i]);
+    for (int i = 0; i < 9; ++i) gst<R, true>(dpl[i], off, g[i]);
   }
 }
 
@@ -311,6 +365,8 @@ LBM_FORCEINLINE RunArgs batch_run_args(const BatchRun& br, int par) {
   a.A[1][1] = br.ayy;
   a.heat[0] = br.s4;
   a.heat[1] = br.s6;
+  if constexpr (sizeof(R) == sizeof(float)) a.relf = rel2_of_rates<float>(a);
+  else a.reld = rel2_of_rates<double>(a);
   return a;
 }
 

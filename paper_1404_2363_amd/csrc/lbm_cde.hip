@@ -560,6 +560,8 @@ RunArgs make_args(const lbm_cde* h, const Run& r, int parity, const Variant* lau
   for (int i = 0; i < 3; ++i)
     for (int j = 0; j < 3; ++j) a.A[i][j] = r.A[i][j];
   for (int i = 0; i < 3; ++i) a.heat[i] = r.heat[i];
+  a.relf = rel2_of_rates<float>(a);
+  a.reld = rel2_of_rates<double>(a);
   if (r.split) {
     // rows of (I - S) of MRT-A (Eq. 31) times scale / |M_k|^2, in FP64, rounded once
     const double sc = a.fp16_scale, k36 = sc / 36.0, k12 = sc / 12.0, k6 = sc / 6.0, k4 = sc / 4.0;
@@ -771,15 +773,16 @@ const FusedEntry kFused[] = {FUSED_ENTRY(128, 4, 2, 2), FUSED_ENTRY(128, 4, 2, 3
 // equilibrium linear in phi and phi u (MRT-A or MRT-B3), periodic in x, each
 // periodic axis spans the tile plus T - 1 nodes on both sides (halo nodes are
 // periodic images taken with one wrap), a run with walls in y or a D field
-// (per-node rates, periodic only) has a constant or separable velocity, and
-// byte offsets within a population plane fit 32 bits.
+// (per-node rates, periodic only) has a constant or separable velocity,
+// byte offsets within a population plane fit 32 bits and node coordinates 24
+// bits (row offsets are 24-bit products).
 bool fused_ok(const Run& r, const Variant& v) {
   const bool wy = r.d.bc[1] != LBM_CDE_PERIODIC;
   return r.d.lattice == LBM_CDE_D2Q9 && !r.half && !r.split && r.d.bc[0] == LBM_CDE_PERIODIC && r.d.nz == 1 &&
          (r.d.model == LBM_CDE_MRT_A || r.d.model == LBM_CDE_MRT_B3) && !(wy && r.d.u_kind == LBM_CDE_U_FIELD) &&
          !(r.node_par && (wy || r.d.u_kind == LBM_CDE_U_FIELD)) &&
          r.d.nx >= (int64_t)v.bx + 2 * (v.fuse - 1) && (wy || r.d.ny >= (int64_t)v.by * v.ny + 2 * (v.fuse - 1)) &&
-         (double)r.nodes * (double)r.elem < 4294967296.0 && r.d.nx < (1ll << 30) && r.d.ny < (1ll << 30) &&
+         (double)r.nodes * (double)r.elem < 4294967296.0 && r.d.nx < (1ll << 24) && r.d.ny < (1ll << 24) &&
          v.grid == 0;
 }
 
