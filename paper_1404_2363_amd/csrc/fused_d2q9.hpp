@@ -101,7 +101,9 @@ LBM_FORCEINLINE void fused_tile(const RunArgs& a, uint32_t txi, uint32_t tyi, ch
   auto outside = [&](int32_t y) { return WY && (y < 0 || y >= ny); };
   // LDS gather of the nine populations of local node (lx, ly), grid row y
   auto gather = [&](R(&f)[9], int lx, int ly, int32_t y) {
-    if constexpr (!WY) {
+    // rows 1 .. ny - 2 pull from rows inside the walls: there the wall rule
+    // is the plain pull, and only the two rows next to a wall need it
+    if (!WY || (y >= 1 && y < ny - 1)) {
 #pragma unroll
       for (int i = 0; i < 9; ++i) f[i] = lds[i * C0 + (ly - kEy9[i]) * W0 + (lx - kEx9[i])];
     } else {
@@ -199,7 +201,7 @@ LBM_FORCEINLINE void fused_tile(const RunArgs& a, uint32_t txi, uint32_t tyi, ch
       const int32_t x = wrap_once(x0 + lx, nx), y = grid_row(ly);
       if (outside(y)) return;
       const uint32_t xm = x == 0 ? nx - 1 : x - 1, xp = x + 1 == nx ? 0 : x + 1;
-      if constexpr (!WY) {
+      if (!WY || (y >= 1 && y < ny - 1)) {  // the plain pull (as in gather)
         const uint32_t r0 = __umul24((uint32_t)y, (uint32_t)nx), rm = y == 0 ? rlast : r0 - nx,
                        rp = y + 1 == ny ? 0u : r0 + nx;
         f[k][0] = gld<R>(spl[0], (r0 + x) * E);
