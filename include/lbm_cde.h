@@ -270,13 +270,15 @@ int lbm_cde_set_velocity(lbm_cde_handle h, int32_t run, const double* u);
  * of that launch (0: one block per tile; otherwise each block walks every
  * grid-th tile), and the number of steps one launch takes.  More than one
  * step per launch is built for D2Q9 FP64/FP32 MRT-A or MRT-B3 runs periodic
- * on both axes whose axes span the tile (block x by block y times rows per thread nodes)
- * plus that many steps minus one nodes on each side: the launch keeps the
+ * in x, and periodic or bounded by walls in y, whose periodic axes span the
+ * tile (block x by block y times rows per thread nodes) plus that many steps
+ * minus one nodes on each side: the launch keeps the
  * intermediate steps of a tile and its halo in LDS (Eq. 5: a population
  * moves one node per step), so the state crosses HBM once per launch; the
  * steps left over when a call's count is not a multiple go one per launch.
- * A run that can take several steps per launch starts with 4 (64 x 16
- * tiles in FP32, 64 x 8 in FP64), any other with one.  A batched handle has
+ * A run that can take several steps per launch starts with 4 (64 x 24
+ * tiles in FP32 where the grid allows them, else 64 x 16; 64 x 8 in FP64),
+ * any other with one.  A batched handle has
  * one variant for all its runs; the run index only has to be valid.  Results
  * are bitwise the same for every variant. */
 

@@ -767,7 +767,8 @@ struct FusedEntry {
   FusedEntry { BX, BY, NY, T, {fused_fn<float, BX, BY, NY, T>(), fused_fn<double, BX, BY, NY, T>()} }
 const FusedEntry kFused[] = {FUSED_ENTRY(128, 4, 2, 2), FUSED_ENTRY(128, 4, 2, 3), FUSED_ENTRY(128, 4, 2, 4),
                              FUSED_ENTRY(128, 4, 2, 5), FUSED_ENTRY(64, 4, 2, 3),  FUSED_ENTRY(64, 4, 2, 4),
-                             FUSED_ENTRY(64, 8, 2, 3),  FUSED_ENTRY(64, 8, 2, 4),  FUSED_ENTRY(64, 8, 2, 5)};
+                             FUSED_ENTRY(64, 8, 2, 3),  FUSED_ENTRY(64, 8, 2, 4),  FUSED_ENTRY(64, 8, 2, 5),
+                             FUSED_ENTRY(64, 8, 3, 4),  FUSED_ENTRY(64, 12, 2, 4)};
 
 // A run can take T steps per launch when it is D2Q9 in FP64 or FP32 with an
 // equilibrium linear in phi and phi u (MRT-A or MRT-B3), periodic in x, each
@@ -1160,7 +1161,8 @@ struct BatchFusedEntry {
     BX, BY, NY, T, {batch_fused_fn<float, BX, BY, NY, T>(), batch_fused_fn<double, BX, BY, NY, T>()} \
   }
 const BatchFusedEntry kBatchFused[] = {BATCH_FUSED_ENTRY(64, 8, 2, 4), BATCH_FUSED_ENTRY(64, 4, 2, 4),
-                                       BATCH_FUSED_ENTRY(128, 4, 2, 4), BATCH_FUSED_ENTRY(64, 8, 2, 2)};
+                                       BATCH_FUSED_ENTRY(128, 4, 2, 4), BATCH_FUSED_ENTRY(64, 8, 2, 2),
+                                       BATCH_FUSED_ENTRY(64, 12, 2, 4)};
 
 // The multi-step batched launch of variant v, or null where it is not built
 // or some run does not allow it.
@@ -1257,10 +1259,13 @@ int init_runs(lbm_cde* h, const lbm_cde_run_desc* runs, int32_t nruns, const dou
     for (int a = 0; a < r.dim; ++a) r.walls |= r.d.bc[a] != LBM_CDE_PERIODIC;
     r.var = default_variant(r.d.lattice, r.d.precision);
     {
-      // runs that can take several steps per launch do so by default (64 x 16
-      // tiles, 4 steps in FP32; 64 x 8, 4 steps, XCD-contiguous order in FP64)
-      const Variant multi = r.dbl ? Variant{64, 4, 2, true, 1, 0, 4} : Variant{64, 8, 2, true, 0, 0, 4};
+      // runs that can take several steps per launch do so by default (64 x 24
+      // tiles, 4 steps, XCD-contiguous order in FP32, else 64 x 16; 64 x 8,
+      // 4 steps, XCD-contiguous order in FP64)
+      const Variant multi = r.dbl ? Variant{64, 4, 2, true, 1, 0, 4} : Variant{64, 12, 2, true, 1, 0, 4};
+      const Variant multi16 = Variant{64, 8, 2, true, 0, 0, 4};
       if (r.d.lattice == LBM_CDE_D2Q9 && !r.half && find_step(r, multi)) r.var = multi;
+      else if (r.d.lattice == LBM_CDE_D2Q9 && !r.half && !r.dbl && find_step(r, multi16)) r.var = multi16;
     }
     if (r.split && h->env16_set) r.var = h->env16;
     if (h->env_variant && !r.half) r.var = r.d.lattice == LBM_CDE_D3Q15 ? h->env3 : h->env;
@@ -1387,7 +1392,8 @@ int init_runs(lbm_cde* h, const lbm_cde_run_desc* runs, int32_t nruns, const dou
     // several steps per launch by default where every run allows it (not
     // when LBM_CDE_BATCH fixes the one-step launch); LBM_CDE_BATCH_FUSE =
     // "BXxBYxNYxT" fixes the multi-step one
-    Variant fv = h->runs[0].dbl ? Variant{64, 4, 2, true, 0, 0, 4} : Variant{64, 8, 2, true, 0, 0, 4};
+    Variant fv = h->runs[0].dbl ? Variant{64, 4, 2, true, 0, 0, 4} : Variant{64, 12, 2, true, 0, 0, 4};
+    if (!find_batch_fused(h, fv)) fv = Variant{64, 8, 2, true, 0, 0, 4};
     int fbx, fby, fny, ft;
     if (const char* e = std::getenv("LBM_CDE_BATCH_FUSE"))
       if (std::sscanf(e, "%dx%dx%dx%d", &fbx, &fby, &fny, &ft) == 4) fv = Variant{fbx, fby, fny, true, 0, 0, ft};
