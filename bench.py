@@ -17,8 +17,10 @@ median per-step time is reported with the minimum and maximum.  The tuned
 variant of a run may take several steps per launch (LDS-blocked D2Q9); its
 launch is timed on its own (5 blocks of 40 back-to-back launches, median)
 for the roofline, whose bound is HBM (algorithmic bytes of a launch: the
-state read and written once) or VALU issue (the launch's VALU instructions
-from the committed instruction-count profile), whichever is nearer its peak.
+state read and written once) or VALU (the algorithmic lane operations of the
+launch's lattice updates against the VALU issue rate), whichever is nearer
+its peak; the rate of all VALU instructions the launch issues (from the
+committed instruction-count profile) is given beside it.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--only NAME]
                        [--quick] [--no-cpu] [--no-tune] [--copy-probe]
@@ -38,6 +40,13 @@ HBM_PEAK_GBS = 8000.0          # MI355X HBM3E peak
 # VALU issue rate without packed FP32 math (the library is built without it):
 # 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz lane instructions per second
 VALU_PEAK_TINSTR = 256 * 4 * 16 * 2.4e9 / 1e12
+# VALU lane operations of the method's own arithmetic per D2Q9 lattice update
+# (an FMA counts once): the modified MRT collision with an equilibrium linear
+# in phi and phi u (Eq. 31 and 37) in the add/sub-tree form of the step --
+# phi and the population sums 9, the moments 22, their non-equilibrium parts
+# 8, the relaxation increments S n / |M_k|^2 14, the back-transform f - M^T a
+# 36 -- and the separable velocity's two products per component, 4
+ALG_VALU_PER_LU_D2Q9 = 93
 # algorithmic bytes per lattice update: Q populations read + Q written
 BYTES_PER_LU = {("d2q9", "fp64"): 144, ("d2q9", "fp32"): 72, ("d2q9", "fp16"): 44,
                 ("d3q15", "fp64"): 240, ("d3q15", "fp32"): 120}
@@ -99,23 +108,31 @@ def profiled_valu(name, launch):
 
 def roofline(v, name, real):
     """The roofline of a run's step kernel: the HBM one (algorithmic bytes of
-    a launch over its measured duration) and, where the kernel's VALU
-    instruction count is profiled, the VALU-issue one (lane instructions of a
-    launch over the same duration); the bound is the one nearer its peak."""
+    a launch over its measured duration) and the VALU one (the algorithmic
+    lane operations of a launch, ALG_VALU_PER_LU_D2Q9 per lattice update, over
+    the same duration, against the VALU issue rate); the bound is the one
+    nearer its peak.  Where the kernel's VALU instruction count is profiled,
+    "issued" gives the rate of all lane instructions the launch issues
+    (recomputed halo rings and addressing included)."""
     launch = v["launch"]
+    secs = v["ms_per_launch"] * 1e-3
     hbm = {"bound": "hbm", "achieved": v["achieved_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
            "frac": v["hbm_frac"]}
-    out = dict(hbm)
+    ops = ALG_VALU_PER_LU_D2Q9 * v["nodes"] * v["steps_per_launch"]
+    t = ops / secs / 1e12
+    alu = {"bound": "alu", "achieved": t, "peak": VALU_PEAK_TINSTR, "unit": "T VALU lane operations/s",
+           "frac": t / VALU_PEAK_TINSTR, "algorithmic_lane_ops_per_launch": ops}
     valu = profiled_valu(name, launch)
     if valu is not None:
-        t = valu * 64 / (v["ms_per_launch"] * 1e-3) / 1e12
-        alu = {"bound": "alu", "achieved": t, "peak": VALU_PEAK_TINSTR, "unit": "T VALU lane instructions/s",
-               "frac": t / VALU_PEAK_TINSTR, "valu_wave_instructions_per_launch": valu}
-        if alu["frac"] > hbm["frac"]:
-            out = dict(alu)
-            out["hbm"] = hbm
-        else:
-            out["alu"] = alu
+        ti = valu * 64 / secs / 1e12
+        alu["issued"] = {"achieved": ti, "frac": ti / VALU_PEAK_TINSTR, "unit": "T VALU lane instructions/s",
+                         "valu_wave_instructions_per_launch": valu}
+    if alu["frac"] > hbm["frac"]:
+        out = dict(alu)
+        out["hbm"] = hbm
+    else:
+        out = dict(hbm)
+        out["alu"] = alu
     out.update({"traffic": v.get("traffic"), "kernel": kernel_name(launch, real), "launch": launch,
                 "bytes_per_launch": v["bytes_per_launch"], "ms_per_launch": v["ms_per_launch"],
                 "steps_per_launch": v["steps_per_launch"]})
