@@ -30,8 +30,11 @@ namespace lbm {
 // the end state into a.dst when store_end.
 template <typename R, int BX, int BY, int NY, int T, int UK, bool NP>
 __global__ __launch_bounds__(BX * BY) void k_fused_v_d2q9(const RunArgs a, char* vout, int64_t vstep, int store_end) {
-  const uint32_t ntx = ((uint32_t)a.nx + BX - 1) / BX, tyi = blockIdx.x / ntx;
-  fused_tile<R, BX, BY, NY, T, UK, false, true, NP>(a, blockIdx.x - tyi * ntx, tyi, vout, vstep, store_end != 0);
+  // XCD-contiguous block order: neighbouring tiles, which share halo rows,
+  // run on one XCD and its L2
+  const uint32_t b = tile_of_block32(blockIdx.x, gridDim.x, a.tiles_x, 1);
+  const uint32_t ntx = ((uint32_t)a.nx + BX - 1) / BX, tyi = b / ntx;
+  fused_tile<R, BX, BY, NY, T, UK, false, true, NP>(a, b - tyi * ntx, tyi, vout, vstep, store_end != 0);
 }
 
 // Reverse steps k_hi, k_hi - 1, ..., k_hi - T + 1 of a segment: mu_in =
@@ -53,7 +56,9 @@ __global__ __launch_bounds__(BX * BY) void k_fused_adj_d2q9(const RunArgs a, con
 
   const int tid = threadIdx.y * BX + threadIdx.x;
   const int32_t nx = (int32_t)a.nx, ny = (int32_t)a.ny;
-  const uint32_t ntx = ((uint32_t)nx + BX - 1) / BX, tyi = blockIdx.x / ntx, txi = blockIdx.x - tyi * ntx;
+  // XCD-contiguous block order, as the forward recomputation
+  const uint32_t b = tile_of_block32(blockIdx.x, gridDim.x, a.tiles_x, 1);
+  const uint32_t ntx = ((uint32_t)nx + BX - 1) / BX, tyi = b / ntx, txi = b - tyi * ntx;
   const int32_t x0 = (int32_t)txi * TX - RG, y0 = (int32_t)tyi * TY - RG;
   const uint32_t N = (uint32_t)nx * (uint32_t)ny;
   const size_t pb = (size_t)a.plane * sizeof(R);
