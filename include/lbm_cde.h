@@ -272,7 +272,8 @@ int lbm_cde_set_velocity(lbm_cde_handle h, int32_t run, const double* u);
  * step per launch is built for D2Q9 FP64/FP32 MRT-A or MRT-B3 runs periodic
  * in x, and periodic or bounded by walls in y, whose periodic axes span the
  * tile (block x by block y times rows per thread nodes) plus that many steps
- * minus one nodes on each side: the launch keeps the
+ * minus one nodes on each side (nx and ny below 2^24, a population plane
+ * below 4 GiB): the launch keeps the
  * intermediate steps of a tile and its halo in LDS (Eq. 5: a population
  * moves one node per step), so the state crosses HBM once per launch; the
  * steps left over when a call's count is not a multiple go one per launch.
