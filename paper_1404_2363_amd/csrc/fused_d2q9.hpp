@@ -273,31 +273,42 @@ LBM_FORCEINLINE void fused_tile(const RunArgs& a, uint32_t txi, uint32_t tyi, ch
   }
   __syncthreads();
 
-  // steps 2 .. T-1: in place in LDS over the ring of width T - s
+  // steps 2 .. T-1: in place in LDS over the ring of width T - s.  Slot k
+  // keeps step 1's node (tid + k NTH of the widened tile), whose coordinates
+  // are computed once; a step takes the slots inside its ring.
+  int slx[K0], sly[K0];
+#pragma unroll
+  for (int k = 0; k < K0; ++k) {
+    const int j = tid + k * NTH;
+    sly[k] = j / W0;
+    slx[k] = j - sly[k] * W0;
+    if (K0 * NTH > C0 && j >= C0) sly[k] = H0;  // past the tile: in no ring
+  }
 #pragma unroll
   for (int s = 2; s < T; ++s) {
-    const int r = T - s, W = TX + 2 * r, H = TY + 2 * r, C = W * H, off = RG - r;
+    const int off = RG - (T - s);  // the ring's first row and column
     R f[K0][9];
-    int at[K0];
+    bool in[K0];
 #pragma unroll
     for (int k = 0; k < K0; ++k) {
-      const int j = tid + k * NTH;
-      at[k] = -1;
-      if (j >= C) continue;
-      const int ly = j / W + off, lx = j % W + off;
+      const int lx = slx[k], ly = sly[k];
+      in[k] = (uint32_t)(lx - off) < (uint32_t)(W0 - 2 * off) && (uint32_t)(ly - off) < (uint32_t)(H0 - 2 * off);
+      if (!in[k]) continue;
       const int32_t y = grid_row(ly);
-      if (outside(y)) continue;
-      at[k] = ly * W0 + lx;
+      if (outside(y)) {
+        in[k] = false;
+        continue;
+      }
       gather(f[k], lx, ly, y);
     }
     __syncthreads();
 #pragma unroll
     for (int k = 0; k < K0; ++k) {
-      if (at[k] < 0) continue;
-      const int ly = at[k] / W0, lx = at[k] - ly * W0;
+      if (!in[k]) continue;
+      const int lx = slx[k], ly = sly[k];
       collide(f[k], wrap_once(x0 + lx, nx), grid_row(ly), lx, ly, s - 1);
 #pragma unroll
-      for (int i = 0; i < 9; ++i) lds[i * C0 + at[k]] = f[k][i];
+      for (int i = 0; i < 9; ++i) lds[i * C0 + ly * W0 + lx] = f[k][i];
     }
     __syncthreads();
   }
